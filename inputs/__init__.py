@@ -1,0 +1,93 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module holds no arithmetic of the method: it only draws seeded random
+numbers and evaluates the synthetic fields that define the workloads
+(random vectors, a spherical-harmonic temperature, the viscosity and density
+profiles of the shell configurations).  Everything is FP64 numpy.
+"""
+import numpy as np
+from scipy.special import lpmv
+
+R_IN, R_OUT = 0.55, 1.0
+
+
+def uniform(seed, n, lo=-1.0, hi=1.0):
+    """n values uniform in [lo, hi) from numpy's default generator."""
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+def normal(seed, n):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+class SHField:
+    """S(x) = sum_{l<=lmax, |m|<=l} a_lm Y_lm(x/|x|) cos(pi c_lm (r - r_in)/(r_out - r_in))
+
+    with real spherical harmonics, a_lm ~ N(0,1)/(l+1) and c_lm in {0,1,2},
+    all drawn from ``seed``.  ``temperature`` maps S to [0, 1] with a bound
+    taken on a fixed seeded sample of the shell, so the field does not
+    depend on the mesh it is evaluated on.
+    """
+
+    def __init__(self, seed, lmax=8, r_in=R_IN, r_out=R_OUT):
+        rng = np.random.default_rng(seed)
+        self.terms = []
+        for l in range(lmax + 1):
+            for m in range(-l, l + 1):
+                self.terms.append((l, m, rng.standard_normal() / (l + 1), int(rng.integers(0, 3))))
+        self.r_in, self.r_out = r_in, r_out
+        srng = np.random.default_rng(seed + 1000)
+        d = srng.standard_normal((4096, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        r = srng.uniform(r_in, r_out, 4096)
+        self.smax = 1.05 * np.abs(self.raw(d * r[:, None])).max()
+
+    def raw(self, xyz):
+        xyz = np.asarray(xyz, dtype=np.float64)
+        r = np.linalg.norm(xyz, axis=1)
+        ct = np.clip(xyz[:, 2] / r, -1.0, 1.0)
+        ph = np.arctan2(xyz[:, 1], xyz[:, 0])
+        s = np.zeros(len(xyz))
+        for (l, m, a, c) in self.terms:
+            ang = np.cos(m * ph) if m >= 0 else np.sin(-m * ph)
+            s += a * lpmv(abs(m), l, ct) * ang * np.cos(np.pi * c * (r - self.r_in) / (self.r_out - self.r_in))
+        return s
+
+    def temperature(self, xyz):
+        return np.clip(0.5 + 0.5 * self.raw(xyz) / self.smax, 0.0, 1.0)
+
+
+def viscosity_contrast(T, contrast=1e4):
+    """eta = exp(ln(contrast) (0.5 - T)), in [contrast^-1/2, contrast^1/2] for T in [0,1]."""
+    return np.exp(np.log(contrast) * (0.5 - np.asarray(T)))
+
+
+def viscosity_1e6(xyz, T, seed=3, r_in=R_IN, r_out=R_OUT):
+    """Depth factor 100^((r_out - r)/(r_out - r_in)), temperature factor
+    100^(0.5 - T) and a x100 slab {r >= 0.75, angle(x, c) <= 15 deg} around a
+    seeded direction c: contrast about 1e6 over the shell."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    r = np.linalg.norm(xyz, axis=1)
+    c = np.random.default_rng(seed).standard_normal(3)
+    c /= np.linalg.norm(c)
+    cosang = (xyz @ c) / r
+    slab = (r >= 0.75) & (cosang >= np.cos(np.deg2rad(15.0)))
+    return (100.0 ** ((r_out - r) / (r_out - r_in))) * (100.0 ** (0.5 - np.asarray(T))) * np.where(slab, 100.0, 1.0)
+
+
+def ln_density(xyz):
+    """ln rho with rho = exp(0.5 (1 - r))."""
+    return 0.5 * (1.0 - np.linalg.norm(np.asarray(xyz), axis=1))
+
+
+def smooth_vector_field(seed, xyz, k=3):
+    """A seeded smooth 3-vector field sum of a few sines, for sampled checks."""
+    rng = np.random.default_rng(seed)
+    xyz = np.asarray(xyz, dtype=np.float64)
+    out = np.zeros((len(xyz), 3))
+    for _ in range(k):
+        w = rng.normal(0.0, 3.0, 3)
+        ph = rng.uniform(0, 2 * np.pi)
+        a = rng.uniform(-1, 1, 3)
+        out += np.sin(xyz @ w + ph)[:, None] * a[None, :]
+    return out

@@ -1,0 +1,192 @@
+"""Pins of the oracle's element integrals and assembled operators (CPU only)."""
+from math import factorial
+
+import numpy as np
+import pytest
+import sympy as sy
+
+from oracle.fem import (assemble_A, assemble_B, assemble_M_inv_eta, element_A, geometry,
+                        rhs_buoyancy, strain_and_div)
+from oracle.mesh import RefinedMesh, cube_macros, shell_macros
+from oracle.quadrature import rule_q4, rule_stroud
+
+
+def _mono_integral(a, b, c):
+    return factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + 3)
+
+
+@pytest.mark.parametrize("rule,deg", [(rule_q4(), 2), (rule_stroud(4), 7), (rule_stroud(2), 3)])
+def test_quadrature_exact_for_monomials(rule, deg):
+    xi, w, lam = rule
+    assert np.all(w > 0)
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            for c in range(deg + 1 - a - b):
+                q = np.sum(w * xi[:, 0] ** a * xi[:, 1] ** b * xi[:, 2] ** c)
+                assert abs(q - _mono_integral(a, b, c)) < 1e-15
+
+
+def test_q4_is_not_degree_3():
+    xi, w, _ = rule_q4()
+    assert abs(np.sum(w * xi[:, 0] ** 3) - _mono_integral(3, 0, 0)) > 1e-5
+
+
+class _OneTet:
+    """A single affine tetrahedron in the RefinedMesh interface."""
+
+    def __init__(self, verts):
+        self.ev = np.asarray(verts, dtype=np.float64)[None]
+        self.blend_g = None
+        self.emacro = np.zeros(1, dtype=np.int64)
+
+
+def _exact_element_matrices(verts):
+    """A (constant eta = 1), B and the P1 mass on one affine tet, integrated
+    exactly from the nodal basis written symbolically."""
+    x1, x2, x3 = sy.symbols("x1 x2 x3")
+    xi = sy.Matrix([x1, x2, x3])
+    V = [sy.Matrix([sy.Rational(int(round(c * 8)), 8) for c in v]) for v in verts]
+    J = sy.Matrix.hstack(V[1] - V[0], V[2] - V[0], V[3] - V[0])
+    detJ = abs(J.det())
+    Jit = J.inv().T
+    lam = [1 - x1 - x2 - x3, x1, x2, x3]
+    edges = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+    N = [lam[i] * (2 * lam[i] - 1) for i in range(4)] + [4 * lam[i] * lam[j] for (i, j) in edges]
+    G = [Jit * sy.Matrix([sy.diff(n, v) for v in (x1, x2, x3)]) for n in N]
+
+    def integ(expr):
+        p = sy.Poly(sy.expand(expr), x1, x2, x3)
+        return sum(coef * sy.Rational(factorial(a) * factorial(b) * factorial(c), factorial(a + b + c + 3))
+                   for (a, b, c), coef in p.terms()) * detJ
+
+    A = np.zeros((30, 30))
+    for c in range(3):
+        for a in range(10):
+            for d in range(3):
+                for b in range(10):
+                    e = (1 if c == d else 0) * (G[a].dot(G[b])) + G[a][d] * G[b][c] \
+                        - sy.Rational(2, 3) * G[a][c] * G[b][d]
+                    A[c * 10 + a, d * 10 + b] = float(integ(e))
+    Bm = np.zeros((4, 30))
+    for i in range(4):
+        for d in range(3):
+            for b in range(10):
+                Bm[i, d * 10 + b] = float(integ(-lam[i] * G[b][d]))
+    M = np.array([[float(integ(lam[i] * lam[j])) for j in range(4)] for i in range(4)])
+    return A, Bm, M
+
+
+def test_element_matrices_exact_on_affine_tet():
+    verts = [[0.125, 0.0, 0.25], [1.0, 0.25, 0.0], [0.25, 1.125, 0.125], [0.0, 0.375, 0.875]]
+    A_ex, B_ex, M_ex = _exact_element_matrices(verts)
+    W, G2, G1, X, N2, N1 = geometry(_OneTet(verts), np.array([0]))
+    A = element_A(W, G2, np.ones((1, 4)))[0]
+    assert np.allclose(A, A_ex, rtol=0, atol=1e-13 * np.abs(A_ex).max())
+    _, div = strain_and_div(G2)
+    B = -np.einsum("eq,qi,eqa->eia", W, N1, div)[0]
+    assert np.allclose(B, B_ex, atol=1e-14)
+    M = np.einsum("eq,qi,qj->ij", W, N1, N1)
+    assert np.allclose(M, M_ex, atol=1e-15)
+
+
+def _fields(X):
+    """10 fields with vanishing deviatoric strain: rigid modes, dilation and
+    the special conformal fields 2(b.x)x - |x|^2 b."""
+    out = []
+    for c in range(3):
+        v = np.zeros_like(X)
+        v[:, c] = 1.0
+        out.append(v)
+    for (i, j) in [(0, 1), (0, 2), (1, 2)]:
+        v = np.zeros_like(X)
+        v[:, i], v[:, j] = X[:, j], -X[:, i]
+        out.append(v)
+    out.append(X.copy())
+    for c in range(3):
+        b = np.zeros(3)
+        b[c] = 1.0
+        out.append(2.0 * (X @ b)[:, None] * X - (X * X).sum(1)[:, None] * b)
+    return [v.T.ravel() for v in out]
+
+
+def test_A_kernel_symmetry_and_definiteness_affine():
+    m = RefinedMesh(cube_macros(), 2)
+    eta = np.random.default_rng(0).uniform(0.01, 100.0, m.n1)
+    A = assemble_A(m, eta)
+    assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+    scale = abs(A).max()
+    for v in _fields(m.x2):
+        assert np.abs(A @ v).max() <= 1e-12 * scale * np.abs(v).max()
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert ev.min() > -1e-12 * ev.max()
+    assert np.sum(ev < 1e-10 * ev.max()) == 10               # kernel is exactly 10-dim
+
+
+def test_literal_formula_reading_breaks_kernel_and_definiteness():
+    """The printed formula without eta in the divergence term does not have
+    the deviatoric kernel and is indefinite for eta < 1 (reading check)."""
+    m = RefinedMesh(cube_macros(), 1)
+    eta = np.full(m.n1, 0.25)
+    rows = []
+    for sel in [np.arange(m.ne)]:
+        W, G2, G1, X, N2, N1 = geometry(m, sel)
+        eps, div = strain_and_div(G2)
+        lit = 2 * np.einsum("eq,eqaij,eqbij->eab", 0.25 * W, eps, eps) \
+            - (2.0 / 3.0) * np.einsum("eq,eqa,eqb->eab", W, div, div)
+    dil = m.x2.T.ravel()
+    d = np.concatenate([m.e2 + c * m.n2 for c in range(3)], axis=1)
+    val = np.einsum("ea,eab,eb->", dil[d], lit, dil[d])
+    assert val < -1.0                                         # 6 eta - 6 per volume
+
+
+def test_A_blended_symmetric_translations():
+    m = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 1)
+    eta = np.random.default_rng(1).uniform(0.1, 10.0, m.n1)
+    A = assemble_A(m, eta)
+    assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+    for c in range(3):
+        v = np.zeros((m.n2, 3))
+        v[:, c] = 1.0
+        assert np.abs(A @ v.T.ravel()).max() <= 1e-12 * abs(A).max()
+    x = np.random.default_rng(2).standard_normal(3 * m.n2)
+    assert x @ (A @ x) > 0
+
+
+def test_B_annihilates_constants_and_Bt_of_constant():
+    m = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 1)
+    B = assemble_B(m)
+    for c in range(3):
+        v = np.zeros((m.n2, 3))
+        v[:, c] = 1.0
+        assert np.abs(B @ v.T.ravel()).max() < 1e-15
+    mc = RefinedMesh(cube_macros(), 2)
+    Bc = assemble_B(mc)
+    g = Bc.T @ np.ones(mc.n1)
+    inner = np.tile(mc.flag2 == 0, 3)
+    assert np.abs(g[inner]).max() < 1e-15
+
+
+def test_C_block():
+    """C = 0 for constant ln rho; for linear ln rho = k.x, C u integrates
+    -(k.u) psi, so 1^T C u = -int k.u."""
+    m = RefinedMesh(cube_macros(), 1)
+    C0 = assemble_B(m, np.full(m.n1, 3.0), only_C=True)
+    assert abs(C0).max() < 1e-15
+    k = np.array([0.3, -0.7, 1.1])
+    C = assemble_B(m, m.x1 @ k, only_C=True)
+    u = np.tile([1.0, 2.0, -1.0], (m.n2, 1)).T.ravel()
+    assert np.isclose(np.ones(m.n1) @ (C @ u), -(k @ [1.0, 2.0, -1.0]), rtol=1e-13)
+
+
+def test_mass_and_buoyancy():
+    m = RefinedMesh(cube_macros(), 1)
+    M = assemble_M_inv_eta(m, np.full(m.n1, 2.0))
+    assert np.isclose(M.sum(), 0.5, rtol=1e-14)
+    # buoyancy: f . I_h(x) = int T r_hat . x = int T |x|; T = 1 on the shell
+    errs = []
+    exact = np.pi * (1.0 - 0.55 ** 4)
+    for L in range(3):
+        ms = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), L)
+        f = rhs_buoyancy(ms, np.ones(ms.n2))
+        errs.append(abs(f @ ms.X2.T.ravel() - exact))
+    assert errs[2] < errs[1] < errs[0] and errs[1] / errs[2] > 3.5

@@ -1,0 +1,157 @@
+"""Pins of the oracle's solver components (CPU only)."""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle.fem import assemble_A, assemble_B
+from oracle.mesh import RefinedMesh, cube_macros, shell_macros
+from oracle.solvers import (bfbt, chebyshev, chebyshev_error_polynomial, fgmres, pcg,
+                            prolongation, symmetric_uzawa, vcycle, vector_prolongation)
+from oracle.system import solve_stokes, velocity_basis
+
+
+def test_chebyshev_matches_closed_form_error_polynomial():
+    rng = np.random.default_rng(0)
+    lam = rng.uniform(0.05, 2.0, 50)
+    A = sp.diags(lam)
+    P = sp.identity(50)
+    e0 = rng.standard_normal(50)
+    lo, hi = 0.2, 2.1
+    for deg in (1, 2, 3, 5):
+        # solving A x = 0 from x = e0: the error is p_deg(A) e0
+        x = chebyshev(A, np.ones(50), P, np.zeros(50), e0, lo, hi, deg, 1)
+        assert np.allclose(x, chebyshev_error_polynomial(lam, lo, hi, deg) * e0, atol=1e-13)
+    x = chebyshev(A, np.ones(50), P, np.zeros(50), e0, lo, hi, 2, 3)
+    assert np.allclose(x, chebyshev_error_polynomial(lam, lo, hi, 2) ** 3 * e0, atol=1e-13)
+
+
+def test_prolongation_reproduces_quadratics_and_restriction_is_adjoint():
+    mac = shell_macros(1, 1, 0.55, 1.0)
+    c, f = RefinedMesh(mac, 0), RefinedMesh(mac, 1)
+    P = prolongation(c, f)
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-14)
+    # a quadratic in reference coordinates is in both P2 spaces
+    q = lambda x: 1 + x[:, 0] - 2 * x[:, 1] * x[:, 2] + 0.5 * x[:, 0] ** 2
+    assert np.allclose(P @ q(c.x2), q(f.x2), atol=1e-13)
+    # weights take the values of the P2 basis at the fine nodes
+    vals = np.unique(np.round(P.data * 8))
+    assert set(vals.tolist()) <= {-1.0, 2.0, 3.0, 4.0, 6.0, 8.0}
+    rng = np.random.default_rng(1)
+    r, e = rng.standard_normal(f.n2), rng.standard_normal(c.n2)
+    assert np.isclose((P.T @ r) @ e, r @ (P @ e), rtol=1e-13)
+
+
+def _levels(mac, lmax, eta_fn):
+    levels = []
+    meshes = [RefinedMesh(mac, l) for l in range(lmax + 1)]
+    for l, m in enumerate(meshes):
+        A = assemble_A(m, eta_fn(m.X1))
+        Q, dm, _ = velocity_basis(m, {1}, set())
+        Pm = Q @ Q.T
+        Dinv = 1.0 / A.diagonal()
+        d = dict(A=A, P=Pm, Dinv=Dinv, Q=Q)
+        x = np.random.default_rng(5).standard_normal(A.shape[0])
+        for _ in range(60):
+            x = Pm @ (Dinv * (A @ (Pm @ x)))
+            lmax_est = np.linalg.norm(x)
+            x /= lmax_est
+        d["lo"], d["hi"] = 0.12 * lmax_est, 1.2 * lmax_est
+        if l > 0:
+            d["Pro"] = vector_prolongation(prolongation(meshes[l - 1], m))
+        levels.append(d)
+    return levels, meshes
+
+
+def test_vcycle_contracts_level_independently():
+    eta = lambda X: 1.0 + 9.0 * (X[:, 0] > 0.5)
+    factors = []
+    for lmax in (2, 3):
+        levels, meshes = _levels(cube_macros(), lmax, eta)
+        Q0 = levels[0]["Q"]
+        A0 = (Q0.T @ levels[0]["A"] @ Q0).tocsc()
+        lu = spla.splu(A0)
+        cs = lambda b: Q0 @ lu.solve(Q0.T @ b)
+        L = levels[lmax]
+        Pm = L["P"]
+        x = Pm @ np.random.default_rng(3).standard_normal(L["A"].shape[0])
+        # error propagation of the V-cycle as a stationary iteration on A e = 0
+        for _ in range(6):
+            xn = x - vcycle(levels, lmax, Pm @ (L["A"] @ x), cs, 2, 3)
+            rho = np.linalg.norm(xn) / np.linalg.norm(x)
+            x = xn
+        factors.append(rho)
+    assert max(factors) < 0.35, factors
+    assert abs(factors[0] - factors[1]) < 0.15, factors
+
+
+def test_bfbt_identity_for_square_B():
+    rng = np.random.default_rng(2)
+    n = 6
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    B = rng.standard_normal((n, n))
+    Ch = rng.standard_normal((n, n))
+    Ch = Ch @ Ch.T + n * np.eye(n)                 # any SPD "A-hat"
+    Ainv = lambda v: np.linalg.solve(Ch, v)
+    BAB = B @ np.linalg.solve(Ch, B.T)
+    r = rng.standard_normal(n)
+    s = bfbt(r, B, B.T, A, Ainv, lambda v: np.linalg.solve(BAB, v))
+    exact = np.linalg.solve(B @ np.linalg.solve(A, B.T), r)
+    assert np.allclose(s, exact, rtol=1e-10)
+
+
+def test_fgmres_with_exact_symmetric_uzawa_converges_in_one_step():
+    rng = np.random.default_rng(4)
+    n, m = 12, 5
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    B = rng.standard_normal((m, n))
+    Cc = 0.1 * rng.standard_normal((m, n))
+    Bbar = B + Cc
+    K = np.block([[A, B.T], [Bbar, np.zeros((m, m))]])
+    S = Bbar @ np.linalg.solve(A, B.T)
+    b = rng.standard_normal(n + m)
+
+    def prec(v):
+        u, p = symmetric_uzawa(v[:n], v[n:], A, B.T, Bbar, lambda r: np.linalg.solve(A, r),
+                               lambda r: np.linalg.solve(S, r), 1.0, 1.0)
+        return np.concatenate([u, p])
+
+    x, it, hist = fgmres(lambda v: K @ v, b, prec, 1e-12, restart=10)
+    assert it <= 2
+    assert np.allclose(K @ x, b, atol=1e-10)
+    # with an inexact preconditioner FGMRES still converges to the solution
+    x, it, hist = fgmres(lambda v: K @ v, b, lambda v: v / 10.0, 1e-11, restart=40)
+    assert np.linalg.norm(K @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_pcg_and_direct_solve_agree():
+    m = RefinedMesh(cube_macros(), 2)
+    A = assemble_A(m, np.ones(m.n1))
+    Q, dm, _ = velocity_basis(m, {1}, set())
+    QAQ = (Q.T @ A @ Q).tocsr()
+    b = np.random.default_rng(0).standard_normal(QAQ.shape[0])
+    x, it = pcg(lambda v: QAQ @ v, b, lambda r: r / QAQ.diagonal(), 1e-12)
+    assert np.allclose(x, spla.spsolve(QAQ.tocsc(), b), rtol=1e-9, atol=1e-11)
+
+
+def test_direct_solve_satisfies_constraints_free_slip():
+    mac = shell_macros(1, 1, 0.55, 1.0)
+    m = RefinedMesh(mac, 1)
+    rng = np.random.default_rng(7)
+    A = assemble_A(m, np.exp(rng.uniform(-2, 2, m.n1)))
+    B = assemble_B(m)
+    C = assemble_B(m, 0.5 * (1 - np.linalg.norm(m.X1, axis=1)), only_C=True)
+    f = rng.standard_normal(3 * m.n2)
+    Q, dm, fs = velocity_basis(m, {1}, {2})
+    u, p, mu = solve_stokes(A, B + C, f, np.zeros(m.n1), Q, Bt=B.T)
+    assert abs(p.mean()) < 1e-13
+    n = m.X2[fs] / np.linalg.norm(m.X2[fs], axis=1, keepdims=True)
+    U = u.reshape(3, -1).T
+    assert np.abs(np.einsum("kd,kd->k", U[fs], n)).max() < 1e-13
+    assert np.abs(u[dm]).max() == 0.0
+    Pm = Q @ Q.T
+    ru = Pm @ (f - A @ u - B.T @ p)
+    rp = (B + C) @ u
+    assert np.linalg.norm(ru) < 1e-10 * np.linalg.norm(f)
+    assert np.linalg.norm(rp - rp.mean()) < 1e-10 * np.linalg.norm(f)
