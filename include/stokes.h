@@ -1,0 +1,178 @@
+/*
+ * C ABI of the MI355X matrix-free blended-shell Stokes solver.
+ *
+ * The operation is the discrete compressible Stokes problem of arXiv
+ * 2506.04157, Sec. 5: P2-P1 Taylor-Hood elements on a uniformly refined
+ * macro mesh of the unit cube or of the icosahedral hollow sphere, mapped by
+ * the radial blending map (Sec. 4.1), with blocks
+ *   A_ij = int 2 eta [eps(phi_j):eps(phi_i) - div phi_j div phi_i / 3]
+ *   B_ij = - int div phi_j psi_i,   C_ij = - int (grad ln rho . phi_j) psi_i
+ * (Sec. 5.1; eta in the divergence term, as the deviatoric stress of Sec. 2
+ * implies), solved by FGMRES right-preconditioned with the symmetric Uzawa
+ * block preconditioner (eq. SymmetricUzawaStep1), whose A-block inverse is a
+ * CG preconditioned by a Chebyshev-smoothed geometric multigrid V-cycle
+ * (Sec. 5.2.2) and whose Schur inverse is the V-cycle BFBT approximation
+ * (eq. schurV, Sec. 5.2.3).
+ *
+ * Conventions (all entry points):
+ *  - Return 0 on success or a negative STK_E* code; stk_last_error() gives a
+ *    thread-local message.  No C++ exception crosses the ABI.
+ *  - Vector arguments are caller-owned DEVICE pointers, contiguous, never
+ *    freed or kept by the library.  Velocity vectors hold 3*n_p2 values,
+ *    component-major [x | y | z], in the library's node order; pressure-type
+ *    vectors hold n_p1 values.  "prec" selects the element type of void*
+ *    vectors: 64 = double, 32 = float.
+ *  - Node order is exposed only through stk_coords; callers match nodes by
+ *    coordinates.
+ *  - All GPU work is enqueued on the stream given to stk_create; calls that
+ *    return host values (sizes, coordinates, reports, scalar outputs)
+ *    synchronise that stream.
+ *  - Workspaces are allocated by the library at stk_create / stk_set_fields
+ *    and freed by stk_destroy.  One context per host thread.
+ */
+#ifndef STOKES_H
+#define STOKES_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STK_OK 0
+#define STK_EINVAL (-1)    /* bad argument (null, size, level, eta <= 0 or NaN) */
+#define STK_ENOMEM (-2)    /* device allocation failed */
+#define STK_EHIP (-3)      /* HIP runtime error */
+#define STK_ENOCONV (-4)   /* solver stopped at max iterations; outputs hold the best iterate */
+#define STK_ENOTREADY (-5) /* stk_set_fields not called yet */
+
+#define STK_MESH_CUBE 0    /* unit cube split into 6 macro-tets along Kuhn paths */
+#define STK_MESH_SHELL 1   /* icosahedral shell: 60 n_tan^2 n_rad macro-tets */
+
+#define STK_BC_DIRICHLET 1 /* prescribed velocity (block row modification, Sec. 5.1) */
+#define STK_BC_FREESLIP 2  /* u.n = 0 by projection P_v (Sec. 5.1); shell only */
+
+typedef struct stk_ctx stk_ctx;
+
+typedef struct {
+  int kind;            /* STK_MESH_CUBE or STK_MESH_SHELL */
+  int n_tan, n_rad;    /* shell: subdivisions of an icosahedron edge, radial layers */
+  double r_in, r_out;  /* shell radii (inner, outer) */
+  int level;           /* finest refinement level L: 8^L micro-tets per macro-tet */
+  int min_level;       /* coarsest multigrid level */
+  int bc_inner;        /* BC on r = r_in (cube: on the whole boundary) */
+  int bc_outer;        /* BC on r = r_out (shell only) */
+} stk_mesh_desc;
+
+/* Solver parameters; stk_default_params fills the values of the paper's
+ * Table parametertable plus the readings stated in the comments. */
+typedef struct {
+  double tol_rel;      /* FGMRES stop: |r| <= tol_rel |b| (Euclidean, projected) */
+  double tol_abs;      /* ... or |r| <= tol_abs */
+  int restart;         /* FGMRES restart length (not given in the paper) */
+  int max_outer;       /* FGMRES iteration cap */
+  int precision;       /* 64: all FP64; 32: FP32 preconditioner inside FP64 FGMRES */
+  double sigma, omega; /* Uzawa scalings: 1, 0.3 */
+  double tol_A;        /* A-block CG relative tolerance: 1e-2 */
+  double tol_vbfbt;    /* CG on B Ac^-1 B^T: 1e-1 */
+  double tol_invmass;  /* CG on M_{1/eta}: 1e-10 */
+  double tol_coarse;   /* coarse-grid CG: 1e-2 */
+  int m_A, deg_A;      /* Chebyshev steps / degree in the A-block V-cycle: 3, 2 */
+  int m_V, deg_V;      /* ... in the BFBT V-cycle Ac: 1, 1 */
+  int max_inner;       /* cap for every inner CG */
+  int use_Bbar;        /* 1: B + C in the Uzawa pressure update (eq. SymmetricUzawaStep1 remark) */
+  int power_its;       /* power iterations for lambda_max(D^-1 A): 15 */
+  double cheb_lo, cheb_hi; /* Chebyshev interval = [cheb_lo, cheb_hi] * lambda_max: 0.12, 1.2 */
+} stk_solver_params;
+
+typedef struct {
+  int iterations;          /* FGMRES iterations */
+  double rel_residual;     /* final projected FP64 residual / initial */
+  double abs_residual;
+  double initial_residual;
+  int a_solves, a_cg_its;  /* A-block solves and their total CG iterations */
+  int s_solves, s_cg_its;  /* BFBT inner solves and their total CG iterations */
+  int vcycles;
+  double seconds;          /* wall time of the solve (host clock, stream synchronised) */
+  int history_len;
+  double history[256];     /* relative residual after each FGMRES iteration */
+} stk_report;
+
+/* Sec. 4.1: build the macro mesh, refine to `level`, number the nodes and
+ * upload the tables.  `hip_stream` is a hipStream_t (NULL = default). */
+int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out);
+int stk_destroy(stk_ctx* ctx);
+void stk_default_params(stk_solver_params* p);
+const char* stk_last_error(void);
+
+/* Node counts of `level` (min_level..level): N_u = 3 n_p2, N_p = n_p1. */
+int stk_sizes(const stk_ctx* ctx, int level, int64_t* n_p2, int64_t* n_p1);
+/* Host outputs: which = 2 (P2 nodes) or 1 (P1 nodes); xyz: 3*n physical
+ * (blended) coordinates, nullable; flags: per node 1 = on r_in / cube
+ * boundary, 2 = on r_out, 0 = interior, nullable. */
+int stk_coords(const stk_ctx* ctx, int level, int which, double* xyz, uint8_t* flags);
+
+/* Fields on the finest level (device, n_p1 doubles): nodal viscosity eta > 0
+ * (P1 interpolant, Sec. 5.2.2) and ln rho (nullable: C = 0).  Injects eta to
+ * the coarse levels, computes diag(A) without P_v (Sec. 5.2.2) and the
+ * Chebyshev bounds per level (FP64 power iteration). */
+int stk_set_fields(stk_ctx* ctx, const double* eta_p1, const double* lnrho_p1, const stk_solver_params* params);
+/* Same with eta = exp(m) computed on the device from nodal log-viscosity m. */
+int stk_set_log_viscosity(stk_ctx* ctx, const double* m_p1, const double* lnrho_p1, const stk_solver_params* params);
+
+/* Buoyancy right-hand side f_i = int scale T_h r_hat . phi_i (Sec. 5.1,
+ * eq. for f with g = -r_hat, unit material factors); T: n_p2 device doubles,
+ * f: 3 n_p2 device doubles (overwritten). */
+int stk_rhs_buoyancy(stk_ctx* ctx, const double* T_p2, double scale, double* f_u);
+
+/* Operator applies on `level` (Sec. 5.1).  bc bits: 1 = project the input
+ * velocity (Dirichlet -> 0, free slip -> tangential), 2 = project the output.
+ * Outputs are overwritten. */
+int stk_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int bc);
+int stk_apply_B(stk_ctx* ctx, int level, int prec, const void* u, void* q, int with_C, int bc);
+int stk_apply_Bt(stk_ctx* ctx, int level, int prec, const void* p, void* y, int with_Ct, int bc);
+/* Fused K [u; p] = [A u + B^T p; (B + C) u] on the finest level (transpose=1:
+ * [A u + (B + C)^T p; B u]); bc as above for the velocity parts. */
+int stk_apply_K(stk_ctx* ctx, int prec, const void* u, const void* p, void* yu, void* yp, int transpose, int bc);
+/* P1 mass with weight 1/eta (Sec. 5.2.3, M_{1/eta}). */
+int stk_apply_mass(stk_ctx* ctx, int level, int prec, const void* p, void* q);
+/* diag(A) on `level` without projections (device, 3 n_p2 doubles). */
+int stk_diag_A(stk_ctx* ctx, int level, double* d);
+/* Chebyshev interval [lo, hi] of D^-1 A used on `level` (host outputs); set
+ * overrides it. */
+int stk_cheb_bounds(stk_ctx* ctx, int level, double* lo, double* hi);
+int stk_set_cheb_bounds(stk_ctx* ctx, int level, double lo, double hi);
+/* `steps` applications of the degree-`degree` Jacobi-Chebyshev polynomial to
+ * A x = b on `level` with projections (Sec. 5.2.2); x updated in place. */
+int stk_smooth(stk_ctx* ctx, int level, int prec, const void* b, void* x, int degree, int steps);
+/* Canonical P2 prolongation from `level`-1 to `level` (ef overwritten) and
+ * its transpose (rc overwritten), with projections on the output. */
+int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef);
+int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, void* rc);
+/* One V-cycle on the finest level, x = V(b); which = 0: A-block cycle
+ * (m_A, deg_A), 1: BFBT cycle Ac (m_V, deg_V). */
+int stk_vcycle(stk_ctx* ctx, const stk_solver_params* params, int prec, const void* b, void* x, int which);
+
+/* Stokes solve (Sec. 5.2.4): f_u (3 n_p2), g_p (n_p1, nullable = 0),
+ * u_dirichlet (3 n_p2, nullable = 0; read at Dirichlet nodes only); outputs
+ * u (3 n_p2, includes the Dirichlet values), p (n_p1, arithmetic mean 0).
+ * rep nullable.  Returns STK_ENOCONV with the best iterate if not converged. */
+int stk_solve(stk_ctx* ctx, const stk_solver_params* params, const double* f_u, const double* g_p,
+              const double* u_dirichlet, double* u, double* p, stk_report* rep);
+/* Adjoint solve K^T [lu; lp] = [ju; jp] with homogeneous constraints. */
+int stk_solve_adjoint(stk_ctx* ctx, const stk_solver_params* params, const double* ju, const double* jp,
+                      double* lu, double* lp, stk_report* rep);
+/* Gradient of J for eta_h = sum exp(m_k) psi_k and f = scale * buoyancy(T):
+ * g_m[k] = - lu^T (dA/dm_k) u (n_p1), g_T[i] = lu^T df/dT_i (n_p2); both
+ * overwritten, device doubles. */
+int stk_gradient(stk_ctx* ctx, const double* u, const double* lu, double scale, double* g_m, double* g_T);
+
+/* Times `reps` back-to-back launches of the A-apply kernel of `level` (input
+ * projected, output accumulated into y, which ends up holding garbage)
+ * between two HIP events on the context stream; *ms_per_apply = average
+ * kernel duration in milliseconds. */
+int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_per_apply);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKES_H */

@@ -1,0 +1,1264 @@
+// HIP kernels for gfx950: matrix-free blended P2-P1 Stokes operators,
+// grid transfers, adjoint gradient and vector operations.
+//
+// Operators (Sec. 5.1 of arXiv 2506.04157, with the divergence term of A
+// weighted by eta as the deviatoric stress tau = 2 eta (sym grad u - div u I/3)
+// of Sec. 2 implies):
+//   A:  y_{a,c} = sum_K sum_q W_q 2 eta_h [eps(u):eps(phi_{a,c}) - div u div phi_{a,c}/3]
+//   B:  q_i     = - sum_K sum_q W_q psi_i div u
+//   C:  q_i     = - sum_K sum_q W_q psi_i (grad ln rho_h . u)
+//   B^T, C^T the transposes.
+// Integrals are pulled back through the blending map B(x) = s(x) x/|x|
+// (s affine per macro-tet, Sec. 4.1) whose Jacobian is recomputed in closed
+// form at every quadrature point:  J_B = d g^T + alpha (I - d d^T) with
+// d = x/|x|, alpha = s/|x|, g = grad s;  det J_B = alpha^2 (g.d);
+// J_B^{-1} = I/alpha + d h^T with h = (d - g/alpha)/(g.d).
+// Quadrature: symmetric 4-point rule of degree 2 (the paper does not state
+// its rule; this reading keeps the Taylor-Hood rates and positive weights).
+//
+// Work decomposition: one workgroup per (macro-tet, brick of 4^3 cubes of
+// the macro's cube lattice).  The brick's P2 box (9^3 nodes) and P1 box (5^3)
+// are staged in LDS through the macro's local-to-global table; wave w of the
+// 6 waves handles micro-tets of type w, one per lane (64 cubes per brick), and
+// accumulates with LDS atomics; the flush stores nodes that only this
+// workgroup touches and atomically adds the rest (brick faces and macro
+// interfaces) into a zero-filled output.
+#include "device.hpp"
+
+namespace stk {
+
+// ---- constants -------------------------------------------------------------
+#define QA 0.58541019662496845446    // (5 + 3 sqrt 5)/20
+#define QB 0.13819660112501051518    // (5 - sqrt 5)/20
+#define QW (1.0 / 24.0)
+#define KAP (4.0 * (QA - QB))          // d/dlambda of the edge/vertex shape functions
+#define C1 (4.0 * QB - 1.0)
+#define NV_OWN (QA * (2.0 * QA - 1.0))  // vertex function at its own point
+#define NV_OTH (QB * (2.0 * QB - 1.0))  // vertex function at another point
+#define NE_OWN (4.0 * QA * QB)          // edge function at a point of its vertices
+#define NE_OTH (4.0 * QB * QB)
+
+__constant__ int c_toff[6][4][3] = {
+    {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {1, 0, 0}, {1, 1, 0}},
+    {{0, 1, 0}, {1, 0, 1}, {1, 1, 0}, {0, 1, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {0, 1, 1}, {0, 0, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {0, 0, 1}, {1, 0, 0}},
+    {{1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}},
+};
+// inverse of the integer vertex-difference matrix of each type (unimodular)
+__constant__ int c_tlinv[6][3][3] = {
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{0, 0, 1}, {0, -1, -1}, {1, 1, 0}},
+    {{0, -1, 0}, {1, 1, 0}, {0, 1, 1}},
+    {{1, 0, 0}, {0, 1, 1}, {-1, -1, 0}},
+    {{1, 1, 1}, {-1, -1, 0}, {0, -1, -1}},
+    {{0, -1, 0}, {-1, 0, 0}, {1, 1, 1}},
+};
+
+// local edge e = (EV0[e], EV1[e]); node index 4 + e
+#define EV0(e) ((e) < 3 ? 0 : ((e) < 5 ? 1 : 2))
+#define EV1(e) ((e) == 0 ? 1 : ((e) == 1 ? 2 : ((e) == 2 ? 3 : ((e) == 3 ? 2 : 3))))
+__host__ __device__ constexpr int eidx(int i, int j) {
+  // node index (4..9) of the edge joining vertices i != j
+  return (i > j) ? eidx(j, i)
+                 : (i == 0 ? 3 + j : (i == 1 ? 5 + j : 9));
+}
+
+template <typename R> __device__ __forceinline__ const R* geo_of(const LevelDev& L);
+template <> __device__ __forceinline__ const double* geo_of<double>(const LevelDev& L) { return L.geo; }
+template <> __device__ __forceinline__ const float* geo_of<float>(const LevelDev& L) { return L.geof; }
+template <typename R> __device__ __forceinline__ const R* tinv_of(const LevelDev& L);
+template <> __device__ __forceinline__ const double* tinv_of<double>(const LevelDev& L) { return L.tinv; }
+template <> __device__ __forceinline__ const float* tinv_of<float>(const LevelDev& L) { return L.tinvf; }
+
+__device__ __forceinline__ long long tetc(long long s) { return (s + 1) * (s + 2) * (s + 3) / 6; }
+__device__ __forceinline__ int lloc(int I, int J, int K, int m) {
+  int s = m - K;
+  return (int)(tetc(m) - tetc(s) + (long long)J * (s + 1) - (long long)J * (J - 1) / 2 + I);
+}
+__device__ __forceinline__ int wmask(int I, int J, int K, int m) {
+  return ((m - I - J - K) > 0) | ((I > 0) << 1) | ((J > 0) << 2) | ((K > 0) << 3);
+}
+
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
+
+template <typename R> __device__ __forceinline__ void ldsadd(R* p, R v) { unsafeAtomicAdd(p, v); }
+template <typename R> __device__ __forceinline__ void gadd(R* p, R v) { unsafeAtomicAdd(p, v); }
+
+// reference position of P2 lattice point (I,J,K) (side m) of a macro
+template <typename R>
+__device__ __forceinline__ void lattice_x(const R* G, int I, int J, int K, int m, R x[3]) {
+  const R im = R(1) / R(m);
+  const R a = R(I) * im, b = R(J) * im, c = R(K) * im;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) x[r] = G[r] + G[3 + 3 * r] * a + G[4 + 3 * r] * b + G[5 + 3 * r] * c;
+}
+
+// project a velocity at a node: Dirichlet -> 0, free slip -> remove normal part
+template <typename R>
+__device__ __forceinline__ void bc_project(int act, const R* G, int I, int J, int K, int m, R& v0, R& v1, R& v2) {
+  if (act == ACT_DIR) {
+    v0 = v1 = v2 = R(0);
+  } else if (act == ACT_FS) {
+    R x[3];
+    lattice_x(G, I, J, K, m, x);
+    R ri = rsq(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    R n0 = x[0] * ri, n1 = x[1] * ri, n2 = x[2] * ri;
+    R dn = v0 * n0 + v1 * n1 + v2 * n2;
+    v0 -= dn * n0;
+    v1 -= dn * n1;
+    v2 -= dn * n2;
+  }
+}
+
+// Geometry at one quadrature point.
+template <typename R, bool BLEND>
+struct QGeo {
+  R d[3], h[3], ia, W;
+  __device__ __forceinline__ void eval(const R* G, const R xq[3], R wdetF) {
+    if (BLEND) {
+      R r2 = xq[0] * xq[0] + xq[1] * xq[1] + xq[2] * xq[2];
+      R ri = rsq(r2);
+      d[0] = xq[0] * ri;
+      d[1] = xq[1] * ri;
+      d[2] = xq[2] * ri;
+      R s = G[12] * xq[0] + G[13] * xq[1] + G[14] * xq[2] + G[15];
+      R alpha = s * ri;
+      ia = R(1) / alpha;
+      R gd = G[12] * d[0] + G[13] * d[1] + G[14] * d[2];
+      R igd = R(1) / gd;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) h[k] = (d[k] - G[12 + k] * ia) * igd;
+      W = wdetF * alpha * alpha * gd;
+    } else {
+      W = wdetF;
+    }
+  }
+  // v^T J_B^{-1}  (row vector times inverse Jacobian) = ia v + (v.d) h
+  __device__ __forceinline__ void rowJinv(R v[3]) const {
+    if (BLEND) {
+      R vd = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[k] = ia * v[k] + vd * h[k];
+    }
+  }
+  // J_B^{-1} v = ia v + d (h.v)   (equivalently (J_B^{-T})^T applied on the left)
+  __device__ __forceinline__ void Jinv(R v[3]) const {
+    if (BLEND) {
+      R hv = h[0] * v[0] + h[1] * v[1] + h[2] * v[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[k] = ia * v[k] + hv * d[k];
+    }
+  }
+  // J_B^{-T} v = ia v + h (d.v)
+  __device__ __forceinline__ void JinvT(R v[3]) const { rowJinv(v); }
+};
+
+// Element context: lattice positions and LDS indices of the 10 P2 / 4 P1 nodes.
+struct ElemIdx {
+  int n2i[10], n1i[4];
+};
+
+__device__ __forceinline__ void elem_indices(int type, int cx, int cy, int cz, ElemIdx& e) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    int a = cx + c_toff[type][v][0], b = cy + c_toff[type][v][1], c = cz + c_toff[type][v][2];
+    e.n1i[v] = a + B1 * (b + B1 * c);
+    e.n2i[v] = 2 * a + B2 * (2 * b + B2 * 2 * c);
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    int a = 2 * cx + c_toff[type][i][0] + c_toff[type][j][0];
+    int b = 2 * cy + c_toff[type][i][1] + c_toff[type][j][1];
+    int c = 2 * cz + c_toff[type][i][2] + c_toff[type][j][2];
+    e.n2i[4 + ed] = a + B2 * (b + B2 * c);
+  }
+}
+
+// reference positions of the element's 4 vertices
+template <typename R>
+__device__ __forceinline__ void elem_vertices(const R* G, int type, int px, int py, int pz, int n, R xv[4][3]) {
+  const R in = R(1) / R(n);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    R a = R(px + c_toff[type][v][0]) * in, b = R(py + c_toff[type][v][1]) * in,
+      c = R(pz + c_toff[type][v][2]) * in;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) xv[v][r] = G[r] + G[3 + 3 * r] * a + G[4 + 3 * r] * b + G[5 + 3 * r] * c;
+  }
+}
+
+__device__ __forceinline__ int type_limit(int type, int n) {
+  return type == 0 ? n - 1 : (type == 5 ? n - 3 : n - 2);
+}
+
+// ---- fused Stokes element kernel -------------------------------------------
+template <typename R, bool BLEND, int FL>
+__global__ __launch_bounds__(384) void k_stokes(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
+                                                const R* __restrict__ eta, const R* __restrict__ lnrho,
+                                                R* __restrict__ yu, R* __restrict__ yp, int bcmode) {
+  constexpr bool DA = FL & F_A, DBT = FL & F_BT, DB = FL & F_B, DC = FL & F_C, DCT = FL & F_CT;
+  constexpr bool NU = DA || DB || DC;
+  constexpr bool NP = DBT || DCT;
+  constexpr bool OU = DA || DBT || DCT;
+  constexpr bool OP = DB || DC;
+  constexpr bool NR = DC || DCT;
+  constexpr bool NEED_G = DA || DB;            // physical gradient of u
+  __shared__ R sx[NU ? 3 * NB2 : 1];
+  __shared__ R sy[OU ? 3 * NB2 : 1];
+  __shared__ R seta[DA ? NB1 : 1];
+  __shared__ R sp[NP ? NB1 : 1];
+  __shared__ R syp[OP ? NB1 : 1];
+  __shared__ R srho[NR ? NB1 : 1];
+
+  const int tile = blockIdx.x % L.ntiles;
+  const int mac = blockIdx.x / L.ntiles;
+  const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
+  const int n = L.n, m2 = 2 * L.n;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const R* G = geo_of<R>(L) + (size_t)mac * 16;
+  const uint8_t* bact = L.bact + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+    if (NU) {
+      R v0 = 0, v1 = 0, v2 = 0;
+      if (I + J + K <= m2) {
+        const size_t g = l2[lloc(I, J, K, m2)];
+        v0 = u[g];
+        v1 = u[g + N2];
+        v2 = u[g + 2 * N2];
+        if (bcmode & BCM_IN) bc_project<R>(bact[wmask(I, J, K, m2)], G, I, J, K, m2, v0, v1, v2);
+      }
+      sx[i] = v0;
+      sx[NB2 + i] = v1;
+      sx[2 * NB2 + i] = v2;
+    }
+    if (OU) {
+      sy[i] = 0;
+      sy[NB2 + i] = 0;
+      sy[2 * NB2 + i] = 0;
+    }
+  }
+  if (DA || NP || OP || NR) {
+    for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+      const int lx = i % B1, ly = (i / B1) % B1, lz = i / (B1 * B1);
+      const int I = ox + lx, J = oy + ly, K = oz + lz;
+      const bool in = I + J + K <= n;
+      const size_t g = in ? l1[lloc(I, J, K, n)] : 0;
+      if (DA) seta[i] = in ? eta[g] : R(0);
+      if (NP) sp[i] = in ? p[g] : R(0);
+      if (NR) srho[i] = in ? lnrho[g] : R(0);
+      if (OP) syp[i] = 0;
+    }
+  }
+  __syncthreads();
+
+  const int type = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+  const int px = ox + cx, py = oy + cy, pz = oz + cz;
+  if (px + py + pz <= type_limit(type, n)) {
+    ElemIdx e;
+    elem_indices(type, cx, cy, cz, e);
+    const R* TI = tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10;
+    R gl[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gl[r][k] = TI[3 * r + k];
+    const R wdetF = R(QW) * TI[9];
+    R xv[4][3];
+    if (BLEND) elem_vertices<R>(G, type, px, py, pz, n, xv);
+    R xs[3] = {0, 0, 0};
+    if (BLEND) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xs[k] += xv[v][k];
+    }
+    R U[3][10];
+    if (NU) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 10; ++a) U[c][a] = sx[c * NB2 + e.n2i[a]];
+    }
+    R et[4], pp[4], rho[4];
+    R set = 0, spp = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (DA) { et[v] = seta[e.n1i[v]]; set += et[v]; }
+      if (NP) { pp[v] = sp[e.n1i[v]]; spp += pp[v]; }
+      if (NR) rho[v] = srho[e.n1i[v]];
+    }
+    // gradient of ln rho_h in reference coordinates (constant per element)
+    R grr[3] = {0, 0, 0};
+    if (NR) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        grr[k] = (rho[1] - rho[0]) * gl[0][k] + (rho[2] - rho[0]) * gl[1][k] + (rho[3] - rho[0]) * gl[2][k];
+    }
+    // per-component sums of edge values at each vertex
+    R Ev[3][4], base[3][4];
+    if (NU) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Ev[c][0] = U[c][4] + U[c][5] + U[c][6];
+        Ev[c][1] = U[c][4] + U[c][7] + U[c][8];
+        Ev[c][2] = U[c][5] + U[c][7] + U[c][9];
+        Ev[c][3] = U[c][6] + U[c][8] + U[c][9];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) base[c][i] = R(C1) * U[c][i] + R(4.0 * QB) * Ev[c][i];
+      }
+    }
+    R Sacc[3][4], Dacc[3][4], Eacc[3][6];
+    R SV[3] = {0, 0, 0}, VQ[3][4];
+    R SP = 0, DP[4];
+    if (OU) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Sacc[c][i] = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Eacc[c][k] = 0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      R xq[3];
+      if (BLEND) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xq[k] = R(QB) * xs[k] + R(QA - QB) * xv[q][k];
+      }
+      QGeo<R, BLEND> geo;
+      geo.eval(G, xq, wdetF);
+      const R W = geo.W;
+      R Gm[3][3];
+      if (NEED_G) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          R g4[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g4[i] = base[c][i] + R(KAP) * (i == q ? U[c][i] : U[c][eidx(i, q)]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            Gm[c][k] = (g4[1] - g4[0]) * gl[0][k] + (g4[2] - g4[0]) * gl[1][k] + (g4[3] - g4[0]) * gl[2][k];
+          geo.rowJinv(Gm[c]);
+        }
+      }
+      R pq = 0;
+      if (NP) pq = R(QB) * spp + R(QA - QB) * pp[q];
+      if (DA || DBT) {
+        R S[3][3];
+        if (DA) {
+          const R e2 = R(2) * (R(QB) * set + R(QA - QB) * et[q]) * W;
+          const R tr3 = (Gm[0][0] + Gm[1][1] + Gm[2][2]) * R(1.0 / 3.0);
+          S[0][0] = e2 * (Gm[0][0] - tr3);
+          S[1][1] = e2 * (Gm[1][1] - tr3);
+          S[2][2] = e2 * (Gm[2][2] - tr3);
+          S[0][1] = S[1][0] = R(0.5) * e2 * (Gm[0][1] + Gm[1][0]);
+          S[0][2] = S[2][0] = R(0.5) * e2 * (Gm[0][2] + Gm[2][0]);
+          S[1][2] = S[2][1] = R(0.5) * e2 * (Gm[1][2] + Gm[2][1]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) S[c][k] = 0;
+        }
+        if (DBT) {
+          const R wp = W * pq;
+          S[0][0] -= wp;
+          S[1][1] -= wp;
+          S[2][2] -= wp;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          R T[3] = {S[c][0], S[c][1], S[c][2]};
+          geo.Jinv(T);
+          R t1 = T[0] * gl[0][0] + T[1] * gl[0][1] + T[2] * gl[0][2];
+          R t2 = T[0] * gl[1][0] + T[1] * gl[1][1] + T[2] * gl[1][2];
+          R t3 = T[0] * gl[2][0] + T[1] * gl[2][1] + T[2] * gl[2][2];
+          R t[4] = {-(t1 + t2 + t3), t1, t2, t3};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            Sacc[c][i] += t[i];
+            if (i == q) Dacc[c][i] = t[i];
+            else Eacc[c][eidx(i, q) - 4] += t[i];
+          }
+        }
+      }
+      if (NR) {
+        // grad ln rho_h (physical) = J_B^{-T} grr
+        R gr[3] = {grr[0], grr[1], grr[2]};
+        geo.JinvT(gr);
+        if (DC) {
+          R val = DB ? (Gm[0][0] + Gm[1][1] + Gm[2][2]) : R(0);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            R sv = U[c][0] + U[c][1] + U[c][2] + U[c][3];
+            R se = U[c][4] + U[c][5] + U[c][6] + U[c][7] + U[c][8] + U[c][9];
+            R uq = R(NV_OTH) * sv + R(NV_OWN - NV_OTH) * U[c][q] + R(NE_OTH) * se + R(NE_OWN - NE_OTH) * Ev[c][q];
+            val += gr[c] * uq;
+          }
+          SP += W * val;
+          DP[q] = W * val;
+        }
+        if (DCT) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            R v = -W * pq * gr[c];
+            SV[c] += v;
+            VQ[c][q] = v;
+          }
+        }
+      }
+      if (DB && !DC) {
+        R val = Gm[0][0] + Gm[1][1] + Gm[2][2];
+        SP += W * val;
+        DP[q] = W * val;
+      }
+    }
+    if (OU) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R* yc = sy + c * NB2;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          R y = (DA || DBT) ? (R(C1) * Sacc[c][i] + R(KAP) * Dacc[c][i]) : R(0);
+          if (DCT) y += R(NV_OTH) * SV[c] + R(NV_OWN - NV_OTH) * VQ[c][i];
+          ldsadd(yc + e.n2i[i], y);
+        }
+#pragma unroll
+        for (int ed = 0; ed < 6; ++ed) {
+          const int i = EV0(ed), j = EV1(ed);
+          R y = (DA || DBT) ? (R(4.0 * QB) * (Sacc[c][i] + Sacc[c][j]) + R(KAP) * Eacc[c][ed]) : R(0);
+          if (DCT) y += R(NE_OTH) * SV[c] + R(NE_OWN - NE_OTH) * (VQ[c][i] + VQ[c][j]);
+          ldsadd(yc + e.n2i[4 + ed], y);
+        }
+      }
+    }
+    if (OP) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ldsadd(syp + e.n1i[i], -(R(QB) * SP + R(QA - QB) * DP[i]));
+    }
+  }
+  __syncthreads();
+
+  if (OU) {
+    for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+      const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+      const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+      if (I + J + K > m2) continue;
+      const int mask = wmask(I, J, K, m2);
+      R v0 = sy[i], v1 = sy[NB2 + i], v2 = sy[2 * NB2 + i];
+      if (bcmode & BCM_OUT) {
+        const int act = bact[mask];
+        if (act == ACT_DIR) continue;
+        bc_project<R>(act, G, I, J, K, m2, v0, v1, v2);
+      }
+      const size_t g = l2[lloc(I, J, K, m2)];
+      const bool excl = mask == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
+      if (excl) {
+        yu[g] = v0;
+        yu[g + N2] = v1;
+        yu[g + 2 * N2] = v2;
+      } else {
+        gadd(yu + g, v0);
+        gadd(yu + g + N2, v1);
+        gadd(yu + g + 2 * N2, v2);
+      }
+    }
+  }
+  if (OP) {
+    for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+      const int lx = i % B1, ly = (i / B1) % B1, lz = i / (B1 * B1);
+      const int I = ox + lx, J = oy + ly, K = oz + lz;
+      if (I + J + K > n) continue;
+      const size_t g = l1[lloc(I, J, K, n)];
+      const bool excl = wmask(I, J, K, n) == 15 && lx > 0 && lx < B1 - 1 && ly > 0 && ly < B1 - 1 && lz > 0 && lz < B1 - 1;
+      if (excl) yp[g] = syp[i];
+      else gadd(yp + g, syp[i]);
+    }
+  }
+}
+
+// ---- diag(A) (no free-slip projection, Sec. 5.2.2) ---------------------------
+template <typename R, bool BLEND>
+__global__ __launch_bounds__(384) void k_diag(LevelDev L, const R* __restrict__ eta, R* __restrict__ dout) {
+  __shared__ R sy[3 * NB2];
+  __shared__ R seta[NB1];
+  const int tile = blockIdx.x % L.ntiles;
+  const int mac = blockIdx.x / L.ntiles;
+  const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
+  const int n = L.n, m2 = 2 * L.n;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const R* G = geo_of<R>(L) + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+  for (int i = threadIdx.x; i < 3 * NB2; i += blockDim.x) sy[i] = 0;
+  for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+    const int I = ox + i % B1, J = oy + (i / B1) % B1, K = oz + i / (B1 * B1);
+    seta[i] = (I + J + K <= n) ? eta[l1[lloc(I, J, K, n)]] : R(0);
+  }
+  __syncthreads();
+  const int type = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+  const int px = ox + cx, py = oy + cy, pz = oz + cz;
+  if (px + py + pz <= type_limit(type, n)) {
+    ElemIdx e;
+    elem_indices(type, cx, cy, cz, e);
+    const R* TI = tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10;
+    R gl[4][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gl[1][k] = TI[k];
+      gl[2][k] = TI[3 + k];
+      gl[3][k] = TI[6 + k];
+      gl[0][k] = -(gl[1][k] + gl[2][k] + gl[3][k]);
+    }
+    const R wdetF = R(QW) * TI[9];
+    R xv[4][3], xs[3] = {0, 0, 0};
+    if (BLEND) {
+      elem_vertices<R>(G, type, px, py, pz, n, xv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xs[k] += xv[v][k];
+    }
+    R et[4], set = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { et[v] = seta[e.n1i[v]]; set += et[v]; }
+    R D[3][10];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < 10; ++a) D[c][a] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      R xq[3];
+      if (BLEND) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xq[k] = R(QB) * xs[k] + R(QA - QB) * xv[q][k];
+      }
+      QGeo<R, BLEND> geo;
+      geo.eval(G, xq, wdetF);
+      const R we = geo.W * (R(QB) * set + R(QA - QB) * et[q]);
+#pragma unroll
+      for (int a = 0; a < 10; ++a) {
+        R gN[3];
+        if (a < 4) {
+          const R f = (a == q) ? R(4.0 * QA - 1.0) : R(C1);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) gN[k] = f * gl[a][k];
+        } else {
+          const int i = EV0(a - 4), j = EV1(a - 4);
+          const R li = (i == q) ? R(4.0 * QA) : R(4.0 * QB), lj = (j == q) ? R(4.0 * QA) : R(4.0 * QB);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) gN[k] = lj * gl[i][k] + li * gl[j][k];
+        }
+        geo.JinvT(gN);
+        const R g2 = gN[0] * gN[0] + gN[1] * gN[1] + gN[2] * gN[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) D[c][a] += we * (g2 + gN[c] * gN[c] * R(1.0 / 3.0));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < 10; ++a) ldsadd(sy + c * NB2 + e.n2i[a], D[c][a]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+    if (I + J + K > m2) continue;
+    const size_t g = l2[lloc(I, J, K, m2)];
+    const bool excl = wmask(I, J, K, m2) == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (excl) dout[g + c * N2] = sy[c * NB2 + i];
+      else gadd(dout + g + c * N2, sy[c * NB2 + i]);
+    }
+  }
+}
+
+// ---- P1 mass with weight 1/eta (Schur approximation M_{1/eta}) --------------
+// DIAG: the diagonal of the same matrix (p unused)
+template <typename R, bool BLEND, bool DIAG>
+__global__ __launch_bounds__(384) void k_mass(LevelDev L, const R* __restrict__ eta, const R* __restrict__ p,
+                                              R* __restrict__ y) {
+  __shared__ R seta[NB1], sp[NB1], sy[NB1];
+  const int tile = blockIdx.x % L.ntiles;
+  const int mac = blockIdx.x / L.ntiles;
+  const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
+  const int n = L.n;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const R* G = geo_of<R>(L) + (size_t)mac * 16;
+  for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+    const int I = ox + i % B1, J = oy + (i / B1) % B1, K = oz + i / (B1 * B1);
+    const bool in = I + J + K <= n;
+    const size_t g = in ? l1[lloc(I, J, K, n)] : 0;
+    seta[i] = in ? eta[g] : R(1);
+    sp[i] = (in && !DIAG) ? p[g] : R(0);
+    sy[i] = 0;
+  }
+  __syncthreads();
+  const int type = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+  const int px = ox + cx, py = oy + cy, pz = oz + cz;
+  if (px + py + pz <= type_limit(type, n)) {
+    ElemIdx e;
+    elem_indices(type, cx, cy, cz, e);
+    const R* TI = tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10;
+    const R wdetF = R(QW) * TI[9];
+    R xv[4][3], xs[3] = {0, 0, 0};
+    if (BLEND) {
+      elem_vertices<R>(G, type, px, py, pz, n, xv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xs[k] += xv[v][k];
+    }
+    R et[4], pp[4], set = 0, spp = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      et[v] = seta[e.n1i[v]];
+      pp[v] = sp[e.n1i[v]];
+      set += et[v];
+      spp += pp[v];
+    }
+    R SM = 0, DM[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      R xq[3];
+      if (BLEND) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xq[k] = R(QB) * xs[k] + R(QA - QB) * xv[q][k];
+      }
+      QGeo<R, BLEND> geo;
+      geo.eval(G, xq, wdetF);
+      const R etaq = R(QB) * set + R(QA - QB) * et[q];
+      const R v = DIAG ? geo.W / etaq : geo.W * (R(QB) * spp + R(QA - QB) * pp[q]) / etaq;
+      SM += v;
+      DM[q] = v;
+    }
+    if (DIAG) {
+      // sum_q w_q lambda_i(q)^2 with lambda_i(q) = QB + (QA - QB) delta_iq
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ldsadd(sy + e.n1i[i], R(QB * QB) * SM + R(QA * QA - QB * QB) * DM[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ldsadd(sy + e.n1i[i], R(QB) * SM + R(QA - QB) * DM[i]);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+    const int lx = i % B1, ly = (i / B1) % B1, lz = i / (B1 * B1);
+    const int I = ox + lx, J = oy + ly, K = oz + lz;
+    if (I + J + K > n) continue;
+    const size_t g = l1[lloc(I, J, K, n)];
+    const bool excl = wmask(I, J, K, n) == 15 && lx > 0 && lx < B1 - 1 && ly > 0 && ly < B1 - 1 && lz > 0 && lz < B1 - 1;
+    if (excl) y[g] = sy[i];
+    else gadd(y + g, sy[i]);
+  }
+}
+
+// ---- buoyancy right-hand side f = int scale T_h r_hat . phi (FP64) ------------
+// ---- and adjoint gradient g_m, g_T (FP64) -------------------------------------
+// MODE 0: rhs (input T (P2 scalar) -> f (P2 vector))
+// MODE 1: gradient (inputs u, lam (P2 vectors), eta -> gm (P1), gT (P2 scalar))
+template <bool BLEND, int MODE>
+__global__ __launch_bounds__(384) void k_rhs_grad(LevelDev L, const double* __restrict__ T,
+                                                  const double* __restrict__ u, const double* __restrict__ lam,
+                                                  const double* __restrict__ eta, double* __restrict__ out2,
+                                                  double* __restrict__ out1, double scale) {
+  constexpr int NIN = MODE == 0 ? 1 : 6;
+  constexpr int NOUT = MODE == 0 ? 3 : 1;
+  __shared__ double sx[NIN * NB2];
+  __shared__ double sy[NOUT * NB2];
+  __shared__ double seta[MODE == 1 ? NB1 : 1], sg[MODE == 1 ? NB1 : 1];
+  const int tile = blockIdx.x % L.ntiles;
+  const int mac = blockIdx.x / L.ntiles;
+  const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
+  const int n = L.n, m2 = 2 * L.n;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const double* G = L.geo + (size_t)mac * 16;
+  const uint8_t* bact = L.bact + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+    const bool in = I + J + K <= m2;
+    const size_t g = in ? l2[lloc(I, J, K, m2)] : 0;
+    if (MODE == 0) {
+      sx[i] = in ? T[g] : 0.0;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        sx[c * NB2 + i] = in ? u[g + c * N2] : 0.0;
+        sx[(3 + c) * NB2 + i] = in ? lam[g + c * N2] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) sy[c * NB2 + i] = 0;
+  }
+  if (MODE == 1) {
+    for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+      const int I = ox + i % B1, J = oy + (i / B1) % B1, K = oz + i / (B1 * B1);
+      seta[i] = (I + J + K <= n) ? eta[l1[lloc(I, J, K, n)]] : 0.0;
+      sg[i] = 0;
+    }
+  }
+  __syncthreads();
+  const int type = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+  const int px = ox + cx, py = oy + cy, pz = oz + cz;
+  if (px + py + pz <= type_limit(type, n)) {
+    ElemIdx e;
+    elem_indices(type, cx, cy, cz, e);
+    const double* TI = L.tinv + ((size_t)mac * 6 + type) * 10;
+    double gl[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gl[r][k] = TI[3 * r + k];
+    const double wdetF = QW * TI[9];
+    double xv[4][3], xs[3] = {0, 0, 0};
+    elem_vertices<double>(G, type, px, py, pz, n, xv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xs[k] += xv[v][k];
+    double SV[3] = {0, 0, 0}, VQ[3][4];
+    double SG = 0, DG[4];
+    double Uv[6][10];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c)
+#pragma unroll
+      for (int a = 0; a < 10; ++a) Uv[c][a] = sx[c * NB2 + e.n2i[a]];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double xq[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xq[k] = QB * xs[k] + (QA - QB) * xv[q][k];
+      QGeo<double, BLEND> geo;
+      geo.eval(G, xq, wdetF);
+      double dir[3];
+      {
+        double ri = 1.0 / sqrt(xq[0] * xq[0] + xq[1] * xq[1] + xq[2] * xq[2]);
+        dir[0] = xq[0] * ri;
+        dir[1] = xq[1] * ri;
+        dir[2] = xq[2] * ri;
+      }
+      // value of a P2 field at qp q
+      auto val_at = [&](const double* f) {
+        double sv = f[0] + f[1] + f[2] + f[3];
+        double se = f[4] + f[5] + f[6] + f[7] + f[8] + f[9];
+        double eq = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i != q) eq += f[eidx(i, q)];
+        return NV_OTH * sv + (NV_OWN - NV_OTH) * f[q] + NE_OTH * se + (NE_OWN - NE_OTH) * eq;
+      };
+      if (MODE == 0) {
+        const double Tq = val_at(Uv[0]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double v = scale * geo.W * Tq * dir[c];
+          SV[c] += v;
+          VQ[c][q] = v;
+        }
+      } else {
+        double Gu[3][3], Gl[3][3];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double* Uc = Uv[3 * f + c];
+            double g4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              double s = 0;
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (j != i) s += Uc[eidx(i, j)];
+              g4[i] = C1 * Uc[i] + 4.0 * QB * s + KAP * (i == q ? Uc[i] : Uc[eidx(i, q)]);
+            }
+            double* Gr = f == 0 ? Gu[c] : Gl[c];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+              Gr[k] = (g4[1] - g4[0]) * gl[0][k] + (g4[2] - g4[0]) * gl[1][k] + (g4[3] - g4[0]) * gl[2][k];
+            geo.rowJinv(Gr);
+          }
+        }
+        double dd = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) dd += 0.25 * (Gu[c][k] + Gu[k][c]) * (Gl[c][k] + Gl[k][c]);
+        dd -= (Gu[0][0] + Gu[1][1] + Gu[2][2]) * (Gl[0][0] + Gl[1][1] + Gl[2][2]) / 3.0;
+        SG += geo.W * dd;
+        DG[q] = geo.W * dd;
+        double lr = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lr += val_at(Uv[3 + c]) * dir[c];
+        const double v = scale * geo.W * lr;
+        SV[0] += v;
+        VQ[0][q] = v;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) {
+      double* yc = sy + c * NB2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ldsadd(yc + e.n2i[i], NV_OTH * SV[c] + (NV_OWN - NV_OTH) * VQ[c][i]);
+#pragma unroll
+      for (int ed = 0; ed < 6; ++ed) {
+        const int i = EV0(ed), j = EV1(ed);
+        ldsadd(yc + e.n2i[4 + ed], NE_OTH * SV[c] + (NE_OWN - NE_OTH) * (VQ[c][i] + VQ[c][j]));
+      }
+    }
+    if (MODE == 1) {
+      double et[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) et[v] = seta[e.n1i[v]];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ldsadd(sg + e.n1i[i], -2.0 * et[i] * (QB * SG + (QA - QB) * DG[i]));
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+    if (I + J + K > m2) continue;
+    const size_t g = l2[lloc(I, J, K, m2)];
+    const bool excl = wmask(I, J, K, m2) == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) {
+      if (excl) out2[g + c * N2] = sy[c * NB2 + i];
+      else gadd(out2 + g + c * N2, sy[c * NB2 + i]);
+    }
+  }
+  if (MODE == 1) {
+    for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
+      const int lx = i % B1, ly = (i / B1) % B1, lz = i / (B1 * B1);
+      const int I = ox + lx, J = oy + ly, K = oz + lz;
+      if (I + J + K > n) continue;
+      const size_t g = l1[lloc(I, J, K, n)];
+      const bool excl = wmask(I, J, K, n) == 15 && lx > 0 && lx < B1 - 1 && ly > 0 && ly < B1 - 1 && lz > 0 && lz < B1 - 1;
+      if (excl) out1[g] = sg[i];
+      else gadd(out1 + g, sg[i]);
+    }
+  }
+  (void)bact;
+}
+
+// ---- grid transfers ------------------------------------------------------------
+// Nested P2 spaces: the fine P2 lattice of a macro (side 4 nc) contains the
+// coarse one (side 2 nc).  Fine point J lies in the coarse cube
+// p_k = (J_k - 1) div 4 (J_k > 0; else 0) at local position f = J - 4p in
+// quarter units; its coarse micro-tet is "up" for |f| <= 4, one of the four
+// octahedron tets for 4 < |f| <= 8 (first one containing it), "down" above.
+// Prolongation evaluates the coarse P2 basis there (weights are multiples of
+// 1/8); restriction is the transpose.  Each fine node is handled by the brick
+// of its coarse cube in its owning macro only.
+struct Bary4 {
+  int type, q[4];   // barycentric coordinates times 4
+};
+
+__device__ __forceinline__ Bary4 locate(int fx, int fy, int fz) {
+  Bary4 b;
+  const int s = fx + fy + fz;
+  int t0, t1;
+  if (s <= 4) { t0 = 0; t1 = 0; }
+  else if (s <= 8) { t0 = 1; t1 = 4; }
+  else { t0 = 5; t1 = 5; }
+  for (int t = t0; t <= t1; ++t) {
+    const int rx = fx - 4 * c_toff[t][0][0], ry = fy - 4 * c_toff[t][0][1], rz = fz - 4 * c_toff[t][0][2];
+    int l1 = c_tlinv[t][0][0] * rx + c_tlinv[t][0][1] * ry + c_tlinv[t][0][2] * rz;
+    int l2 = c_tlinv[t][1][0] * rx + c_tlinv[t][1][1] * ry + c_tlinv[t][1][2] * rz;
+    int l3 = c_tlinv[t][2][0] * rx + c_tlinv[t][2][1] * ry + c_tlinv[t][2][2] * rz;
+    int l0 = 4 - l1 - l2 - l3;
+    b.type = t;
+    b.q[0] = l0; b.q[1] = l1; b.q[2] = l2; b.q[3] = l3;
+    if (l0 >= 0 && l1 >= 0 && l2 >= 0 && l3 >= 0) break;
+  }
+  return b;
+}
+
+// P2 basis values times 8 at barycentric coordinates q/4
+__device__ __forceinline__ void p2w8(const int q[4], int w[10]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = q[i] * (q[i] - 2);       // 8 * lam(2 lam - 1)
+#pragma unroll
+  for (int e = 0; e < 6; ++e) w[4 + e] = 2 * q[EV0(e)] * q[EV1(e)];   // 8 * 4 lam_i lam_j
+}
+
+template <typename R, int MODE>   // MODE 0 prolongation, 1 restriction
+__global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, const R* __restrict__ in,
+                                                  R* __restrict__ out, int bcmode) {
+  __shared__ R sc[3 * NB2];
+  const int tile = blockIdx.x % Lc.ntiles;
+  const int mac = blockIdx.x / Lc.ntiles;
+  const int ox = Lc.tiles[3 * tile], oy = Lc.tiles[3 * tile + 1], oz = Lc.tiles[3 * tile + 2];
+  const int nc = Lc.n, mc2 = 2 * nc, mf2 = 4 * nc;
+  const uint32_t* l2c = Lc.l2g2 + (size_t)mac * Lc.nloc2;
+  const uint32_t* l2f = Lf.l2g2 + (size_t)mac * Lf.nloc2;
+  const R* G = geo_of<R>(Lc) + (size_t)mac * 16;
+  const uint8_t* bact = Lc.bact + (size_t)mac * 16;
+  const uint8_t* own = Lf.own + (size_t)mac * 16;
+  const size_t Nc = (size_t)Lc.n2, Nf = (size_t)Lf.n2;
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+    R v0 = 0, v1 = 0, v2 = 0;
+    if (MODE == 0 && I + J + K <= mc2) {
+      const size_t g = l2c[lloc(I, J, K, mc2)];
+      v0 = in[g];
+      v1 = in[g + Nc];
+      v2 = in[g + 2 * Nc];
+    }
+    sc[i] = v0;
+    sc[NB2 + i] = v1;
+    sc[2 * NB2 + i] = v2;
+  }
+  __syncthreads();
+  const int lo[3] = {ox > 0 ? 1 : 0, oy > 0 ? 1 : 0, oz > 0 ? 1 : 0};
+  for (int i = threadIdx.x; i < BF * BF * BF; i += blockDim.x) {
+    const int ax = i % BF, ay = (i / BF) % BF, az = i / (BF * BF);
+    if (ax < lo[0] || ay < lo[1] || az < lo[2]) continue;
+    const int JX = 4 * ox + ax, JY = 4 * oy + ay, JZ = 4 * oz + az;
+    if (JX + JY + JZ > mf2) continue;
+    const int mask = wmask(JX, JY, JZ, mf2);
+    if (!own[mask]) continue;
+    // coarse cube and local quarter position
+    const int px = JX > 0 ? (JX - 1) >> 2 : 0, py = JY > 0 ? (JY - 1) >> 2 : 0, pz = JZ > 0 ? (JZ - 1) >> 2 : 0;
+    const Bary4 b = locate(JX - 4 * px, JY - 4 * py, JZ - 4 * pz);
+    int w[10];
+    p2w8(b.q, w);
+    ElemIdx e;
+    elem_indices(b.type, px - ox, py - oy, pz - oz, e);
+    const size_t gf = l2f[lloc(JX, JY, JZ, mf2)];
+    if (MODE == 0) {
+      R v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R s = 0;
+#pragma unroll
+        for (int a = 0; a < 10; ++a)
+          if (w[a]) s += R(w[a]) * sc[c * NB2 + e.n2i[a]];
+        v[c] = s * R(0.125);
+      }
+      if (bcmode & BCM_OUT) {
+        // fine node class = coarse sub-simplex class (same macro, nested)
+        const int act = Lf.bact[(size_t)mac * 16 + mask];
+        bc_project<R>(act, G, JX, JY, JZ, mf2, v[0], v[1], v[2]);
+      }
+      out[gf] = v[0];
+      out[gf + Nf] = v[1];
+      out[gf + 2 * Nf] = v[2];
+    } else {
+      R v0 = in[gf], v1 = in[gf + Nf], v2 = in[gf + 2 * Nf];
+      if (bcmode & BCM_IN) bc_project<R>(Lf.bact[(size_t)mac * 16 + mask], G, JX, JY, JZ, mf2, v0, v1, v2);
+#pragma unroll
+      for (int a = 0; a < 10; ++a) {
+        if (!w[a]) continue;
+        const R f = R(w[a]) * R(0.125);
+        ldsadd(sc + e.n2i[a], f * v0);
+        ldsadd(sc + NB2 + e.n2i[a], f * v1);
+        ldsadd(sc + 2 * NB2 + e.n2i[a], f * v2);
+      }
+    }
+  }
+  if (MODE == 1) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+      const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+      const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+      if (I + J + K > mc2) continue;
+      const int mask = wmask(I, J, K, mc2);
+      R v0 = sc[i], v1 = sc[NB2 + i], v2 = sc[2 * NB2 + i];
+      if (bcmode & BCM_OUT) {
+        const int act = bact[mask];
+        if (act == ACT_DIR) continue;
+        bc_project<R>(act, G, I, J, K, mc2, v0, v1, v2);
+      }
+      const size_t g = l2c[lloc(I, J, K, mc2)];
+      const bool excl = mask == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
+      if (excl) {
+        out[g] = v0;
+        out[g + Nc] = v1;
+        out[g + 2 * Nc] = v2;
+      } else {
+        gadd(out + g, v0);
+        gadd(out + g + Nc, v1);
+        gadd(out + g + 2 * Nc, v2);
+      }
+    }
+  }
+}
+
+// nodal injection of a P1 field to the next coarser level (coarse node = fine node)
+template <typename R>
+__global__ void k_inject(LevelDev Lc, LevelDev Lf, const R* __restrict__ vf, R* __restrict__ vc) {
+  const int mac = blockIdx.y;
+  const int nc = Lc.n;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < Lc.nloc1; l += gridDim.x * blockDim.x) {
+    // decode lattice point from local index (K-major, then J, then I)
+    int K = 0;
+    while (tetc(nc) - tetc(nc - K - 1) <= l) ++K;
+    int r = l - (int)(tetc(nc) - tetc(nc - K));
+    const int s = nc - K;
+    int J = 0;
+    while (r >= s - J + 1) { r -= s - J + 1; ++J; }
+    const int I = r;
+    if (!Lc.own[(size_t)mac * 16 + wmask(I, J, K, nc)]) continue;
+    const size_t gc = Lc.l2g1[(size_t)mac * Lc.nloc1 + l];
+    const size_t gf = Lf.l2g1[(size_t)mac * Lf.nloc1 + lloc(2 * I, 2 * J, 2 * K, 2 * nc)];
+    vc[gc] = vf[gf];
+  }
+}
+
+// velocity projection over boundary node lists
+template <typename R>
+__global__ void k_project(BcDev bc, long long n2, R* v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < bc.ndir) {
+    const size_t g = bc.dir[i];
+    v[g] = 0;
+    v[g + n2] = 0;
+    v[g + 2 * n2] = 0;
+  } else if (i < bc.ndir + bc.nfs) {
+    const int k = i - bc.ndir;
+    const size_t g = bc.fs[k];
+    const double* nr = bc.nrm + 3 * (size_t)k;
+    R a = v[g], b = v[g + n2], c = v[g + 2 * n2];
+    R dn = a * R(nr[0]) + b * R(nr[1]) + c * R(nr[2]);
+    v[g] = a - dn * R(nr[0]);
+    v[g + n2] = b - dn * R(nr[1]);
+    v[g + 2 * n2] = c - dn * R(nr[2]);
+  }
+}
+
+// ---- vector kernels --------------------------------------------------------------
+template <typename R> __global__ void k_fill(R* x, R a, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) x[i] = a;
+}
+template <typename R> __global__ void k_copy(const R* __restrict__ x, R* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = x[i];
+}
+template <typename R> __global__ void k_axpy(R a, const R* __restrict__ x, R* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] += a * x[i];
+}
+template <typename R> __global__ void k_axpby(R a, const R* __restrict__ x, R b, R* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = a * x[i] + b * y[i];
+}
+template <typename R> __global__ void k_scale(R a, R* x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) x[i] *= a;
+}
+template <typename R> __global__ void k_mul(const R* __restrict__ a, const R* __restrict__ x, R* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = a[i] * x[i];
+}
+template <typename A, typename B> __global__ void k_convert(const A* __restrict__ x, B* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = (B)x[i];
+}
+template <typename R> __global__ void k_invert(const R* __restrict__ d, R* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = d[i] != R(0) ? R(1) / d[i] : R(1);
+}
+__global__ void k_exp(const double* __restrict__ x, double* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = exp(x[i]);
+}
+template <typename R>
+__global__ void k_cheb_dir(const R* __restrict__ dinv, const R* __restrict__ r, R c1, R c2, R* __restrict__ d, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    d[i] = (c2 == R(0)) ? c1 * dinv[i] * r[i] : c1 * dinv[i] * r[i] + c2 * d[i];
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_dot(const R* __restrict__ x, const R* __restrict__ y, long long n, double* partial) {
+  __shared__ double red[256];
+  double s = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s += (double)x[i] * (double)y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ partial, int np, double* out) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int i = threadIdx.x; i < np; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// ---- launch wrappers ----------------------------------------------------------------
+static inline int vgrid(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename R, int FL>
+static void stokes_dispatch(const LevelDev& L, const R* u, const R* p, const R* eta, const R* lnrho, R* yu, R* yp,
+                            int bcmode, hipStream_t s) {
+  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+  if (L.blend)
+    hipLaunchKernelGGL((k_stokes<R, true, FL>), grid, dim3(384), 0, s, L, u, p, eta, lnrho, yu, yp, bcmode);
+  else
+    hipLaunchKernelGGL((k_stokes<R, false, FL>), grid, dim3(384), 0, s, L, u, p, eta, lnrho, yu, yp, bcmode);
+}
+
+template <typename R>
+void launch_stokes(int flags, const LevelDev& L, const R* u, const R* p, const R* eta, const R* lnrho, R* yu, R* yp,
+                   int bcmode, hipStream_t s) {
+  switch (flags) {
+    case F_A: stokes_dispatch<R, F_A>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_BT: stokes_dispatch<R, F_BT>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_BT | F_CT: stokes_dispatch<R, F_BT | F_CT>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_B: stokes_dispatch<R, F_B>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_B | F_C: stokes_dispatch<R, F_B | F_C>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_A | F_BT: stokes_dispatch<R, F_A | F_BT>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_A | F_BT | F_B: stokes_dispatch<R, F_A | F_BT | F_B>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_A | F_BT | F_B | F_C: stokes_dispatch<R, F_A | F_BT | F_B | F_C>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
+    case F_A | F_BT | F_CT | F_B:
+      stokes_dispatch<R, F_A | F_BT | F_CT | F_B>(L, u, p, eta, lnrho, yu, yp, bcmode, s);
+      break;
+    default: break;
+  }
+}
+template void launch_stokes<double>(int, const LevelDev&, const double*, const double*, const double*, const double*,
+                                    double*, double*, int, hipStream_t);
+template void launch_stokes<float>(int, const LevelDev&, const float*, const float*, const float*, const float*, float*,
+                                   float*, int, hipStream_t);
+
+template <typename R>
+void launch_diag(const LevelDev& L, const R* eta, R* d, hipStream_t s) {
+  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+  if (L.blend) hipLaunchKernelGGL((k_diag<R, true>), grid, dim3(384), 0, s, L, eta, d);
+  else hipLaunchKernelGGL((k_diag<R, false>), grid, dim3(384), 0, s, L, eta, d);
+}
+template void launch_diag<double>(const LevelDev&, const double*, double*, hipStream_t);
+template void launch_diag<float>(const LevelDev&, const float*, float*, hipStream_t);
+
+template <typename R>
+void launch_mass(const LevelDev& L, const R* eta, const R* p, R* y, hipStream_t s) {
+  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+  if (L.blend) hipLaunchKernelGGL((k_mass<R, true, false>), grid, dim3(384), 0, s, L, eta, p, y);
+  else hipLaunchKernelGGL((k_mass<R, false, false>), grid, dim3(384), 0, s, L, eta, p, y);
+}
+template void launch_mass<double>(const LevelDev&, const double*, const double*, double*, hipStream_t);
+template void launch_mass<float>(const LevelDev&, const float*, const float*, float*, hipStream_t);
+void launch_mass_diag(const LevelDev& L, const double* eta, double* y, hipStream_t s) {
+  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+  if (L.blend) hipLaunchKernelGGL((k_mass<double, true, true>), grid, dim3(384), 0, s, L, eta, nullptr, y);
+  else hipLaunchKernelGGL((k_mass<double, false, true>), grid, dim3(384), 0, s, L, eta, nullptr, y);
+}
+
+void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s) {
+  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+  if (L.blend)
+    hipLaunchKernelGGL((k_rhs_grad<true, 0>), grid, dim3(384), 0, s, L, T, nullptr, nullptr, nullptr, f, nullptr, scale);
+  else
+    hipLaunchKernelGGL((k_rhs_grad<false, 0>), grid, dim3(384), 0, s, L, T, nullptr, nullptr, nullptr, f, nullptr, scale);
+}
+void launch_gradient(const LevelDev& L, const double* eta, const double* u, const double* lam, double* gm, double* gT,
+                     double scale, hipStream_t s) {
+  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+  if (L.blend)
+    hipLaunchKernelGGL((k_rhs_grad<true, 1>), grid, dim3(384), 0, s, L, nullptr, u, lam, eta, gT, gm, scale);
+  else
+    hipLaunchKernelGGL((k_rhs_grad<false, 1>), grid, dim3(384), 0, s, L, nullptr, u, lam, eta, gT, gm, scale);
+}
+
+template <typename R>
+void launch_prolong(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, int bcmode, hipStream_t s) {
+  dim3 grid((unsigned)(Lc.ntiles * Lc.nmacro));
+  hipLaunchKernelGGL((k_transfer<R, 0>), grid, dim3(256), 0, s, Lc, Lf, ec, ef, bcmode);
+}
+template <typename R>
+void launch_restrict(const LevelDev& Lc, const LevelDev& Lf, const R* rf, R* rc, int bcmode, hipStream_t s) {
+  dim3 grid((unsigned)(Lc.ntiles * Lc.nmacro));
+  hipLaunchKernelGGL((k_transfer<R, 1>), grid, dim3(256), 0, s, Lc, Lf, rf, rc, bcmode);
+}
+template void launch_prolong<double>(const LevelDev&, const LevelDev&, const double*, double*, int, hipStream_t);
+template void launch_prolong<float>(const LevelDev&, const LevelDev&, const float*, float*, int, hipStream_t);
+template void launch_restrict<double>(const LevelDev&, const LevelDev&, const double*, double*, int, hipStream_t);
+template void launch_restrict<float>(const LevelDev&, const LevelDev&, const float*, float*, int, hipStream_t);
+
+template <typename R>
+void launch_inject(const LevelDev& Lc, const LevelDev& Lf, const R* vf, R* vc, hipStream_t s) {
+  dim3 grid((unsigned)((Lc.nloc1 + 255) / 256), (unsigned)Lc.nmacro);
+  hipLaunchKernelGGL((k_inject<R>), grid, dim3(256), 0, s, Lc, Lf, vf, vc);
+}
+template void launch_inject<double>(const LevelDev&, const LevelDev&, const double*, double*, hipStream_t);
+template void launch_inject<float>(const LevelDev&, const LevelDev&, const float*, float*, hipStream_t);
+
+template <typename R>
+void launch_project(const BcDev& bc, long long n2, R* v, hipStream_t s) {
+  const int n = bc.ndir + bc.nfs;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_project<R>), dim3((n + 255) / 256), dim3(256), 0, s, bc, n2, v);
+}
+template void launch_project<double>(const BcDev&, long long, double*, hipStream_t);
+template void launch_project<float>(const BcDev&, long long, float*, hipStream_t);
+
+template <typename R> void vfill(R* x, R a, long long n, hipStream_t s) { hipLaunchKernelGGL((k_fill<R>), dim3(vgrid(n)), dim3(256), 0, s, x, a, n); }
+template <typename R> void vcopy(const R* x, R* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_copy<R>), dim3(vgrid(n)), dim3(256), 0, s, x, y, n); }
+template <typename R> void vaxpy(R a, const R* x, R* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_axpy<R>), dim3(vgrid(n)), dim3(256), 0, s, a, x, y, n); }
+template <typename R> void vaxpby(R a, const R* x, R b, R* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_axpby<R>), dim3(vgrid(n)), dim3(256), 0, s, a, x, b, y, n); }
+template <typename R> void vscale(R a, R* x, long long n, hipStream_t s) { hipLaunchKernelGGL((k_scale<R>), dim3(vgrid(n)), dim3(256), 0, s, a, x, n); }
+template <typename R> void vmul(const R* a, const R* x, R* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_mul<R>), dim3(vgrid(n)), dim3(256), 0, s, a, x, y, n); }
+template <typename A, typename B> void vconvert(const A* x, B* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_convert<A, B>), dim3(vgrid(n)), dim3(256), 0, s, x, y, n); }
+template <typename R> void vinvert(const R* d, R* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_invert<R>), dim3(vgrid(n)), dim3(256), 0, s, d, y, n); }
+void vexp(const double* x, double* y, long long n, hipStream_t s) { hipLaunchKernelGGL(k_exp, dim3(vgrid(n)), dim3(256), 0, s, x, y, n); }
+template <typename R> void vcheb_dir(const R* dinv, const R* r, R c1, R c2, R* d, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_dir<R>), dim3(vgrid(n)), dim3(256), 0, s, dinv, r, c1, c2, d, n);
+}
+template <typename R> void vdot(const R* x, const R* y, long long n, double* partial, double* out, hipStream_t s) {
+  long long g = (n + 255) / 256;
+  int nb = (int)(g < DOT_BLOCKS ? (g < 1 ? 1 : g) : DOT_BLOCKS);
+  hipLaunchKernelGGL((k_dot<R>), dim3(nb), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, nb, out);
+}
+void vsum_partials(double* partial, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, np, out);
+}
+
+#define INST_V(R)                                                                  \
+  template void vfill<R>(R*, R, long long, hipStream_t);                           \
+  template void vcopy<R>(const R*, R*, long long, hipStream_t);                    \
+  template void vaxpy<R>(R, const R*, R*, long long, hipStream_t);                 \
+  template void vaxpby<R>(R, const R*, R, R*, long long, hipStream_t);             \
+  template void vscale<R>(R, R*, long long, hipStream_t);                          \
+  template void vmul<R>(const R*, const R*, R*, long long, hipStream_t);           \
+  template void vinvert<R>(const R*, R*, long long, hipStream_t);                  \
+  template void vcheb_dir<R>(const R*, const R*, R, R, R*, long long, hipStream_t); \
+  template void vdot<R>(const R*, const R*, long long, double*, double*, hipStream_t);
+INST_V(double)
+INST_V(float)
+template void vconvert<double, float>(const double*, float*, long long, hipStream_t);
+template void vconvert<float, double>(const float*, double*, long long, hipStream_t);
+
+}  // namespace stk

@@ -1,0 +1,448 @@
+// Host-side geometry (see mesh.hpp).
+#include "mesh.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <stdexcept>
+
+namespace stk {
+
+// Micro-tet types of the structured refinement, vertex offsets in P1 lattice
+// units relative to the cube origin p: 0 = "up" p+{0,a,b,c}; 1..4 = the
+// octahedron p+{a,b,c,a+b,a+c,b+c} cut along its diagonal b <-> a+c; 5 =
+// "down" p+{a+b,a+c,b+c,a+b+c}.
+const int TYPE_OFF[6][4][3] = {
+    {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {1, 0, 0}, {1, 1, 0}},
+    {{0, 1, 0}, {1, 0, 1}, {1, 1, 0}, {0, 1, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {0, 1, 1}, {0, 0, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {0, 0, 1}, {1, 0, 0}},
+    {{1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}},
+};
+const int EDGE_V[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+MacroMesh make_cube() {
+  MacroMesh mm;
+  mm.kind = 0;
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      for (int z = 0; z < 2; ++z) {
+        mm.V.push_back(x);
+        mm.V.push_back(y);
+        mm.V.push_back(z);
+        mm.layer.push_back(-1);
+      }
+  // Kuhn paths 0 -> e_s1 -> e_s1+e_s2 -> (1,1,1), permutations in lexicographic order
+  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (auto& s : perms) {
+    int p[3] = {0, 0, 0};
+    std::array<int, 4> t;
+    t[0] = 0;
+    for (int k = 0; k < 3; ++k) {
+      p[s[k]] = 1;
+      t[k + 1] = 4 * p[0] + 2 * p[1] + p[2];
+    }
+    mm.tets.push_back(t);
+  }
+  return mm;
+}
+
+MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out) {
+  const double phi = (1.0 + std::sqrt(5.0)) / 2.0;
+  const double raw[12][3] = {{0, 1, phi},  {0, -1, phi},  {0, 1, -phi},  {0, -1, -phi},
+                             {1, phi, 0},  {-1, phi, 0},  {1, -phi, 0},  {-1, -phi, 0},
+                             {phi, 0, 1},  {-phi, 0, 1},  {phi, 0, -1},  {-phi, 0, -1}};
+  double ico[12][3];
+  for (int i = 0; i < 12; ++i) {
+    double n = std::sqrt(raw[i][0] * raw[i][0] + raw[i][1] * raw[i][1] + raw[i][2] * raw[i][2]);
+    for (int d = 0; d < 3; ++d) ico[i][d] = raw[i][d] / n;
+  }
+  auto dist = [&](int i, int j) {
+    double s = 0;
+    for (int d = 0; d < 3; ++d) s += (ico[i][d] - ico[j][d]) * (ico[i][d] - ico[j][d]);
+    return std::sqrt(s);
+  };
+  double emin = 10;
+  for (int i = 0; i < 12; ++i)
+    for (int j = i + 1; j < 12; ++j) emin = std::min(emin, dist(i, j));
+  std::vector<std::array<int, 3>> faces;
+  for (int i = 0; i < 12; ++i)
+    for (int j = i + 1; j < 12; ++j)
+      for (int k = j + 1; k < 12; ++k)
+        if (std::fabs(dist(i, j) - emin) < 1e-9 && std::fabs(dist(j, k) - emin) < 1e-9 &&
+            std::fabs(dist(i, k) - emin) < 1e-9)
+          faces.push_back({i, j, k});
+  if (faces.size() != 20) throw std::runtime_error("icosahedron faces");
+
+  // sphere points keyed by their integer weights over the 12 icosahedron vertices
+  using Key = std::array<int, 12>;
+  std::map<Key, int> keymap;
+  std::vector<Key> keys;
+  std::vector<std::array<int, 3>> tris;   // by key index (pre-sort)
+  for (auto& f : faces) {
+    std::map<std::pair<int, int>, int> idx;
+    for (int i = 0; i <= n_tan; ++i)
+      for (int j = 0; j <= n_tan - i; ++j) {
+        Key w{};
+        w[f[0]] += i;
+        w[f[1]] += j;
+        w[f[2]] += n_tan - i - j;
+        auto it = keymap.find(w);
+        int id;
+        if (it == keymap.end()) {
+          id = (int)keys.size();
+          keymap[w] = id;
+          keys.push_back(w);
+        } else {
+          id = it->second;
+        }
+        idx[{i, j}] = id;
+      }
+    for (int i = 0; i < n_tan; ++i)
+      for (int j = 0; j < n_tan - i; ++j) {
+        tris.push_back({idx[{i, j}], idx[{i + 1, j}], idx[{i, j + 1}]});
+        if (i + j <= n_tan - 2) tris.push_back({idx[{i + 1, j}], idx[{i, j + 1}], idx[{i + 1, j + 1}]});
+      }
+  }
+  // rank of each key in lexicographic order = the point id
+  std::vector<int> rank(keys.size());
+  {
+    int r = 0;
+    for (auto& kv : keymap) rank[kv.second] = r++;
+  }
+  const int ns = (int)keys.size();
+  std::vector<double> dirs(3 * ns);
+  for (int s = 0; s < ns; ++s) {
+    const Key& w = keys[s];
+    double v[3] = {0, 0, 0};
+    for (int k = 0; k < 12; ++k)
+      for (int d = 0; d < 3; ++d) v[d] += w[k] * ico[k][d];
+    double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int d = 0; d < 3; ++d) dirs[3 * rank[s] + d] = v[d] / n;
+  }
+  MacroMesh mm;
+  mm.kind = 1;
+  mm.r_in = r_in;
+  mm.r_out = r_out;
+  mm.n_rad = n_rad;
+  for (int k = 0; k <= n_rad; ++k) {
+    double r = r_in + (r_out - r_in) * k / n_rad;
+    for (int s = 0; s < ns; ++s) {
+      for (int d = 0; d < 3; ++d) mm.V.push_back(r * dirs[3 * s + d]);
+      mm.layer.push_back(k);
+    }
+  }
+  for (auto& t : tris) {
+    int s[3] = {rank[t[0]], rank[t[1]], rank[t[2]]};
+    std::sort(s, s + 3);
+    for (int k = 0; k < n_rad; ++k) {
+      int a0 = s[0] + k * ns, a1 = s[1] + k * ns, a2 = s[2] + k * ns;
+      int b0 = s[0] + (k + 1) * ns, b1 = s[1] + (k + 1) * ns, b2 = s[2] + (k + 1) * ns;
+      mm.tets.push_back({a0, a1, a2, b2});
+      mm.tets.push_back({a0, a1, b1, b2});
+      mm.tets.push_back({a0, b0, b1, b2});
+    }
+  }
+  return mm;
+}
+
+Topology build_topology(const MacroMesh& mm) {
+  Topology t;
+  const int nm = mm.nm();
+  std::map<std::array<int, 3>, int> fmap;
+  std::map<std::array<int, 2>, int> emap;
+  std::vector<int> fcount;
+  t.mface.resize(nm);
+  t.medge.resize(nm);
+  for (int m = 0; m < nm; ++m) {
+    const auto& v = mm.tets[m];
+    for (int f = 0; f < 4; ++f) {
+      std::array<int, 3> k;
+      int c = 0;
+      for (int i = 0; i < 4; ++i)
+        if (i != f) k[c++] = v[i];
+      std::sort(k.begin(), k.end());
+      auto it = fmap.find(k);
+      if (it == fmap.end()) {
+        int id = (int)t.faces.size();
+        fmap[k] = id;
+        t.faces.push_back(k);
+        fcount.push_back(1);
+        t.fowner.push_back(m);
+        t.mface[m][f] = id;
+      } else {
+        fcount[it->second]++;
+        t.mface[m][f] = it->second;
+      }
+    }
+    for (int e = 0; e < 6; ++e) {
+      std::array<int, 2> k = {v[EDGE_V[e][0]], v[EDGE_V[e][1]]};
+      if (k[0] > k[1]) std::swap(k[0], k[1]);
+      auto it = emap.find(k);
+      if (it == emap.end()) {
+        int id = (int)t.edges.size();
+        emap[k] = id;
+        t.edges.push_back(k);
+        t.eowner.push_back(m);
+        t.medge[m][e] = id;
+      } else {
+        t.medge[m][e] = it->second;
+      }
+    }
+  }
+  t.vowner.assign(mm.nv(), -1);
+  for (int m = 0; m < nm; ++m)
+    for (int i = 0; i < 4; ++i)
+      if (t.vowner[mm.tets[m][i]] < 0) t.vowner[mm.tets[m][i]] = m;
+  t.fkind.assign(t.faces.size(), 0);
+  t.ekind.assign(t.edges.size(), 0);
+  t.vkind.assign(mm.nv(), 0);
+  for (size_t f = 0; f < t.faces.size(); ++f) {
+    if (fcount[f] != 1) continue;
+    int kind = 1;
+    if (mm.kind == 1) {
+      const auto& k = t.faces[f];
+      int l0 = mm.layer[k[0]];
+      if (l0 != mm.layer[k[1]] || l0 != mm.layer[k[2]] || (l0 != 0 && l0 != mm.n_rad))
+        throw std::runtime_error("boundary face not on a sphere");
+      kind = (l0 == 0) ? 1 : 2;
+    }
+    t.fkind[f] = kind;
+    const auto& k = t.faces[f];
+    for (int a = 0; a < 3; ++a) {
+      t.vkind[k[a]] = kind;
+      for (int b = a + 1; b < 3; ++b) t.ekind[emap[{k[a], k[b]}]] = kind;
+    }
+  }
+  t.bkind.assign((size_t)nm * 16, 0);
+  t.own.assign((size_t)nm * 16, 0);
+  for (int m = 0; m < nm; ++m) {
+    for (int mask = 1; mask < 16; ++mask) {
+      int cnt = __builtin_popcount(mask);
+      int kind = 0, owner = m;
+      if (cnt == 1) {
+        int v = __builtin_ctz(mask);
+        kind = t.vkind[mm.tets[m][v]];
+        owner = t.vowner[mm.tets[m][v]];
+      } else if (cnt == 2) {
+        int i = __builtin_ctz(mask), j = 31 - __builtin_clz(mask);
+        int e = 0;
+        for (; e < 6; ++e)
+          if (EDGE_V[e][0] == i && EDGE_V[e][1] == j) break;
+        kind = t.ekind[t.medge[m][e]];
+        owner = t.eowner[t.medge[m][e]];
+      } else if (cnt == 3) {
+        int f = __builtin_ctz(~mask & 15);
+        kind = t.fkind[t.mface[m][f]];
+        owner = t.fowner[t.mface[m][f]];
+      }
+      t.bkind[(size_t)m * 16 + mask] = (uint8_t)kind;
+      t.own[(size_t)m * 16 + mask] = (uint8_t)(owner == m);
+    }
+  }
+  return t;
+}
+
+std::vector<double> macro_geometry(const MacroMesh& mm) {
+  const int nm = mm.nm();
+  std::vector<double> G((size_t)nm * 16, 0.0);
+  for (int m = 0; m < nm; ++m) {
+    double v[4][3];
+    for (int i = 0; i < 4; ++i)
+      for (int d = 0; d < 3; ++d) v[i][d] = mm.V[3 * mm.tets[m][i] + d];
+    double* g = &G[(size_t)m * 16];
+    for (int d = 0; d < 3; ++d) g[d] = v[0][d];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) g[3 + 3 * r + c] = v[c + 1][r] - v[0][r];
+    if (mm.kind == 1) {
+      // s(x) = gs.x + s0 interpolates the vertex radii: solve [v_i^T 1][gs; s0] = |v_i|
+      double M[4][5];
+      for (int i = 0; i < 4; ++i) {
+        for (int d = 0; d < 3; ++d) M[i][d] = v[i][d];
+        M[i][3] = 1.0;
+        M[i][4] = std::sqrt(v[i][0] * v[i][0] + v[i][1] * v[i][1] + v[i][2] * v[i][2]);
+      }
+      for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+          if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+        for (int k = 0; k < 5; ++k) std::swap(M[c][k], M[piv][k]);
+        for (int r = 0; r < 4; ++r) {
+          if (r == c) continue;
+          double f = M[r][c] / M[c][c];
+          for (int k = c; k < 5; ++k) M[r][k] -= f * M[c][k];
+        }
+      }
+      for (int c = 0; c < 4; ++c) g[12 + c] = M[c][4] / M[c][c];
+    }
+  }
+  return G;
+}
+
+static void inv3(const double A[3][3], double R[3][3], double* det) {
+  double d = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+             A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+             A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  R[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / d;
+  R[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / d;
+  R[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / d;
+  R[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / d;
+  R[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / d;
+  R[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / d;
+  R[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / d;
+  R[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / d;
+  R[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / d;
+  *det = d;
+}
+
+Level build_level(const MacroMesh& mm, const Topology& top, int L) {
+  Level lv;
+  lv.L = L;
+  lv.n = 1 << L;
+  const int nm = mm.nm();
+  const std::vector<double> geo = macro_geometry(mm);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int m = pass == 0 ? 2 * lv.n : lv.n;   // lattice side (P2 then P1)
+    const int64_t ci = (int64_t)(m - 1) * (m - 2) * (m - 3) / 6;
+    const int64_t fi = (int64_t)(m - 1) * (m - 2) / 2;
+    const int64_t ei = m - 1;
+    const int64_t faceBase = (int64_t)nm * ci;
+    const int64_t edgeBase = faceBase + (int64_t)top.faces.size() * fi;
+    const int64_t vertBase = edgeBase + (int64_t)top.edges.size() * ei;
+    const int64_t total = vertBase + mm.nv();
+    if (total >= (int64_t)UINT32_MAX) throw std::runtime_error("node count exceeds 32-bit indices");
+    const int64_t nloc = tet_count(m);
+    std::vector<uint32_t>& l2g = pass == 0 ? lv.l2g2 : lv.l2g1;
+    l2g.resize((size_t)nm * nloc);
+    // local lattice classification (same for every macro)
+    std::vector<int> loc_w(4 * nloc), loc_int(nloc, -1);
+    {
+      int64_t l = 0, ni = 0;
+      for (int K = 0; K <= m; ++K)
+        for (int J = 0; J <= m - K; ++J)
+          for (int I = 0; I <= m - J - K; ++I, ++l) {
+            int w[4] = {m - I - J - K, I, J, K};
+            for (int k = 0; k < 4; ++k) loc_w[4 * l + k] = w[k];
+            if (w[0] > 0 && I > 0 && J > 0 && K > 0) loc_int[l] = (int)ni++;
+          }
+    }
+    for (int mc = 0; mc < nm; ++mc) {
+      const auto& tv = mm.tets[mc];
+      for (int64_t l = 0; l < nloc; ++l) {
+        const int* w = &loc_w[4 * l];
+        int mask = (w[0] > 0) | ((w[1] > 0) << 1) | ((w[2] > 0) << 2) | ((w[3] > 0) << 3);
+        int cnt = __builtin_popcount(mask);
+        int64_t gid;
+        if (cnt == 4) {
+          gid = (int64_t)mc * ci + loc_int[l];
+        } else if (cnt == 3) {
+          int f = __builtin_ctz(~mask & 15);
+          int gf = top.mface[mc][f];
+          const auto& fv = top.faces[gf];
+          int wv[3];
+          for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 4; ++k)
+              if (tv[k] == fv[a]) wv[a] = w[k];
+          int64_t kk = wv[2] - 1;
+          gid = faceBase + (int64_t)gf * fi + kk * (m - 1) - kk * (kk + 1) / 2 + (wv[1] - 1);
+        } else if (cnt == 2) {
+          int i = __builtin_ctz(mask), j = 31 - __builtin_clz(mask);
+          int e = 0;
+          for (; e < 6; ++e)
+            if (EDGE_V[e][0] == i && EDGE_V[e][1] == j) break;
+          int ge = top.medge[mc][e];
+          int hi = top.edges[ge][1];
+          int whi = (tv[i] == hi) ? w[i] : w[j];
+          gid = edgeBase + (int64_t)ge * ei + (whi - 1);
+        } else {
+          gid = vertBase + tv[__builtin_ctz(mask)];
+        }
+        l2g[(size_t)mc * nloc + l] = (uint32_t)gid;
+        const int kind = top.bkind[(size_t)mc * 16 + mask];
+        if (pass == 0 && kind != 0 && top.own[(size_t)mc * 16 + mask]) {
+          double xt[3];
+          for (int d = 0; d < 3; ++d)
+            xt[d] = (w[0] * mm.V[3 * tv[0] + d] + w[1] * mm.V[3 * tv[1] + d] +
+                     w[2] * mm.V[3 * tv[2] + d] + w[3] * mm.V[3 * tv[3] + d]) / m;
+          double r = std::sqrt(xt[0] * xt[0] + xt[1] * xt[1] + xt[2] * xt[2]);
+          lv.bnode.push_back((uint32_t)gid);
+          lv.bkind.push_back((uint8_t)kind);
+          for (int d = 0; d < 3; ++d) lv.bnormal.push_back(r > 0 ? xt[d] / r : 0.0);
+        }
+      }
+    }
+    if (pass == 0) {
+      lv.n2 = total;
+      lv.nloc2 = nloc;
+    } else {
+      lv.n1 = total;
+      lv.nloc1 = nloc;
+    }
+  }
+  // inverse Jacobians of the 6 micro-tet types per macro
+  lv.tinv.assign((size_t)nm * 60, 0.0);
+  for (int mc = 0; mc < nm; ++mc) {
+    const double* g = &geo[(size_t)mc * 16];
+    for (int t = 0; t < 6; ++t) {
+      double JF[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double s = 0;
+          for (int k = 0; k < 3; ++k) s += g[3 + 3 * r + k] * (TYPE_OFF[t][c + 1][k] - TYPE_OFF[t][0][k]);
+          JF[r][c] = s / lv.n;
+        }
+      double R[3][3], det;
+      inv3(JF, R, &det);
+      double* o = &lv.tinv[((size_t)mc * 6 + t) * 10];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) o[3 * r + c] = R[r][c];
+      o[9] = std::fabs(det);
+    }
+  }
+  const int nb = (lv.n - 1) / TILE;
+  for (int bk = 0; bk <= nb; ++bk)
+    for (int bj = 0; bj <= nb - bk; ++bj)
+      for (int bi = 0; bi <= nb - bj - bk; ++bi) {
+        lv.tiles.push_back(TILE * bi);
+        lv.tiles.push_back(TILE * bj);
+        lv.tiles.push_back(TILE * bk);
+      }
+  return lv;
+}
+
+void level_coords(const MacroMesh& mm, const Topology& top, const Level& lv, int which, double* X,
+                  uint8_t* flags) {
+  const int nm = mm.nm();
+  const int m = which == 2 ? 2 * lv.n : lv.n;
+  const int64_t nloc = which == 2 ? lv.nloc2 : lv.nloc1;
+  const std::vector<uint32_t>& l2g = which == 2 ? lv.l2g2 : lv.l2g1;
+  const std::vector<double> geo = macro_geometry(mm);
+  for (int mc = 0; mc < nm; ++mc) {
+    const auto& tv = mm.tets[mc];
+    const double* g = &geo[(size_t)mc * 16];
+    int64_t l = 0;
+    for (int K = 0; K <= m; ++K)
+      for (int J = 0; J <= m - K; ++J)
+        for (int I = 0; I <= m - J - K; ++I, ++l) {
+          const int w[4] = {m - I - J - K, I, J, K};
+          const int mask = (w[0] > 0) | ((w[1] > 0) << 1) | ((w[2] > 0) << 2) | ((w[3] > 0) << 3);
+          if (!top.own[(size_t)mc * 16 + mask]) continue;
+          const uint32_t gid = l2g[(size_t)mc * nloc + l];
+          if (flags) flags[gid] = top.bkind[(size_t)mc * 16 + mask];
+          if (!X) continue;
+          double xt[3];
+          for (int d = 0; d < 3; ++d)
+            xt[d] = (w[0] * mm.V[3 * tv[0] + d] + w[1] * mm.V[3 * tv[1] + d] + w[2] * mm.V[3 * tv[2] + d] +
+                     w[3] * mm.V[3 * tv[3] + d]) / m;
+          double f = 1.0;
+          if (mm.kind == 1) {
+            double s = g[12] * xt[0] + g[13] * xt[1] + g[14] * xt[2] + g[15];
+            f = s / std::sqrt(xt[0] * xt[0] + xt[1] * xt[1] + xt[2] * xt[2]);
+          }
+          for (int d = 0; d < 3; ++d) X[3 * (size_t)gid + d] = xt[d] * f;
+        }
+  }
+}
+
+}  // namespace stk

@@ -1,0 +1,90 @@
+// Host-side geometry: macro meshes, structured refinement, global numbering.
+//
+// Macro meshes follow Sec. 4.1 of arXiv 2506.04157 (hybrid hierarchical grid:
+// unstructured macro-tetrahedra, each refined uniformly into 8^L micro-tets;
+// the hollow sphere is built from the hollow icosahedron, cut into radial
+// layers of equal height, each prism cut into three tetrahedra).  Where the
+// paper is silent the same readings as the oracle are implemented here from
+// their statement (icosahedron orientation, lexicographic order of the
+// integer point keys, prism split, octahedron diagonal, radial blending).
+//
+// Global numbering: every P1/P2 node belongs to exactly one primitive of the
+// macro mesh (vertex, edge, face or cell interior) and vectors are laid out
+// [cell interiors | face interiors | edge interiors | vertices].  Per level and
+// macro a local-to-global table maps the macro's lattice points
+// (I,J,K), I+J+K <= m, in the order K-major, then J, then I, to global ids.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace stk {
+
+enum { BC_NONE = 0, BC_DIRICHLET = 1, BC_FREESLIP = 2 };
+
+struct MacroMesh {
+  int kind = 0;                       // 0 cube, 1 shell
+  double r_in = 0, r_out = 0;
+  int n_rad = 0;
+  std::vector<double> V;              // 3 * nv reference coordinates
+  std::vector<int> layer;             // radial layer per vertex (shell)
+  std::vector<std::array<int, 4>> tets;
+  int nv() const { return (int)layer.size(); }
+  int nm() const { return (int)tets.size(); }
+};
+
+MacroMesh make_cube();
+MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out);
+
+// Number of lattice points with i+j+k <= s.
+inline int64_t tet_count(int64_t s) { return s < 0 ? 0 : (s + 1) * (s + 2) * (s + 3) / 6; }
+// Local index of lattice point (I,J,K) in a lattice of side m.
+inline int64_t lattice_loc(int I, int J, int K, int m) {
+  int s = m - K;
+  return tet_count(m) - tet_count(m - K) + (int64_t)J * (s + 1) - (int64_t)J * (J - 1) / 2 + I;
+}
+
+// Primitives of the macro mesh and boundary classification.
+struct Topology {
+  std::vector<std::array<int, 3>> faces;   // sorted global vertex ids
+  std::vector<std::array<int, 2>> edges;   // sorted
+  std::vector<std::array<int, 4>> mface;   // per macro: global face id opposite local vertex f
+  std::vector<std::array<int, 6>> medge;   // per macro: global edge id of local edge e
+  std::vector<int> vkind, ekind, fkind;    // boundary kind: 0 interior, 1 inner/cube, 2 outer
+  std::vector<int> vowner, eowner, fowner; // smallest macro containing the primitive
+  std::vector<uint8_t> bkind;              // per macro x 16 (nonzero-weight mask): boundary kind
+  std::vector<uint8_t> own;                // per macro x 16: 1 if this macro owns the sub-simplex
+};
+
+Topology build_topology(const MacroMesh& mm);
+
+// One refinement level: numbering and per-macro tables.
+struct Level {
+  int L = 0, n = 1;                        // n = 2^L
+  int64_t n2 = 0, n1 = 0;                  // global P2 / P1 node counts
+  int64_t nloc2 = 0, nloc1 = 0;            // lattice points per macro
+  std::vector<uint32_t> l2g2, l2g1;        // nm * nloc
+  std::vector<uint32_t> bnode;             // boundary P2 nodes (each once)
+  std::vector<uint8_t> bkind;              // their boundary kind (1 inner/cube, 2 outer)
+  std::vector<double> bnormal;             // 3 per boundary node: x~/|x~| (radial normal)
+  std::vector<double> tinv;                // nm * 6 types * 10: grad lambda_1..3 rows, |det J_F|
+  std::vector<int> tiles;                  // brick origins (3 ints each) in the cube lattice
+};
+
+constexpr int TILE = 4;                    // cubes per brick side
+
+Level build_level(const MacroMesh& mm, const Topology& top, int L);
+// Blended coordinates (3 per node, nullable) and boundary kinds (nullable) of
+// the P2 (which = 2) or P1 (which = 1) nodes of a level.
+void level_coords(const MacroMesh& mm, const Topology& top, const Level& lv, int which, double* X,
+                  uint8_t* flags);
+
+// Per-macro geometry: v0(3), E columns (9: E[r*3+c] = (v_{c+1}-v0)_r), g(3), s0.
+std::vector<double> macro_geometry(const MacroMesh& mm);
+
+// Micro-tet type tables (lattice offsets of the 4 vertices, P1 units).
+extern const int TYPE_OFF[6][4][3];
+extern const int EDGE_V[6][2];
+
+}  // namespace stk

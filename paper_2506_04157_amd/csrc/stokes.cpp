@@ -1,0 +1,1190 @@
+// C ABI, context, and host-side solver orchestration (Sec. 5.2 of
+// arXiv 2506.04157): Chebyshev smoother, geometric multigrid V-cycle, A-block
+// CG, V-cycle BFBT Schur approximation, symmetric Uzawa block
+// preconditioner and the outer FGMRES, all launching the HIP kernels of
+// kernels.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "mesh.hpp"
+#include "stokes.h"
+
+using namespace stk;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct StkError : std::runtime_error {
+  int code;
+  StkError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) throw StkError(STK_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define REQUIRE(c, msg) \
+  do {                  \
+    if (!(c)) throw StkError(STK_EINVAL, msg); \
+  } while (0)
+
+template <class F>
+int guard(F&& f) {
+  try {
+    f();
+    return STK_OK;
+  } catch (StkError& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return STK_ENOMEM;
+  } catch (std::exception& e) {
+    g_err = e.what();
+    return STK_EINVAL;
+  }
+}
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (n == count && p) return;
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw StkError(STK_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void upload(const std::vector<T>& v) {
+    alloc(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+};
+
+// work vectors of one precision on one level
+template <class R>
+struct Pool {
+  std::vector<std::unique_ptr<DBuf<R>>> v;
+  R* get(size_t k, size_t count, hipStream_t s) {
+    while (v.size() <= k) v.emplace_back(new DBuf<R>());
+    if (v[k]->n != count || !v[k]->p) {
+      v[k]->alloc(count);
+      HIPCHK(hipMemsetAsync(v[k]->p, 0, count * sizeof(R), s));
+    }
+    return v[k]->p;
+  }
+};
+
+struct LevelData {
+  Level h;
+  LevelDev d{};
+  BcDev bc{};
+  DBuf<uint32_t> l2g2, l2g1, dir, fs;
+  DBuf<double> tinv, nrm, eta, dinv;
+  DBuf<float> tinvf, nrmf, etaf, dinvf;
+  DBuf<int> tiles;
+  double lo = 0, hi = 0;
+  bool bounds_set = false;
+  Pool<double> p64, q64;   // velocity-size / pressure-size work vectors
+  Pool<float> p32, q32;
+  template <class R> Pool<R>& pool();
+  template <class R> Pool<R>& ppool();
+  template <class R> const R* etap() const;
+  template <class R> const R* dinvp() const;
+};
+template <> Pool<double>& LevelData::pool<double>() { return p64; }
+template <> Pool<float>& LevelData::pool<float>() { return p32; }
+template <> Pool<double>& LevelData::ppool<double>() { return q64; }
+template <> Pool<float>& LevelData::ppool<float>() { return q32; }
+template <> const double* LevelData::etap<double>() const { return eta.p; }
+template <> const float* LevelData::etap<float>() const { return etaf.p; }
+template <> const double* LevelData::dinvp<double>() const { return dinv.p; }
+template <> const float* LevelData::dinvp<float>() const { return dinvf.p; }
+
+// indices into the per-level velocity work pools
+enum { W_B = 0, W_X, W_R, W_D, W_T, W_CG_R, W_CG_Z, W_CG_P, W_CG_Q, W_U0, W_U1, W_U2, W_U3, W_U4, W_U5,
+       W_F0, W_F1, W_F2, W_F3, W_C_R, W_C_Z, W_C_P, W_C_Q, W_C_B, W_C_X };
+// pressure-size pools
+enum { Q_0 = 0, Q_1, Q_2, Q_3, Q_4, Q_5, Q_6, Q_7, Q_8, Q_9, Q_ONES, Q_MD, Q_U0, Q_U1, Q_F0, Q_F1, Q_F2, Q_F3 };
+
+}  // namespace
+
+struct stk_ctx {
+  stk_mesh_desc desc{};
+  MacroMesh mm;
+  Topology top;
+  std::vector<std::unique_ptr<LevelData>> lv;   // index = level; [0, min_level) unused
+  DBuf<double> geo;
+  DBuf<float> geof;
+  DBuf<uint8_t> bact, own;
+  hipStream_t s = nullptr;
+  DBuf<double> dotbuf;
+  double* hpin = nullptr;
+  bool ready = false;
+  bool has_rho = false;
+  DBuf<double> lnrho;
+  DBuf<float> lnrhof;
+  stk_solver_params par{};
+  stk_report* rep = nullptr;
+  // FGMRES storage
+  DBuf<double> fg;
+  int L() const { return desc.level; }
+  int lmin() const { return desc.min_level; }
+  LevelData& at(int l) { return *lv[l]; }
+  template <class R> const R* rho() const;
+};
+template <> const double* stk_ctx::rho<double>() const { return has_rho ? lnrho.p : nullptr; }
+template <> const float* stk_ctx::rho<float>() const { return has_rho ? lnrhof.p : nullptr; }
+
+namespace {
+
+using Ctx = stk_ctx;
+
+long long n2of(Ctx& c, int l) { return c.at(l).h.n2; }
+long long n1of(Ctx& c, int l) { return c.at(l).h.n1; }
+
+template <class R>
+double dot(Ctx& c, const R* x, const R* y, long long n) {
+  vdot<R>(x, y, n, c.dotbuf.p, c.dotbuf.p + DOT_BLOCKS, c.s);
+  HIPCHK(hipMemcpyAsync(c.hpin, c.dotbuf.p + DOT_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  HIPCHK(hipStreamSynchronize(c.s));
+  return *c.hpin;
+}
+template <class R>
+double nrm2(Ctx& c, const R* x, long long n) { return std::sqrt(dot<R>(c, x, x, n)); }
+
+template <class R>
+void project(Ctx& c, int l, R* v) {
+  launch_project<R>(c.at(l).bc, n2of(c, l), v, c.s);
+}
+
+template <class R>
+R* ones(Ctx& c) {
+  LevelData& F = c.at(c.L());
+  Pool<R>& q = F.ppool<R>();
+  bool fresh = q.v.size() <= Q_ONES || !q.v[Q_ONES]->p;
+  R* o = q.get(Q_ONES, n1of(c, c.L()), c.s);
+  if (fresh) vfill<R>(o, R(1), n1of(c, c.L()), c.s);
+  return o;
+}
+
+// P_p: arithmetic mean zero (Sec. 5.1)
+template <class R>
+void project_mean(Ctx& c, R* p) {
+  const long long n1 = n1of(c, c.L());
+  double mean = dot<R>(c, p, ones<R>(c), n1) / (double)n1;
+  vaxpy<R>(R(-mean), ones<R>(c), p, n1, c.s);
+}
+
+// ---- operator applies (outputs overwritten) ---------------------------------
+template <class R>
+void applyA(Ctx& c, int l, const R* x, R* y, int bc) {
+  LevelData& L = c.at(l);
+  vfill<R>(y, R(0), 3 * L.h.n2, c.s);
+  launch_stokes<R>(F_A, L.d, x, nullptr, L.etap<R>(), nullptr, y, nullptr, bc, c.s);
+}
+template <class R>
+void applyB(Ctx& c, int l, const R* u, R* q, bool withC, int bc) {
+  LevelData& L = c.at(l);
+  REQUIRE(!withC || (c.has_rho && l == c.L()), "C block needs ln rho on the finest level");
+  vfill<R>(q, R(0), L.h.n1, c.s);
+  launch_stokes<R>(withC ? (F_B | F_C) : F_B, L.d, u, nullptr, nullptr, c.rho<R>(), nullptr, q, bc, c.s);
+}
+template <class R>
+void applyBt(Ctx& c, int l, const R* p, R* y, bool withCt, int bc) {
+  LevelData& L = c.at(l);
+  REQUIRE(!withCt || (c.has_rho && l == c.L()), "C block needs ln rho on the finest level");
+  vfill<R>(y, R(0), 3 * L.h.n2, c.s);
+  launch_stokes<R>(withCt ? (F_BT | F_CT) : F_BT, L.d, nullptr, p, nullptr, c.rho<R>(), y, nullptr, bc, c.s);
+}
+// K [u;p] on the finest level, velocity projected on both sides
+template <class R>
+void applyK(Ctx& c, const R* u, const R* p, R* yu, R* yp, bool transpose, int bc) {
+  LevelData& L = c.at(c.L());
+  vfill<R>(yu, R(0), 3 * L.h.n2, c.s);
+  vfill<R>(yp, R(0), L.h.n1, c.s);
+  int fl = F_A | F_BT | F_B;
+  if (c.has_rho) fl |= transpose ? F_CT : F_C;
+  launch_stokes<R>(fl, L.d, u, p, L.etap<R>(), c.rho<R>(), yu, yp, bc, c.s);
+}
+
+// ---- Chebyshev smoother (Jacobi preconditioned) -------------------------------
+template <class R>
+void chebyshev(Ctx& c, int l, const R* b, R* x, int steps, int deg, bool xzero) {
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo), sigma = theta / delta;
+  R* r = L.pool<R>().get(W_R, N, c.s);
+  R* d = L.pool<R>().get(W_D, N, c.s);
+  R* t = L.pool<R>().get(W_T, N, c.s);
+  const R* dinv = L.dinvp<R>();
+  for (int st = 0; st < steps; ++st) {
+    if (xzero && st == 0) {
+      vcopy<R>(b, r, N, c.s);
+    } else {
+      applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
+      vcopy<R>(b, r, N, c.s);
+      vaxpy<R>(R(-1), t, r, N, c.s);
+    }
+    project<R>(c, l, r);
+    vcheb_dir<R>(dinv, r, R(1.0 / theta), R(0), d, N, c.s);
+    project<R>(c, l, d);
+    double rho_old = 1.0 / sigma;
+    for (int k = 1; k <= deg; ++k) {
+      vaxpy<R>(R(1), d, x, N, c.s);
+      if (k == deg) break;
+      applyA<R>(c, l, d, t, BCM_IN | BCM_OUT);
+      vaxpy<R>(R(-1), t, r, N, c.s);
+      const double rho = 1.0 / (2.0 * sigma - rho_old);
+      vcheb_dir<R>(dinv, r, R(2.0 * rho / delta), R(rho * rho_old), d, N, c.s);
+      project<R>(c, l, d);
+      rho_old = rho;
+    }
+  }
+}
+
+// ---- coarse grid: Jacobi-preconditioned CG in FP64 (Sec. 5.2.2, tol_coarse) ---
+void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit) {
+  const int l = c.lmin();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  Pool<double>& P = L.pool<double>();
+  double* r = P.get(W_C_R, N, c.s);
+  double* z = P.get(W_C_Z, N, c.s);
+  double* p = P.get(W_C_P, N, c.s);
+  double* q = P.get(W_C_Q, N, c.s);
+  vfill<double>(x, 0.0, N, c.s);
+  vcopy<double>(b, r, N, c.s);
+  project<double>(c, l, r);
+  const double nb = nrm2<double>(c, r, N);
+  if (nb == 0.0) return;
+  vmul<double>(L.dinv.p, r, z, N, c.s);
+  project<double>(c, l, z);
+  vcopy<double>(z, p, N, c.s);
+  double rz = dot<double>(c, r, z, N);
+  for (int it = 1; it <= maxit; ++it) {
+    applyA<double>(c, l, p, q, BCM_IN | BCM_OUT);
+    const double alpha = rz / dot<double>(c, p, q, N);
+    vaxpy<double>(alpha, p, x, N, c.s);
+    vaxpy<double>(-alpha, q, r, N, c.s);
+    if (nrm2<double>(c, r, N) <= tol * nb) break;
+    vmul<double>(L.dinv.p, r, z, N, c.s);
+    project<double>(c, l, z);
+    const double rz2 = dot<double>(c, r, z, N);
+    vaxpby<double>(1.0, z, rz2 / rz, p, N, c.s);
+    rz = rz2;
+  }
+}
+
+template <class R>
+void coarse_solve(Ctx& c, const R* b, R* x) {
+  const int l = c.lmin();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  if (std::is_same<R, double>::value) {
+    coarse_cg64(c, (const double*)b, (double*)x, c.par.tol_coarse, c.par.max_inner * 10);
+  } else {
+    double* b64 = L.pool<double>().get(W_C_B, N, c.s);
+    double* x64 = L.pool<double>().get(W_C_X, N, c.s);
+    vconvert<float, double>((const float*)b, b64, N, c.s);
+    coarse_cg64(c, b64, x64, c.par.tol_coarse, c.par.max_inner * 10);
+    vconvert<double, float>(x64, (float*)x, N, c.s);
+  }
+}
+
+// ---- V-cycle (Sec. 5.2.2, Fig. ASolverStructure) ------------------------------
+template <class R>
+void vcycle(Ctx& c, int l, const R* b, R* x, int steps, int deg) {
+  if (l == c.lmin()) {
+    coarse_solve<R>(c, b, x);
+    return;
+  }
+  LevelData& L = c.at(l);
+  LevelData& C = c.at(l - 1);
+  const long long N = 3 * L.h.n2, Nc = 3 * C.h.n2;
+  vfill<R>(x, R(0), N, c.s);
+  chebyshev<R>(c, l, b, x, steps, deg, true);
+  R* r = L.pool<R>().get(W_R, N, c.s);
+  R* t = L.pool<R>().get(W_T, N, c.s);
+  applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
+  vcopy<R>(b, r, N, c.s);
+  vaxpy<R>(R(-1), t, r, N, c.s);
+  R* bc = C.pool<R>().get(W_B, Nc, c.s);
+  R* xc = C.pool<R>().get(W_X, Nc, c.s);
+  vfill<R>(bc, R(0), Nc, c.s);
+  launch_restrict<R>(C.d, L.d, r, bc, BCM_IN | BCM_OUT, c.s);
+  vcycle<R>(c, l - 1, bc, xc, steps, deg);
+  launch_prolong<R>(C.d, L.d, xc, t, BCM_OUT, c.s);
+  vaxpy<R>(R(1), t, x, N, c.s);
+  chebyshev<R>(c, l, b, x, steps, deg, false);
+  if (c.rep) c.rep->vcycles += (l == c.L());
+}
+
+// ---- A-block solve: CG preconditioned by one V-cycle (Sec. 5.2.2, tol_A) -------
+template <class R>
+void solve_A(Ctx& c, const R* b, R* x) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  Pool<R>& P = L.pool<R>();
+  R* r = P.get(W_CG_R, N, c.s);
+  R* z = P.get(W_CG_Z, N, c.s);
+  R* p = P.get(W_CG_P, N, c.s);
+  R* q = P.get(W_CG_Q, N, c.s);
+  vfill<R>(x, R(0), N, c.s);
+  vcopy<R>(b, r, N, c.s);
+  project<R>(c, l, r);
+  const double nb = nrm2<R>(c, r, N);
+  if (c.rep) c.rep->a_solves++;
+  if (nb == 0.0) return;
+  vcycle<R>(c, l, r, z, c.par.m_A, c.par.deg_A);
+  vcopy<R>(z, p, N, c.s);
+  double rz = dot<R>(c, r, z, N);
+  for (int it = 1; it <= c.par.max_inner; ++it) {
+    if (c.rep) c.rep->a_cg_its++;
+    applyA<R>(c, l, p, q, BCM_IN | BCM_OUT);
+    const double alpha = rz / dot<R>(c, p, q, N);
+    vaxpy<R>(R(alpha), p, x, N, c.s);
+    vaxpy<R>(R(-alpha), q, r, N, c.s);
+    if (nrm2<R>(c, r, N) <= c.par.tol_A * nb) break;
+    vcycle<R>(c, l, r, z, c.par.m_A, c.par.deg_A);
+    const double rz2 = dot<R>(c, r, z, N);
+    vaxpby<R>(R(1), z, R(rz2 / rz), p, N, c.s);
+    rz = rz2;
+  }
+}
+
+// ---- M_{1/eta} solve: Jacobi CG to tol_invmass (Sec. 5.2.3) --------------------
+template <class R>
+void solve_mass(Ctx& c, const R* b, R* x) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long n1 = L.h.n1;
+  Pool<R>& Q = L.ppool<R>();
+  R* md = Q.get(Q_MD, n1, c.s);   // inverse diagonal, filled by set_fields
+  R* r = Q.get(Q_6, n1, c.s);
+  R* p = Q.get(Q_7, n1, c.s);
+  R* q = Q.get(Q_8, n1, c.s);
+  R* z = Q.get(Q_9, n1, c.s);
+  vfill<R>(x, R(0), n1, c.s);
+  vcopy<R>(b, r, n1, c.s);
+  const double nb = nrm2<R>(c, r, n1);
+  if (nb == 0.0) return;
+  vmul<R>(md, r, z, n1, c.s);
+  vcopy<R>(z, p, n1, c.s);
+  double rz = dot<R>(c, r, z, n1);
+  for (int it = 1; it <= c.par.max_inner * 10; ++it) {
+    vfill<R>(q, R(0), n1, c.s);
+    launch_mass<R>(L.d, L.etap<R>(), p, q, c.s);
+    const double alpha = rz / dot<R>(c, p, q, n1);
+    vaxpy<R>(R(alpha), p, x, n1, c.s);
+    vaxpy<R>(R(-alpha), q, r, n1, c.s);
+    if (nrm2<R>(c, r, n1) <= c.par.tol_invmass * nb) break;
+    vmul<R>(md, r, z, n1, c.s);
+    const double rz2 = dot<R>(c, r, z, n1);
+    vaxpby<R>(R(1), z, R(rz2 / rz), p, n1, c.s);
+    rz = rz2;
+  }
+}
+
+// S_C p = B Ac^-1 B^T p, with Ac one V-cycle (m_V, deg_V)
+template <class R>
+void apply_SC(Ctx& c, const R* p, R* y) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  R* t = L.pool<R>().get(W_U3, N, c.s);
+  R* z = L.pool<R>().get(W_U4, N, c.s);
+  applyBt<R>(c, l, p, t, false, BCM_OUT);
+  vcycle<R>(c, l, t, z, c.par.m_V, c.par.deg_V);
+  applyB<R>(c, l, z, y, false, BCM_IN);
+  project_mean<R>(c, y);
+}
+
+// CG on S_C preconditioned by M_{1/eta}^-1, to tol_vbfbt (Sec. 5.2.3)
+template <class R>
+void solve_SC(Ctx& c, const R* b, R* x) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long n1 = L.h.n1;
+  Pool<R>& Q = L.ppool<R>();
+  R* r = Q.get(Q_2, n1, c.s);
+  R* z = Q.get(Q_3, n1, c.s);
+  R* p = Q.get(Q_4, n1, c.s);
+  R* q = Q.get(Q_5, n1, c.s);
+  vfill<R>(x, R(0), n1, c.s);
+  vcopy<R>(b, r, n1, c.s);
+  project_mean<R>(c, r);
+  const double nb = nrm2<R>(c, r, n1);
+  if (c.rep) c.rep->s_solves++;
+  if (nb == 0.0) return;
+  solve_mass<R>(c, r, z);
+  project_mean<R>(c, z);
+  vcopy<R>(z, p, n1, c.s);
+  double rz = dot<R>(c, r, z, n1);
+  for (int it = 1; it <= c.par.max_inner; ++it) {
+    if (c.rep) c.rep->s_cg_its++;
+    apply_SC<R>(c, p, q);
+    const double alpha = rz / dot<R>(c, p, q, n1);
+    vaxpy<R>(R(alpha), p, x, n1, c.s);
+    vaxpy<R>(R(-alpha), q, r, n1, c.s);
+    if (nrm2<R>(c, r, n1) <= c.par.tol_vbfbt * nb) break;
+    solve_mass<R>(c, r, z);
+    project_mean<R>(c, z);
+    const double rz2 = dot<R>(c, r, z, n1);
+    vaxpby<R>(R(1), z, R(rz2 / rz), p, n1, c.s);
+    rz = rz2;
+  }
+}
+
+// V-cycle BFBT, eq. (schurV): (B Ac^-1 B^T)^-1 (B Ac^-1 A Ac^-1 B^T) (B Ac^-1 B^T)^-1
+template <class R>
+void schur_vbfbt(Ctx& c, const R* rp, R* out) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2, n1 = L.h.n1;
+  Pool<R>& Q = L.ppool<R>();
+  R* y1 = Q.get(Q_0, n1, c.s);
+  R* y2 = Q.get(Q_1, n1, c.s);
+  R* t = L.pool<R>().get(W_U3, N, c.s);
+  R* z = L.pool<R>().get(W_U4, N, c.s);
+  R* w = L.pool<R>().get(W_U5, N, c.s);
+  solve_SC<R>(c, rp, y1);
+  applyBt<R>(c, l, y1, t, false, BCM_OUT);
+  vcycle<R>(c, l, t, z, c.par.m_V, c.par.deg_V);
+  applyA<R>(c, l, z, w, BCM_IN | BCM_OUT);
+  vcycle<R>(c, l, w, z, c.par.m_V, c.par.deg_V);
+  applyB<R>(c, l, z, y2, false, BCM_IN);
+  project_mean<R>(c, y2);
+  solve_SC<R>(c, y2, out);
+}
+
+// Symmetric Uzawa step from zero, eq. (SymmetricUzawaStep1):
+//   uh = sigma A^-1 ru;  p = -omega S^-1 (rp - Bbar uh);  u = uh + sigma A^-1 (ru - A uh - B^T p)
+// For the transposed system the roles of B and Bbar swap.
+template <class R>
+void uzawa(Ctx& c, const R* ru, const R* rp, R* u, R* p, bool transpose) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2, n1 = L.h.n1;
+  R* uh = L.pool<R>().get(W_U0, N, c.s);
+  R* t = L.pool<R>().get(W_U1, N, c.s);
+  R* w = L.pool<R>().get(W_U2, N, c.s);
+  R* tp = L.ppool<R>().get(Q_U0, n1, c.s);
+  R* qp = L.ppool<R>().get(Q_U1, n1, c.s);
+  const bool withC = c.has_rho && !transpose && c.par.use_Bbar;
+  const bool withCt = c.has_rho && transpose;
+  solve_A<R>(c, ru, uh);
+  if (c.par.sigma != 1.0) vscale<R>(R(c.par.sigma), uh, N, c.s);
+  applyB<R>(c, l, uh, qp, withC, BCM_IN);
+  vcopy<R>(rp, tp, n1, c.s);
+  vaxpy<R>(R(-1), qp, tp, n1, c.s);
+  project_mean<R>(c, tp);
+  schur_vbfbt<R>(c, tp, p);
+  vscale<R>(R(-c.par.omega), p, n1, c.s);
+  project_mean<R>(c, p);
+  applyA<R>(c, l, uh, t, BCM_IN | BCM_OUT);
+  vcopy<R>(ru, w, N, c.s);
+  vaxpy<R>(R(-1), t, w, N, c.s);
+  applyBt<R>(c, l, p, t, withCt, BCM_OUT);
+  vaxpy<R>(R(-1), t, w, N, c.s);
+  project<R>(c, l, w);
+  solve_A<R>(c, w, u);
+  vaxpby<R>(R(1), uh, R(c.par.sigma), u, N, c.s);
+}
+
+// ---- FGMRES (Saad 1993), right preconditioned, FP64 -----------------------------
+struct FgmresOut {
+  int its = 0;
+  double r0 = 0, rfin = 0;
+  bool converged = false;
+};
+
+FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double* xp, bool transpose) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2, n1 = L.h.n1, Nt = N + n1;
+  const int m = c.par.restart;
+  // m+1 Krylov vectors V, m preconditioned vectors Z, and the right-hand side
+  c.fg.alloc((size_t)(2 * m + 2) * Nt);
+  auto V = [&](int j) { return c.fg.p + (size_t)j * Nt; };
+  auto Z = [&](int j) { return c.fg.p + (size_t)(m + 1 + j) * Nt; };
+  double* b = c.fg.p + (size_t)(2 * m + 1) * Nt;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  auto Hs = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  auto Kapply = [&](const double* x, double* y) {
+    applyK<double>(c, x, x + N, y, y + N, transpose, BCM_IN | BCM_OUT);
+    project_mean<double>(c, y + N);
+  };
+  const bool mixed = c.par.precision == 32;
+  auto precond = [&](const double* v, double* z) {
+    if (mixed) {
+      float* vu = L.pool<float>().get(W_F0, N, c.s);
+      float* zu = L.pool<float>().get(W_F1, N, c.s);
+      float* vp = L.ppool<float>().get(Q_F0, n1, c.s);
+      float* zp = L.ppool<float>().get(Q_F1, n1, c.s);
+      vconvert<double, float>(v, vu, N, c.s);
+      vconvert<double, float>(v + N, vp, n1, c.s);
+      uzawa<float>(c, vu, vp, zu, zp, transpose);
+      vconvert<float, double>(zu, z, N, c.s);
+      vconvert<float, double>(zp, z + N, n1, c.s);
+    } else {
+      uzawa<double>(c, v, v + N, z, z + N, transpose);
+    }
+  };
+  FgmresOut out;
+  vfill<double>(xu, 0.0, N, c.s);
+  vfill<double>(xp, 0.0, n1, c.s);
+  vcopy<double>(bu, b, N, c.s);
+  vcopy<double>(bp, b + N, n1, c.s);
+  project<double>(c, l, b);
+  project_mean<double>(c, b + N);
+  const double nb = nrm2<double>(c, b, Nt);
+  out.r0 = nb;
+  if (c.rep) c.rep->initial_residual = nb;
+  if (nb == 0.0) {
+    out.converged = true;
+    return out;
+  }
+  const double target = std::max(c.par.tol_rel * nb, c.par.tol_abs);
+  double beta = nb;
+  vcopy<double>(b, V(0), Nt, c.s);
+  int total = 0;
+  while (total < c.par.max_outer) {
+    vscale<double>(1.0 / beta, V(0), Nt, c.s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j_used = 0;
+    for (int j = 0; j < m && total < c.par.max_outer; ++j) {
+      precond(V(j), Z(j));
+      Kapply(Z(j), V(j + 1));
+      for (int i = 0; i <= j; ++i) {
+        Hs(i, j) = dot<double>(c, V(j + 1), V(i), Nt);
+        vaxpy<double>(-Hs(i, j), V(i), V(j + 1), Nt, c.s);
+      }
+      Hs(j + 1, j) = nrm2<double>(c, V(j + 1), Nt);
+      if (Hs(j + 1, j) > 0) vscale<double>(1.0 / Hs(j + 1, j), V(j + 1), Nt, c.s);
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * Hs(i, j) + sn[i] * Hs(i + 1, j);
+        Hs(i + 1, j) = -sn[i] * Hs(i, j) + cs[i] * Hs(i + 1, j);
+        Hs(i, j) = t;
+      }
+      double den = std::hypot(Hs(j, j), Hs(j + 1, j));
+      cs[j] = Hs(j, j) / den;
+      sn[j] = Hs(j + 1, j) / den;
+      Hs(j, j) = den;
+      Hs(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      j_used = j + 1;
+      if (c.rep && c.rep->history_len < 256) c.rep->history[c.rep->history_len++] = std::fabs(g[j + 1]) / nb;
+      if (std::fabs(g[j + 1]) <= target) break;
+    }
+    // x += Z y
+    std::vector<double> y(j_used);
+    for (int i = j_used - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < j_used; ++k) s -= Hs(i, k) * y[k];
+      y[i] = s / Hs(i, i);
+    }
+    for (int i = 0; i < j_used; ++i) {
+      vaxpy<double>(y[i], Z(i), xu, N, c.s);
+      vaxpy<double>(y[i], Z(i) + N, xp, n1, c.s);
+    }
+    // true residual r = b - K x  (into V(0))
+    double* tmp = Z(0);
+    vcopy<double>(xu, tmp, N, c.s);
+    vcopy<double>(xp, tmp + N, n1, c.s);
+    Kapply(tmp, V(0));
+    vaxpby<double>(1.0, b, -1.0, V(0), Nt, c.s);
+    project<double>(c, l, V(0));
+    project_mean<double>(c, V(0) + N);
+    beta = nrm2<double>(c, V(0), Nt);
+    out.rfin = beta;
+    out.its = total;
+    if (beta <= target) {
+      out.converged = true;
+      break;
+    }
+  }
+  project_mean<double>(c, xp);
+  return out;
+}
+
+// ---- setup --------------------------------------------------------------------------
+void upload_level(Ctx& c, int l) {
+  LevelData& L = c.at(l);
+  const Level& h = L.h;
+  L.l2g2.upload(h.l2g2);
+  L.l2g1.upload(h.l2g1);
+  L.tinv.upload(h.tinv);
+  std::vector<float> tf(h.tinv.begin(), h.tinv.end());
+  L.tinvf.upload(tf);
+  L.tiles.upload(h.tiles);
+  LevelDev& d = L.d;
+  d.n = h.n;
+  d.nloc2 = (int)h.nloc2;
+  d.nloc1 = (int)h.nloc1;
+  d.nmacro = c.mm.nm();
+  d.ntiles = (int)h.tiles.size() / 3;
+  d.blend = c.mm.kind == 1;
+  d.n2 = h.n2;
+  d.n1 = h.n1;
+  d.l2g2 = L.l2g2.p;
+  d.l2g1 = L.l2g1.p;
+  d.geo = c.geo.p;
+  d.geof = c.geof.p;
+  d.tinv = L.tinv.p;
+  d.tinvf = L.tinvf.p;
+  d.bact = c.bact.p;
+  d.own = c.own.p;
+  d.tiles = L.tiles.p;
+  // boundary lists
+  std::vector<uint32_t> dir, fs;
+  std::vector<double> nrm;
+  for (size_t i = 0; i < h.bnode.size(); ++i) {
+    const int kind = h.bkind[i];
+    const int bc = kind == 1 ? c.desc.bc_inner : c.desc.bc_outer;
+    if (bc == STK_BC_DIRICHLET) {
+      dir.push_back(h.bnode[i]);
+    } else if (bc == STK_BC_FREESLIP) {
+      fs.push_back(h.bnode[i]);
+      for (int k = 0; k < 3; ++k) nrm.push_back(h.bnormal[3 * i + k]);
+    }
+  }
+  L.dir.upload(dir);
+  L.fs.upload(fs);
+  L.nrm.upload(nrm);
+  std::vector<float> nf(nrm.begin(), nrm.end());
+  L.nrmf.upload(nf);
+  L.bc.ndir = (int)dir.size();
+  L.bc.nfs = (int)fs.size();
+  L.bc.dir = L.dir.p;
+  L.bc.fs = L.fs.p;
+  L.bc.nrm = L.nrm.p;
+  L.bc.nrmf = L.nrmf.p;
+}
+
+void check_params(const stk_solver_params* p) {
+  REQUIRE(p, "null solver parameters");
+  REQUIRE(p->precision == 32 || p->precision == 64, "precision must be 32 or 64");
+  REQUIRE(p->restart >= 1 && p->restart <= 200, "restart out of range");
+  REQUIRE(p->m_A >= 1 && p->deg_A >= 1 && p->m_V >= 1 && p->deg_V >= 1, "smoother steps/degree must be >= 1");
+  REQUIRE(p->cheb_lo > 0 && p->cheb_hi > p->cheb_lo, "bad Chebyshev interval factors");
+  REQUIRE(p->max_inner >= 1 && p->max_outer >= 1 && p->power_its >= 1, "iteration caps must be >= 1");
+}
+
+// power iteration for lambda_max(D^-1 A) with projections, FP64
+double power_lambda(Ctx& c, int l, int its) {
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  Pool<double>& P = L.pool<double>();
+  double* x = P.get(W_CG_R, N, c.s);
+  double* t = P.get(W_CG_Z, N, c.s);
+  std::vector<double> hx(N);
+  uint64_t st = 0x9E3779B97F4A7C15ull ^ (uint64_t)l;
+  for (long long i = 0; i < N; ++i) {   // splitmix64, uniform in [-1, 1)
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    hx[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  }
+  HIPCHK(hipMemcpyAsync(x, hx.data(), N * sizeof(double), hipMemcpyHostToDevice, c.s));
+  project<double>(c, l, x);
+  double nx = nrm2<double>(c, x, N);
+  vscale<double>(1.0 / nx, x, N, c.s);
+  double lam = 0;
+  for (int it = 0; it < its; ++it) {
+    applyA<double>(c, l, x, t, BCM_IN | BCM_OUT);
+    vmul<double>(L.dinv.p, t, x, N, c.s);
+    project<double>(c, l, x);
+    lam = nrm2<double>(c, x, N);
+    vscale<double>(1.0 / lam, x, N, c.s);
+  }
+  return lam;
+}
+
+void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const stk_solver_params* par) {
+  check_params(par);
+  c.par = *par;
+  const int Lf = c.L();
+  LevelData& F = c.at(Lf);
+  const long long n1 = F.h.n1;
+  // validate eta > 0, finite
+  {
+    std::vector<double> h(n1);
+    HIPCHK(hipMemcpyAsync(h.data(), eta, n1 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    for (long long i = 0; i < n1; ++i)
+      REQUIRE(std::isfinite(h[i]) && h[i] > 0.0, "viscosity must be positive and finite");
+  }
+  for (int l = c.lmin(); l <= Lf; ++l) {
+    LevelData& L = c.at(l);
+    L.eta.alloc(L.h.n1);
+    L.etaf.alloc(L.h.n1);
+  }
+  if (eta != F.eta.p) vcopy<double>(eta, F.eta.p, n1, c.s);
+  for (int l = Lf; l > c.lmin(); --l) launch_inject<double>(c.at(l - 1).d, c.at(l).d, c.at(l).eta.p, c.at(l - 1).eta.p, c.s);
+  c.has_rho = lnrho != nullptr;
+  if (lnrho) {
+    c.lnrho.alloc(n1);
+    c.lnrhof.alloc(n1);
+    vcopy<double>(lnrho, c.lnrho.p, n1, c.s);
+    vconvert<double, float>(c.lnrho.p, c.lnrhof.p, n1, c.s);
+  }
+  for (int l = c.lmin(); l <= Lf; ++l) {
+    LevelData& L = c.at(l);
+    const long long N = 3 * L.h.n2;
+    vconvert<double, float>(L.eta.p, L.etaf.p, L.h.n1, c.s);
+    L.dinv.alloc(N);
+    L.dinvf.alloc(N);
+    vfill<double>(L.dinv.p, 0.0, N, c.s);
+    launch_diag<double>(L.d, L.eta.p, L.dinv.p, c.s);
+    vinvert<double>(L.dinv.p, L.dinv.p, N, c.s);
+    vconvert<double, float>(L.dinv.p, L.dinvf.p, N, c.s);
+  }
+  for (int l = c.lmin() + 1; l <= Lf; ++l) {
+    LevelData& L = c.at(l);
+    if (!L.bounds_set) {
+      const double lam = power_lambda(c, l, par->power_its);
+      L.lo = par->cheb_lo * lam;
+      L.hi = par->cheb_hi * lam;
+    }
+  }
+  // inverse diagonal of M_{1/eta} (Jacobi preconditioner of its CG)
+  {
+    double* md = F.ppool<double>().get(Q_MD, n1, c.s);
+    vfill<double>(md, 0.0, n1, c.s);
+    launch_mass_diag(F.d, F.eta.p, md, c.s);
+    vinvert<double>(md, md, n1, c.s);
+    float* mdf = F.ppool<float>().get(Q_MD, n1, c.s);
+    vconvert<double, float>(md, mdf, n1, c.s);
+  }
+  HIPCHK(hipStreamSynchronize(c.s));
+  HIPCHK(hipGetLastError());
+  c.ready = true;
+}
+
+void need_ready(Ctx* c) {
+  REQUIRE(c, "null context");
+  if (!c->ready) throw StkError(STK_ENOTREADY, "stk_set_fields has not been called");
+}
+void check_level(Ctx* c, int level) {
+  REQUIRE(c, "null context");
+  REQUIRE(level >= c->lmin() && level <= c->L(), "level outside [min_level, level]");
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+const char* stk_last_error(void) { return g_err.c_str(); }
+
+void stk_default_params(stk_solver_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tol_rel = 1e-8;
+  p->tol_abs = 0.0;
+  p->restart = 20;
+  p->max_outer = 200;
+  p->precision = 64;
+  p->sigma = 1.0;
+  p->omega = 0.3;
+  p->tol_A = 1e-2;
+  p->tol_vbfbt = 1e-1;
+  p->tol_invmass = 1e-10;
+  p->tol_coarse = 1e-2;
+  p->m_A = 3;
+  p->deg_A = 2;
+  p->m_V = 1;
+  p->deg_V = 1;
+  p->max_inner = 100;
+  p->use_Bbar = 1;
+  p->power_its = 15;
+  p->cheb_lo = 0.12;
+  p->cheb_hi = 1.2;
+}
+
+int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
+  return guard([&] {
+    REQUIRE(desc && out, "null argument");
+    REQUIRE(desc->kind == STK_MESH_CUBE || desc->kind == STK_MESH_SHELL, "unknown mesh kind");
+    REQUIRE(desc->level >= 0 && desc->level <= 7, "level must be in [0, 7]");
+    REQUIRE(desc->min_level >= 0 && desc->min_level <= desc->level, "min_level must be in [0, level]");
+    REQUIRE(desc->bc_inner == STK_BC_DIRICHLET || desc->bc_inner == STK_BC_FREESLIP, "bad bc_inner");
+    if (desc->kind == STK_MESH_CUBE) {
+      REQUIRE(desc->bc_inner == STK_BC_DIRICHLET, "the cube supports Dirichlet boundaries only");
+    } else {
+      REQUIRE(desc->bc_outer == STK_BC_DIRICHLET || desc->bc_outer == STK_BC_FREESLIP, "bad bc_outer");
+      REQUIRE(desc->n_tan >= 1 && desc->n_rad >= 1, "n_tan and n_rad must be >= 1");
+      REQUIRE(desc->r_in > 0 && desc->r_out > desc->r_in, "need 0 < r_in < r_out");
+    }
+    std::unique_ptr<stk_ctx> c(new stk_ctx());
+    c->desc = *desc;
+    c->s = (hipStream_t)hip_stream;
+    c->mm = desc->kind == STK_MESH_CUBE ? make_cube() : make_shell(desc->n_tan, desc->n_rad, desc->r_in, desc->r_out);
+    c->top = build_topology(c->mm);
+    std::vector<double> geo = macro_geometry(c->mm);
+    c->geo.upload(geo);
+    std::vector<float> gf(geo.begin(), geo.end());
+    c->geof.upload(gf);
+    // BC action per macro and node class
+    std::vector<uint8_t> act(c->top.bkind.size());
+    for (size_t i = 0; i < act.size(); ++i) {
+      const int k = c->top.bkind[i];
+      act[i] = k == 0 ? ACT_NONE : (uint8_t)(k == 1 ? desc->bc_inner : desc->bc_outer);
+    }
+    c->bact.upload(act);
+    c->own.upload(c->top.own);
+    c->lv.resize(desc->level + 1);
+    for (int l = desc->min_level; l <= desc->level; ++l) {
+      c->lv[l].reset(new LevelData());
+      c->lv[l]->h = build_level(c->mm, c->top, l);
+      upload_level(*c, l);
+    }
+    c->dotbuf.alloc(DOT_BLOCKS + 8);
+    HIPCHK(hipHostMalloc((void**)&c->hpin, 64, hipHostMallocDefault));
+    HIPCHK(hipDeviceSynchronize());
+    *out = c.release();
+  });
+}
+
+int stk_destroy(stk_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->s);
+    if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+    delete ctx;
+  });
+}
+
+int stk_sizes(const stk_ctx* ctx, int level, int64_t* n_p2, int64_t* n_p1) {
+  return guard([&] {
+    check_level(const_cast<stk_ctx*>(ctx), level);
+    if (n_p2) *n_p2 = ctx->lv[level]->h.n2;
+    if (n_p1) *n_p1 = ctx->lv[level]->h.n1;
+  });
+}
+
+int stk_coords(const stk_ctx* ctx, int level, int which, double* xyz, uint8_t* flags) {
+  return guard([&] {
+    check_level(const_cast<stk_ctx*>(ctx), level);
+    REQUIRE(which == 1 || which == 2, "which must be 1 (P1) or 2 (P2)");
+    level_coords(ctx->mm, ctx->top, ctx->lv[level]->h, which, xyz, flags);
+  });
+}
+
+int stk_set_fields(stk_ctx* ctx, const double* eta_p1, const double* lnrho_p1, const stk_solver_params* params) {
+  return guard([&] {
+    REQUIRE(ctx && eta_p1, "null argument");
+    set_fields_internal(*ctx, eta_p1, lnrho_p1, params);
+  });
+}
+
+int stk_set_log_viscosity(stk_ctx* ctx, const double* m_p1, const double* lnrho_p1, const stk_solver_params* params) {
+  return guard([&] {
+    REQUIRE(ctx && m_p1, "null argument");
+    LevelData& F = ctx->at(ctx->L());
+    F.eta.alloc(F.h.n1);
+    vexp(m_p1, F.eta.p, F.h.n1, ctx->s);
+    set_fields_internal(*ctx, F.eta.p, lnrho_p1, params);
+  });
+}
+
+int stk_rhs_buoyancy(stk_ctx* ctx, const double* T_p2, double scale, double* f_u) {
+  return guard([&] {
+    REQUIRE(ctx && T_p2 && f_u, "null argument");
+    LevelData& F = ctx->at(ctx->L());
+    vfill<double>(f_u, 0.0, 3 * F.h.n2, ctx->s);
+    launch_rhs(F.d, T_p2, scale, f_u, ctx->s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+#define PREC_DISPATCH(prec, CALL64, CALL32)                       \
+  do {                                                            \
+    if ((prec) == 64) { CALL64; }                                 \
+    else if ((prec) == 32) { CALL32; }                            \
+    else throw StkError(STK_EINVAL, "prec must be 32 or 64");     \
+  } while (0)
+
+int stk_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int bc) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(x && y, "null vector");
+    PREC_DISPATCH(prec, applyA<double>(*ctx, level, (const double*)x, (double*)y, bc & 3),
+                  applyA<float>(*ctx, level, (const float*)x, (float*)y, bc & 3));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_B(stk_ctx* ctx, int level, int prec, const void* u, void* q, int with_C, int bc) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(u && q, "null vector");
+    PREC_DISPATCH(prec, applyB<double>(*ctx, level, (const double*)u, (double*)q, with_C != 0, bc & 1),
+                  applyB<float>(*ctx, level, (const float*)u, (float*)q, with_C != 0, bc & 1));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_Bt(stk_ctx* ctx, int level, int prec, const void* p, void* y, int with_Ct, int bc) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(p && y, "null vector");
+    PREC_DISPATCH(prec, applyBt<double>(*ctx, level, (const double*)p, (double*)y, with_Ct != 0, bc & 2),
+                  applyBt<float>(*ctx, level, (const float*)p, (float*)y, with_Ct != 0, bc & 2));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_K(stk_ctx* ctx, int prec, const void* u, const void* p, void* yu, void* yp, int transpose, int bc) {
+  return guard([&] {
+    need_ready(ctx);
+    REQUIRE(u && p && yu && yp, "null vector");
+    PREC_DISPATCH(prec,
+                  applyK<double>(*ctx, (const double*)u, (const double*)p, (double*)yu, (double*)yp, transpose != 0, bc & 3),
+                  applyK<float>(*ctx, (const float*)u, (const float*)p, (float*)yu, (float*)yp, transpose != 0, bc & 3));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_mass(stk_ctx* ctx, int level, int prec, const void* p, void* q) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(p && q, "null vector");
+    LevelData& L = ctx->at(level);
+    PREC_DISPATCH(prec,
+                  (vfill<double>((double*)q, 0.0, L.h.n1, ctx->s),
+                   launch_mass<double>(L.d, L.eta.p, (const double*)p, (double*)q, ctx->s)),
+                  (vfill<float>((float*)q, 0.f, L.h.n1, ctx->s),
+                   launch_mass<float>(L.d, L.etaf.p, (const float*)p, (float*)q, ctx->s)));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_diag_A(stk_ctx* ctx, int level, double* d) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(d, "null vector");
+    LevelData& L = ctx->at(level);
+    vfill<double>(d, 0.0, 3 * L.h.n2, ctx->s);
+    launch_diag<double>(L.d, L.eta.p, d, ctx->s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_cheb_bounds(stk_ctx* ctx, int level, double* lo, double* hi) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    if (lo) *lo = ctx->at(level).lo;
+    if (hi) *hi = ctx->at(level).hi;
+  });
+}
+
+int stk_set_cheb_bounds(stk_ctx* ctx, int level, double lo, double hi) {
+  return guard([&] {
+    check_level(ctx, level);
+    REQUIRE(lo > 0 && hi > lo, "need 0 < lo < hi");
+    ctx->at(level).lo = lo;
+    ctx->at(level).hi = hi;
+    ctx->at(level).bounds_set = true;
+  });
+}
+
+int stk_smooth(stk_ctx* ctx, int level, int prec, const void* b, void* x, int degree, int steps) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(b && x, "null vector");
+    REQUIRE(degree >= 1 && steps >= 1, "degree and steps must be >= 1");
+    REQUIRE(ctx->at(level).hi > 0, "no Chebyshev bounds on this level");
+    PREC_DISPATCH(prec, chebyshev<double>(*ctx, level, (const double*)b, (double*)x, steps, degree, false),
+                  chebyshev<float>(*ctx, level, (const float*)b, (float*)x, steps, degree, false));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef) {
+  return guard([&] {
+    REQUIRE(ctx && ec && ef, "null argument");
+    check_level(ctx, level);
+    REQUIRE(level > ctx->lmin(), "prolongation needs level > min_level");
+    LevelData &C = ctx->at(level - 1), &F = ctx->at(level);
+    PREC_DISPATCH(prec, launch_prolong<double>(C.d, F.d, (const double*)ec, (double*)ef, BCM_OUT, ctx->s),
+                  launch_prolong<float>(C.d, F.d, (const float*)ec, (float*)ef, BCM_OUT, ctx->s));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, void* rc) {
+  return guard([&] {
+    REQUIRE(ctx && rf && rc, "null argument");
+    check_level(ctx, level);
+    REQUIRE(level > ctx->lmin(), "restriction needs level > min_level");
+    LevelData &C = ctx->at(level - 1), &F = ctx->at(level);
+    PREC_DISPATCH(prec,
+                  (vfill<double>((double*)rc, 0.0, 3 * C.h.n2, ctx->s),
+                   launch_restrict<double>(C.d, F.d, (const double*)rf, (double*)rc, BCM_OUT, ctx->s)),
+                  (vfill<float>((float*)rc, 0.f, 3 * C.h.n2, ctx->s),
+                   launch_restrict<float>(C.d, F.d, (const float*)rf, (float*)rc, BCM_OUT, ctx->s)));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_vcycle(stk_ctx* ctx, const stk_solver_params* params, int prec, const void* b, void* x, int which) {
+  return guard([&] {
+    need_ready(ctx);
+    check_params(params);
+    REQUIRE(b && x, "null vector");
+    ctx->par = *params;
+    const int st = which == 0 ? params->m_A : params->m_V, dg = which == 0 ? params->deg_A : params->deg_V;
+    PREC_DISPATCH(prec, vcycle<double>(*ctx, ctx->L(), (const double*)b, (double*)x, st, dg),
+                  vcycle<float>(*ctx, ctx->L(), (const float*)b, (float*)x, st, dg));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+static int solve_common(stk_ctx* ctx, const stk_solver_params* params, const double* f_u, const double* g_p,
+                        const double* u_dir, double* u, double* p, stk_report* rep, bool transpose) {
+  int status = STK_OK;
+  int rc = guard([&] {
+    need_ready(ctx);
+    check_params(params);
+    REQUIRE(f_u && u && p, "null vector");
+    ctx->par = *params;
+    stk_report local{};
+    ctx->rep = &local;
+    Ctx& c = *ctx;
+    const int l = c.L();
+    LevelData& F = c.at(l);
+    const long long N = 3 * F.h.n2, n1 = F.h.n1;
+    HIPCHK(hipStreamSynchronize(c.s));
+    auto t0 = std::chrono::steady_clock::now();
+    double* bu = F.pool<double>().get(W_F2, N, c.s);
+    double* bp = F.ppool<double>().get(Q_F2, n1, c.s);
+    double* ud = F.pool<double>().get(W_F3, N, c.s);
+    vcopy<double>(f_u, bu, N, c.s);
+    if (g_p) vcopy<double>(g_p, bp, n1, c.s);
+    else vfill<double>(bp, 0.0, n1, c.s);
+    const bool have_ud = u_dir != nullptr && F.bc.ndir > 0;
+    if (have_ud) {
+      // u_D restricted to Dirichlet nodes: ud = u_dir - P u_dir
+      vcopy<double>(u_dir, ud, N, c.s);
+      double* t = F.pool<double>().get(W_U0, N, c.s);
+      vcopy<double>(u_dir, t, N, c.s);
+      launch_project<double>(BcDev{F.bc.ndir, 0, F.bc.dir, nullptr, nullptr, nullptr}, F.h.n2, t, c.s);
+      vaxpy<double>(-1.0, t, ud, N, c.s);
+      // b_u -= A u_D, b_p -= Bbar u_D (or B for the transpose)
+      double* tp = F.ppool<double>().get(Q_F3, n1, c.s);
+      applyA<double>(c, l, ud, t, BCM_OUT);
+      vaxpy<double>(-1.0, t, bu, N, c.s);
+      applyB<double>(c, l, ud, tp, c.has_rho && !transpose, 0);
+      vaxpy<double>(-1.0, tp, bp, n1, c.s);
+    }
+    FgmresOut fo = fgmres(c, bu, bp, u, p, transpose);
+    if (have_ud) vaxpy<double>(1.0, ud, u, N, c.s);
+    HIPCHK(hipStreamSynchronize(c.s));
+    HIPCHK(hipGetLastError());
+    auto t1 = std::chrono::steady_clock::now();
+    local.iterations = fo.its;
+    local.initial_residual = fo.r0;
+    local.abs_residual = fo.rfin;
+    local.rel_residual = fo.r0 > 0 ? fo.rfin / fo.r0 : 0.0;
+    local.seconds = std::chrono::duration<double>(t1 - t0).count();
+    ctx->rep = nullptr;
+    if (rep) *rep = local;
+    if (!fo.converged) status = STK_ENOCONV;
+  });
+  if (ctx) ctx->rep = nullptr;
+  if (rc != STK_OK) return rc;
+  if (status == STK_ENOCONV) g_err = "FGMRES reached max_outer before the tolerance";
+  return status;
+}
+
+int stk_solve(stk_ctx* ctx, const stk_solver_params* params, const double* f_u, const double* g_p,
+              const double* u_dirichlet, double* u, double* p, stk_report* rep) {
+  return solve_common(ctx, params, f_u, g_p, u_dirichlet, u, p, rep, false);
+}
+
+int stk_solve_adjoint(stk_ctx* ctx, const stk_solver_params* params, const double* ju, const double* jp, double* lu,
+                      double* lp, stk_report* rep) {
+  return solve_common(ctx, params, ju, jp, nullptr, lu, lp, rep, true);
+}
+
+int stk_gradient(stk_ctx* ctx, const double* u, const double* lu, double scale, double* g_m, double* g_T) {
+  return guard([&] {
+    need_ready(ctx);
+    REQUIRE(u && lu && g_m && g_T, "null vector");
+    LevelData& F = ctx->at(ctx->L());
+    vfill<double>(g_m, 0.0, F.h.n1, ctx->s);
+    vfill<double>(g_T, 0.0, F.h.n2, ctx->s);
+    launch_gradient(F.d, F.eta.p, u, lu, g_m, g_T, scale, ctx->s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_per_apply) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(x && y && ms_per_apply && reps >= 1, "bad argument");
+    LevelData& L = ctx->at(level);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, ctx->s));
+    for (int i = 0; i < reps; ++i) {
+      if (prec == 64)
+        launch_stokes<double>(F_A, L.d, (const double*)x, nullptr, L.eta.p, nullptr, (double*)y, nullptr,
+                              BCM_IN | BCM_OUT, ctx->s);
+      else
+        launch_stokes<float>(F_A, L.d, (const float*)x, nullptr, L.etaf.p, nullptr, (float*)y, nullptr,
+                             BCM_IN | BCM_OUT, ctx->s);
+    }
+    HIPCHK(hipEventRecord(e1, ctx->s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_apply = ms / reps;
+  });
+}
+
+}  // extern "C"
