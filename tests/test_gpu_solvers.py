@@ -1,0 +1,231 @@
+"""GPU parity of the solver components against the oracle's assembled references."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import inputs
+from oracle.adjoint import grad_log_eta, grad_temperature
+from oracle.fem import assemble_A, assemble_B, rhs_buoyancy
+from oracle.solvers import chebyshev, prolongation, vcycle, vector_prolongation
+from oracle.system import solve_stokes
+from paper_2506_04157_amd import default_params
+from tests._util import Pair, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _eta(m, seed=3, lo=-2.0, hi=2.0):
+    return np.exp(inputs.uniform(seed, m.n1, lo, hi))
+
+
+@pytest.mark.parametrize("kind,L,lmin", [("cube", 3, 1), ("shell", 2, 0)])
+def test_prolongation_and_restriction(kind, L, lmin):
+    print(f"\n[transfers {kind} L{L}]", flush=True)
+    P = Pair(kind, L, min_level=lmin)
+    for l in range(lmin + 1, L + 1):
+        mc, mf = P.meshes[l - 1], P.meshes[l]
+        Pro = vector_prolongation(prolongation(mc, mf))
+        Pf, _ = P.projector(l)
+        Pc, _ = P.projector(l - 1)
+        for dtype, tol in [(torch.float64, 1e-14), (torch.float32, 1e-6)]:
+            ec = inputs.uniform(7, 3 * mc.n2)
+            ef = P.u_to_or(P.ctx.prolong(P.u_to_lib(ec, l - 1, dtype), l), l)
+            assert relerr(ef, Pf @ (Pro @ ec)) < tol
+            rf = inputs.uniform(8, 3 * mf.n2)
+            rc = P.u_to_or(P.ctx.restrict(P.u_to_lib(rf, l, dtype), l), l - 1)
+            assert relerr(rc, Pc @ (Pro.T @ rf)) < tol
+
+
+def _oracle_levels(P, eta_fine, bounds):
+    levels = []
+    lmin = min(P.meshes)
+    etas = {}
+    for l in sorted(P.meshes):
+        m = P.meshes[l]
+        # nodal injection of the fine viscosity (coarse nodes are fine nodes)
+        from scipy.spatial import cKDTree
+        idx = cKDTree(P.meshes[P.L].X1).query(m.X1)[1]
+        etas[l] = eta_fine[idx]
+        A = assemble_A(m, etas[l])
+        Pm, Q = P.projector(l)
+        d = dict(A=A, P=Pm, Q=Q, Dinv=1.0 / A.diagonal())
+        if l in bounds:
+            d["lo"], d["hi"] = bounds[l]
+        if l > lmin:
+            d["Pro"] = vector_prolongation(prolongation(P.meshes[l - 1], m))
+        levels.append(d)
+    return levels
+
+
+def _power_bounds(levels, lmin):
+    b = {}
+    for i, d in enumerate(levels[1:], start=1):
+        x = d["P"] @ inputs.uniform(20 + i, d["A"].shape[0])
+        for _ in range(30):
+            x = d["P"] @ (d["Dinv"] * (d["A"] @ (d["P"] @ x)))
+            lam = np.linalg.norm(x)
+            x /= lam
+        b[lmin + i] = (0.12 * lam, 1.2 * lam)
+    return b
+
+
+@pytest.mark.parametrize("kind,L,lmin", [("cube", 3, 1), ("shell", 2, 0)])
+def test_chebyshev_smoother(kind, L, lmin):
+    print(f"\n[chebyshev {kind} L{L}]", flush=True)
+    P = Pair(kind, L, min_level=lmin)
+    m = P.meshes[L]
+    eta = _eta(m)
+    P.ctx.set_fields(P.p_to_lib(eta))
+    levels = _oracle_levels(P, eta, {})
+    bounds = _power_bounds(levels, lmin)
+    lo, hi = bounds[L]
+    P.ctx.set_cheb_bounds(L, lo, hi)
+    d = levels[-1]
+    b = d["P"] @ inputs.uniform(1, 3 * m.n2)
+    x0 = d["P"] @ inputs.uniform(2, 3 * m.n2)
+    for deg, steps in [(1, 1), (2, 3), (3, 2)]:
+        ref = chebyshev(d["A"], d["Dinv"], d["P"], b, x0, lo, hi, deg, steps)
+        for dtype, tol in [(torch.float64, 1e-12), (torch.float32, 1e-5)]:
+            x = P.u_to_lib(x0, dtype=dtype)
+            P.ctx.smooth(P.u_to_lib(b, dtype=dtype), x, degree=deg, steps=steps)
+            assert relerr(P.u_to_or(x), ref) < tol, (deg, steps, dtype)
+
+
+@pytest.mark.parametrize("kind,L,lmin", [("cube", 3, 1), ("shell", 2, 0)])
+def test_vcycle_matches_assembled_vcycle(kind, L, lmin):
+    print(f"\n[vcycle {kind} L{L}]", flush=True)
+    P = Pair(kind, L, min_level=lmin)
+    m = P.meshes[L]
+    eta = _eta(m)
+    levels = _oracle_levels(P, eta, {})
+    bounds = _power_bounds(levels, lmin)
+    for l, (lo, hi) in bounds.items():
+        levels[l - lmin]["lo"], levels[l - lmin]["hi"] = lo, hi
+        P.ctx.set_cheb_bounds(l, lo, hi)
+    params = default_params(tol_coarse=1e-15, max_inner=2000)
+    P.ctx.set_fields(P.p_to_lib(eta), params=params)
+    Q0 = levels[0]["Q"]
+    lu = spla.splu((Q0.T @ levels[0]["A"] @ Q0).tocsc())
+    cs = lambda r: Q0 @ lu.solve(Q0.T @ r)
+    b = levels[-1]["P"] @ inputs.uniform(4, 3 * m.n2)
+    for which, (steps, deg) in [(0, (3, 2)), (1, (1, 1))]:
+        ref = vcycle(levels, L - lmin, b, cs, deg, steps)
+        x = P.ctx.vcycle(P.u_to_lib(b), params, which=which)
+        assert relerr(P.u_to_or(x), ref) < 1e-9
+        x32 = P.ctx.vcycle(P.u_to_lib(b, dtype=torch.float32), params, which=which)
+        assert relerr(P.u_to_or(x32), ref) < 1e-4
+
+
+def _oracle_solution(P, eta, lnrho, f, uD=None, transpose=False):
+    m = P.meshes[P.L]
+    A = assemble_A(m, eta)
+    B = assemble_B(m)
+    Bb = B + assemble_B(m, lnrho, only_C=True) if lnrho is not None else B
+    _, Q = P.projector()
+    if transpose:
+        return solve_stokes(A, B, f, np.zeros(m.n1), Q, uD, Bt=Bb.T), (A, B, Bb, Q)
+    return solve_stokes(A, Bb, f, np.zeros(m.n1), Q, uD, Bt=B.T), (A, B, Bb, Q)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_solve_cube_dirichlet_data(precision):
+    print(f"\n[solve cube prec {precision}]", flush=True)
+    P = Pair("cube", 3, min_level=1)
+    m = P.meshes[3]
+    eta = np.exp(2.0 * np.sin(3 * m.X1[:, 0]) * np.cos(2 * m.X1[:, 1]))
+    f = inputs.uniform(5, 3 * m.n2)
+    uD = inputs.smooth_vector_field(6, m.X2).T.ravel()
+    (uo, po, _), (A, B, Bb, Q) = _oracle_solution(P, eta, None, f, uD)
+    params = default_params(tol_rel=1e-10, precision=precision)
+    P.ctx.set_fields(P.p_to_lib(eta), params=params)
+    u, p, rep = P.ctx.solve(P.u_to_lib(f), u_dirichlet=P.u_to_lib(uD), params=params)
+    print(rep["iterations"], rep["rel_residual"], rep["seconds"])
+    ug, pg = P.u_to_or(u), P.p_to_or(p)
+    assert rep["rel_residual"] <= 1e-10
+    assert relerr(ug, uo) < 1e-7 and relerr(pg, po) < 1e-6
+    # residual of the GPU solution in the oracle's assembled system
+    Pm = Q @ Q.T
+    ru = Pm @ (f - A @ ug - B.T @ pg)
+    assert np.linalg.norm(ru) <= 1e-8 * np.linalg.norm(Pm @ (f - A @ uD))
+    dm = np.tile(m.flag2 == 1, 3)
+    assert np.allclose(ug[dm], uD[dm], atol=1e-14)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_solve_shell_freeslip_compressible(precision):
+    print(f"\n[solve shell prec {precision}]", flush=True)
+    P = Pair("shell", 2, min_level=0, n_tan=1, n_rad=1)
+    m = P.meshes[2]
+    field = inputs.SHField(2)
+    eta = inputs.viscosity_contrast(field.temperature(m.X1), 1e4)
+    lnrho = inputs.ln_density(m.X1)
+    T = field.temperature(m.X2)
+    f = rhs_buoyancy(m, T)
+    (uo, po, _), (A, B, Bb, Q) = _oracle_solution(P, eta, lnrho, f)
+    params = default_params(tol_rel=1e-10, precision=precision)
+    P.ctx.set_fields(P.p_to_lib(eta), P.p_to_lib(lnrho), params=params)
+    fl = P.ctx.rhs_buoyancy(P.s2_to_lib(T))
+    assert relerr(P.u_to_or(fl), f) < 1e-12
+    u, p, rep = P.ctx.solve(fl, params=params)
+    print(rep["iterations"], rep["rel_residual"], rep["seconds"], rep["a_cg_its"], rep["s_cg_its"])
+    ug, pg = P.u_to_or(u), P.p_to_or(p)
+    assert rep["rel_residual"] <= 1e-10
+    assert relerr(ug, uo) < 1e-7 and relerr(pg, po) < 1e-6
+    assert abs(pg.mean()) < 1e-12 * np.abs(pg).max()
+
+
+def test_adjoint_solve_and_gradient():
+    print("\n[adjoint]", flush=True)
+    P = Pair("shell", 2, min_level=0)
+    m = P.meshes[2]
+    eta = _eta(m, 9, -1.5, 1.5)
+    lnrho = inputs.ln_density(m.X1)
+    ju = inputs.uniform(10, 3 * m.n2)
+    (lo, lpo, _), (A, B, Bb, Q) = _oracle_solution(P, eta, lnrho, ju, transpose=True)
+    params = default_params(tol_rel=1e-11)
+    P.ctx.set_fields(P.p_to_lib(eta), P.p_to_lib(lnrho), params=params)
+    lu, lp, rep = P.ctx.solve_adjoint(P.u_to_lib(ju), params=params)
+    assert relerr(P.u_to_or(lu), lo) < 1e-7
+    # gradient kernel vs the oracle's assembled gradient (any u, lambda)
+    u = inputs.uniform(11, 3 * m.n2)
+    lam = inputs.uniform(12, 3 * m.n2)
+    gm, gT = P.ctx.gradient(P.u_to_lib(u), P.u_to_lib(lam), scale=1.5)
+    assert relerr(P.p_to_or(gm), grad_log_eta(m, eta, u, lam)) < 1e-12
+    assert relerr(P.s2_to_or(gT), grad_temperature(m, lam, scale=1.5)) < 1e-12
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_autograd_matches_central_differences(precision):
+    """dJ/dm and dJ/dT of J = 1/2 |u - u_obs|^2 within 1e-6 of central
+    differences (h = 1e-6) on seeded directions."""
+    from paper_2506_04157_amd import StokesSolve
+    print(f"\n[autograd prec {precision}]", flush=True)
+    P = Pair("shell", 2, min_level=0)
+    m = P.meshes[2]
+    field = inputs.SHField(2)
+    m0 = np.log(inputs.viscosity_contrast(field.temperature(m.X1), 1e4))
+    T0 = field.temperature(m.X2)
+    uobs = P.u_to_lib(0.01 * inputs.uniform(5, 3 * m.n2))
+    params = default_params(tol_rel=1e-13, precision=precision, max_outer=400)
+
+    def J(mv, Tv, grad=False):
+        mt = P.p_to_lib(mv).requires_grad_(grad)
+        Tt = P.s2_to_lib(Tv).requires_grad_(grad)
+        u, p = StokesSolve.apply(mt, Tt, P.ctx, params)
+        j = 0.5 * ((u - uobs) ** 2).sum()
+        if grad:
+            j.backward()
+            return j.item(), P.p_to_or(mt.grad), P.s2_to_or(Tt.grad)
+        return j.item()
+
+    j0, gm, gT = J(m0, T0, grad=True)
+    h = 1e-6
+    for k in range(3):
+        dmv = inputs.normal(40 + k, m.n1)
+        dT = inputs.normal(50 + k, m.n2)
+        fd_m = (J(m0 + h * dmv, T0) - J(m0 - h * dmv, T0)) / (2 * h)
+        fd_T = (J(m0, T0 + h * dT) - J(m0, T0 - h * dT)) / (2 * h)
+        print(k, fd_m, gm @ dmv, fd_T, gT @ dT)
+        assert abs(fd_m - gm @ dmv) <= 1e-6 * abs(fd_m) + 1e-12
+        assert abs(fd_T - gT @ dT) <= 1e-6 * abs(fd_T) + 1e-12
