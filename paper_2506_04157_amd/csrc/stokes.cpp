@@ -556,6 +556,10 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
     } else {
       uzawa<double>(c, v, v + N, z, z + N, transpose);
     }
+    // keep the Krylov space exactly in range(P): FP32 projections leave
+    // normal components of relative size ~1e-7 at free-slip nodes
+    project<double>(c, l, z);
+    project_mean<double>(c, z + N);
   };
   FgmresOut out;
   vfill<double>(xu, 0.0, N, c.s);
@@ -633,6 +637,7 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
       break;
     }
   }
+  project<double>(c, l, xu);
   project_mean<double>(c, xp);
   return out;
 }
