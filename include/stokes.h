@@ -91,7 +91,9 @@ typedef struct {
   double initial_residual;
   int a_solves, a_cg_its;  /* A-block solves and their total CG iterations */
   int s_solves, s_cg_its;  /* BFBT inner solves and their total CG iterations */
-  int vcycles;
+  int vcycles;             /* V-cycles on the finest level */
+  int coarse_its;          /* coarse-grid CG iterations (all V-cycles) */
+  int mass_its;            /* M_{1/eta} CG iterations (all BFBT solves) */
   double seconds;          /* wall time of the solve (host clock, stream synchronised) */
   int history_len;
   double history[256];     /* relative residual after each FGMRES iteration */
@@ -166,11 +168,13 @@ int stk_solve_adjoint(stk_ctx* ctx, const stk_solver_params* params, const doubl
  * overwritten, device doubles. */
 int stk_gradient(stk_ctx* ctx, const double* u, const double* lu, double scale, double* g_m, double* g_T);
 
-/* Times `reps` back-to-back launches of the A-apply kernel of `level` (input
- * projected, output accumulated into y, which ends up holding garbage)
- * between two HIP events on the context stream; *ms_per_apply = average
- * kernel duration in milliseconds. */
-int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_per_apply);
+/* Times `reps` back-to-back A-applies of `level` (input and output projected)
+ * between HIP events on the context stream: *ms_apply = average time of the
+ * whole operator (plane-sweep kernel, gather of shared nodes, projection);
+ * *ms_kernel (nullable) = average time of the plane-sweep kernel alone,
+ * launched `reps` more times.  y is overwritten. */
+int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_apply,
+                     double* ms_kernel);
 
 #ifdef __cplusplus
 }

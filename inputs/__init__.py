@@ -56,6 +56,34 @@ class SHField:
     def temperature(self, xyz):
         return np.clip(0.5 + 0.5 * self.raw(xyz) / self.smax, 0.0, 1.0)
 
+    def temperature_torch(self, xyz):
+        """Same field for a (n, 3) float64 torch tensor, evaluated where the
+        tensor lives (associated Legendre functions by the standard
+        three-term recurrence, Condon-Shortley phase as scipy's lpmv)."""
+        import torch
+        r = torch.linalg.norm(xyz, dim=1)
+        ct = torch.clamp(xyz[:, 2] / r, -1.0, 1.0)
+        st = torch.sqrt(torch.clamp(1.0 - ct * ct, min=0.0))
+        ph = torch.atan2(xyz[:, 1], xyz[:, 0])
+        lmax = max(l for (l, _, _, _) in self.terms)
+        P = {}
+        for m in range(lmax + 1):
+            pmm = torch.ones_like(ct)
+            fact = 1.0
+            for _ in range(m):
+                pmm = -pmm * fact * st
+                fact += 2.0
+            P[(m, m)] = pmm
+            if m + 1 <= lmax:
+                P[(m + 1, m)] = ct * (2 * m + 1) * pmm
+            for l in range(m + 2, lmax + 1):
+                P[(l, m)] = ((2 * l - 1) * ct * P[(l - 1, m)] - (l + m - 1) * P[(l - 2, m)]) / (l - m)
+        s = torch.zeros_like(ct)
+        for (l, m, a, c) in self.terms:
+            ang = torch.cos(m * ph) if m >= 0 else torch.sin(-m * ph)
+            s += a * P[(l, abs(m))] * ang * torch.cos(np.pi * c * (r - self.r_in) / (self.r_out - self.r_in))
+        return torch.clamp(0.5 + 0.5 * s / self.smax, 0.0, 1.0)
+
 
 def viscosity_contrast(T, contrast=1e4):
     """eta = exp(ln(contrast) (0.5 - T)), in [contrast^-1/2, contrast^1/2] for T in [0,1]."""

@@ -30,7 +30,8 @@ class Report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
                 ("abs_residual", ctypes.c_double), ("initial_residual", ctypes.c_double),
                 ("a_solves", ctypes.c_int), ("a_cg_its", ctypes.c_int), ("s_solves", ctypes.c_int),
-                ("s_cg_its", ctypes.c_int), ("vcycles", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("s_cg_its", ctypes.c_int), ("vcycles", ctypes.c_int), ("coarse_its", ctypes.c_int),
+                ("mass_its", ctypes.c_int), ("seconds", ctypes.c_double),
                 ("history_len", ctypes.c_int), ("history", ctypes.c_double * 256)]
 
     def as_dict(self):
@@ -70,7 +71,7 @@ SIGNATURES = {
     "stk_solve": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, _P, ctypes.POINTER(Report)],
     "stk_solve_adjoint": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, ctypes.POINTER(Report)],
     "stk_gradient": [_CTX, _P, _P, _D, _P, _P],
-    "stk_time_apply_A": [_CTX, _I, _I, _P, _P, _I, ctypes.POINTER(_D)],
+    "stk_time_apply_A": [_CTX, _I, _I, _P, _P, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)],
 }
 
 _lib = None

@@ -197,7 +197,9 @@ class StokesContext:
         return gm, gT
 
     def time_apply_A(self, x, y, reps=20, level=None):
+        """(ms per A-apply operator, ms per plane-sweep kernel launch)."""
         level = self.level if level is None else level
-        ms = ctypes.c_double()
-        check(self.lib.stk_time_apply_A(self.h, level, _prec(x), _ptr(x), _ptr(y), reps, ctypes.byref(ms)))
-        return ms.value
+        ms, mk = ctypes.c_double(), ctypes.c_double()
+        check(self.lib.stk_time_apply_A(self.h, level, _prec(x), _ptr(x), _ptr(y), reps, ctypes.byref(ms),
+                                        ctypes.byref(mk)))
+        return ms.value, mk.value

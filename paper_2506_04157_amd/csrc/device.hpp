@@ -13,12 +13,30 @@ constexpr int NB2 = B2 * B2 * B2;
 constexpr int NB1 = B1 * B1 * B1;
 constexpr int BF = 4 * TS + 1;         // fine P2 box side of a coarse brick (transfers)
 
-// Operator selection for the fused Stokes element kernel.
-enum { F_A = 1, F_BT = 2, F_B = 4, F_C = 8, F_CT = 16 };
+// Operator selection for the fused element kernel (F_M: P1 mass with weight 1/eta).
+enum { F_A = 1, F_BT = 2, F_B = 4, F_C = 8, F_CT = 16, F_M = 32 };
 // Boundary handling: bit 0 project the input velocity, bit 1 the output.
 enum { BCM_IN = 1, BCM_OUT = 2 };
 // BC action per node class.
 enum { ACT_NONE = 0, ACT_DIR = 1, ACT_FS = 2 };
+
+// Plane-sweep tables of a level (see mesh.hpp, Sweep) and gather lists.
+struct SweepDev {
+  int nstrips, cap2, cap1, nsh2, nsh1;
+  const int* strip;    // j0, j1 per strip
+  const int2* plist2;  // (packed I | J<<10 | K<<20, slot or -1)
+  const int* poff2;    // per strip: m2 + 2 offsets
+  const int2* plist1;
+  const int* poff1;    // per strip: n + 2 offsets
+  const int* elist;    // packed type | px<<3 | py<<13
+  const int* eoff;     // per strip: n + 1 offsets
+};
+struct GatherDev {
+  int nnodes;
+  const uint32_t* node;
+  const int* ptr;
+  const int* slot;
+};
 
 struct LevelDev {
   int n;                  // P1 lattice side 2^L (P2 side 2n)
@@ -35,6 +53,10 @@ struct LevelDev {
   const uint8_t* bact;    // 16 per macro: BC action by nonzero-weight mask
   const uint8_t* own;     // 16 per macro: ownership by nonzero-weight mask
   const int* tiles;       // 3 ints per brick origin
+  SweepDev sw;
+  GatherDev g2, g1;
+  int elemwise;           // 1: element-parallel kernel (coarse levels)
+  const int* eall;        // all micro-tets of a macro: type | px<<3 | py<<13 | pz<<23
 };
 
 // Boundary node lists of a level (for vector projections).
@@ -47,13 +69,18 @@ struct BcDev {
 };
 
 // ---- launch wrappers (defined in kernels.hip) --------------------------------
+// Fused plane-sweep apply; sl2 / sl1 are the slot buffers of the level
+// (3 * nmacro * nsh2 and nmacro * nsh1 values).  Outputs are fully written
+// (no zero fill needed); bcmode & BCM_OUT projects the velocity output.
 template <typename R>
-void launch_stokes(int flags, const LevelDev& L, const R* u, const R* p, const R* eta,
-                   const R* lnrho, R* yu, R* yp, int bcmode, hipStream_t s);
+void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, const R* p, const R* eta,
+                   const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s);
+// LDS bytes of the sweep kernel for a flag set
+size_t sweep_lds_bytes(int flags, int cap2, int cap1, int real_bytes);
 template <typename R>
 void launch_diag(const LevelDev& L, const R* eta, R* d, hipStream_t s);
 template <typename R>
-void launch_mass(const LevelDev& L, const R* eta, const R* p, R* y, hipStream_t s);
+void launch_mass_bricks(const LevelDev& L, const R* eta, const R* p, R* y, hipStream_t s);
 void launch_mass_diag(const LevelDev& L, const double* eta, double* y, hipStream_t s);
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s);
 void launch_gradient(const LevelDev& L, const double* eta, const double* u, const double* lam,
@@ -79,9 +106,25 @@ template <typename R> void vinvert(const R* d, R* y, long long n, hipStream_t s)
 void vexp(const double* x, double* y, long long n, hipStream_t s);
 // Chebyshev helpers (see solver): d = c1 * Dinv .* r  + c2 * d
 template <typename R> void vcheb_dir(const R* dinv, const R* r, R c1, R c2, R* d, long long n, hipStream_t s);
+// r = b - t (t nullable: r = b); d = c1 dinv .* r
+template <typename R> void vcheb_start(const R* b, const R* t, const R* dinv, R c1, R* r, R* d, long long n, hipStream_t s);
+// r -= t; x += d; d = c1 dinv .* r + c2 d
+template <typename R> void vcheb_step(const R* t, const R* dinv, R c1, R c2, R* r, R* x, R* d, long long n, hipStream_t s);
+template <typename R> void vsub(const R* b, const R* t, R* r, long long n, hipStream_t s);   // r = b - t
 // Deterministic two-stage dot product accumulated in FP64; result to device *out.
 template <typename R> void vdot(const R* x, const R* y, long long n, double* partial, double* out, hipStream_t s);
 void vsum_partials(double* partial, int np, double* out, hipStream_t s);
 constexpr int DOT_BLOCKS = 1024;
+// device-resident Jacobi CG pieces (scalars in sc[]: see kernels.hip)
+enum { CGS_RZ = 0, CGS_RR, CGS_THR, CGS_DONE, CGS_IT, CGS_ALPHA, CGS_BETA, CGS_N };
+template <typename R>
+void cg_init(const R* r, const R* dinv, R* z, long long n, double tol, double* part, double* sc, hipStream_t s);
+template <typename R>
+void cg_alpha(const R* p, const R* q, long long n, double* part, double* sc, hipStream_t s);
+template <typename R>
+void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long long n, double* part, double* sc,
+               hipStream_t s);
+template <typename R>
+void cg_pupdate(const R* z, R* p, long long n, const double* sc, hipStream_t s);
 
 }  // namespace stk

@@ -61,9 +61,11 @@ __constant__ int c_tlinv[6][3][3] = {
 #define EV1(e) ((e) == 0 ? 1 : ((e) == 1 ? 2 : ((e) == 2 ? 3 : ((e) == 3 ? 2 : 3))))
 __host__ __device__ constexpr int eidx(int i, int j) {
   // node index (4..9) of the edge joining vertices i != j
-  return (i > j) ? eidx(j, i)
-                 : (i == 0 ? 3 + j : (i == 1 ? 5 + j : 9));
+  return (i < j ? i : j) == 0 ? 3 + (i < j ? j : i) : ((i < j ? i : j) == 1 ? 5 + (i < j ? j : i) : 9);
 }
+static_assert(eidx(0, 1) == 4 && eidx(2, 0) == 5 && eidx(0, 3) == 6 && eidx(2, 1) == 7 && eidx(1, 3) == 8 &&
+                  eidx(3, 2) == 9,
+              "edge numbering");
 
 template <typename R> __device__ __forceinline__ const R* geo_of(const LevelDev& L);
 template <> __device__ __forceinline__ const double* geo_of<double>(const LevelDev& L) { return L.geo; }
@@ -72,17 +74,33 @@ template <typename R> __device__ __forceinline__ const R* tinv_of(const LevelDev
 template <> __device__ __forceinline__ const double* tinv_of<double>(const LevelDev& L) { return L.tinv; }
 template <> __device__ __forceinline__ const float* tinv_of<float>(const LevelDev& L) { return L.tinvf; }
 
-__device__ __forceinline__ long long tetc(long long s) { return (s + 1) * (s + 2) * (s + 3) / 6; }
+// 32-bit lattice arithmetic (side m <= 256: all products fit)
+__device__ __forceinline__ int tetc(int s) { return s < 0 ? 0 : (s + 1) * (s + 2) * (s + 3) / 6; }
 __device__ __forceinline__ int lloc(int I, int J, int K, int m) {
-  int s = m - K;
-  return (int)(tetc(m) - tetc(s) + (long long)J * (s + 1) - (long long)J * (J - 1) / 2 + I);
+  const int s = m - K;
+  return tetc(m) - tetc(s) + J * (s + 1) - ((J * (J - 1)) >> 1) + I;
 }
 __device__ __forceinline__ int wmask(int I, int J, int K, int m) {
   return ((m - I - J - K) > 0) | ((I > 0) << 1) | ((J > 0) << 2) | ((K > 0) << 3);
 }
 
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
+// reciprocal and reciprocal square root: hardware approximation refined by
+// Newton steps (two in FP64, giving full double accuracy)
+__device__ __forceinline__ double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <typename R> __device__ __forceinline__ void ldsadd(R* p, R v) { unsafeAtomicAdd(p, v); }
 template <typename R> __device__ __forceinline__ void gadd(R* p, R v) { unsafeAtomicAdd(p, v); }
@@ -126,9 +144,9 @@ struct QGeo {
       d[2] = xq[2] * ri;
       R s = G[12] * xq[0] + G[13] * xq[1] + G[14] * xq[2] + G[15];
       R alpha = s * ri;
-      ia = R(1) / alpha;
+      ia = rcp(alpha);
       R gd = G[12] * d[0] + G[13] * d[1] + G[14] * d[2];
-      R igd = R(1) / gd;
+      R igd = rcp(gd);
 #pragma unroll
       for (int k = 0; k < 3; ++k) h[k] = (d[k] - G[12 + k] * ia) * igd;
       W = wdetF * alpha * alpha * gd;
@@ -196,118 +214,44 @@ __device__ __forceinline__ int type_limit(int type, int n) {
 }
 
 // ---- fused Stokes element kernel -------------------------------------------
+// Per-element state of the fused kernel.  The quadrature point is a template
+// parameter so that every register array is indexed with constants.
 template <typename R, bool BLEND, int FL>
-__global__ __launch_bounds__(384) void k_stokes(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
-                                                const R* __restrict__ eta, const R* __restrict__ lnrho,
-                                                R* __restrict__ yu, R* __restrict__ yp, int bcmode) {
-  constexpr bool DA = FL & F_A, DBT = FL & F_BT, DB = FL & F_B, DC = FL & F_C, DCT = FL & F_CT;
-  constexpr bool NU = DA || DB || DC;
-  constexpr bool NP = DBT || DCT;
-  constexpr bool OU = DA || DBT || DCT;
-  constexpr bool OP = DB || DC;
-  constexpr bool NR = DC || DCT;
-  constexpr bool NEED_G = DA || DB;            // physical gradient of u
-  __shared__ R sx[NU ? 3 * NB2 : 1];
-  __shared__ R sy[OU ? 3 * NB2 : 1];
-  __shared__ R seta[DA ? NB1 : 1];
-  __shared__ R sp[NP ? NB1 : 1];
-  __shared__ R syp[OP ? NB1 : 1];
-  __shared__ R srho[NR ? NB1 : 1];
+struct StokesElem {
+  static constexpr bool DA = FL & F_A, DBT = FL & F_BT, DB = FL & F_B, DC = FL & F_C, DCT = FL & F_CT,
+                        DM = FL & F_M;
+  static constexpr bool NU = DA || DB || DC;
+  static constexpr bool NP = DBT || DCT || DM;
+  static constexpr bool NE = DA || DM;
+  static constexpr bool OU = DA || DBT || DCT;
+  static constexpr bool OP = DB || DC || DM;
+  static constexpr bool NR = DC || DCT;
+  static constexpr bool NEED_G = DA || DB;
+  R gl[3][3], wdetF, xv[4][3], xs[3];
+  R U[3][10], Ev[3][4], base[3][4];
+  R et[4], pp[4], set, spp, grr[3];
+  R Sacc[3][4], Dacc[3][4], Eacc[3][6];
+  R SV[3], VQ[3][4], SP, DP[4];
 
-  const int tile = blockIdx.x % L.ntiles;
-  const int mac = blockIdx.x / L.ntiles;
-  const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
-  const int n = L.n, m2 = 2 * L.n;
-  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
-  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
-  const R* G = geo_of<R>(L) + (size_t)mac * 16;
-  const uint8_t* bact = L.bact + (size_t)mac * 16;
-  const size_t N2 = (size_t)L.n2;
-
-  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
-    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
-    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
-    if (NU) {
-      R v0 = 0, v1 = 0, v2 = 0;
-      if (I + J + K <= m2) {
-        const size_t g = l2[lloc(I, J, K, m2)];
-        v0 = u[g];
-        v1 = u[g + N2];
-        v2 = u[g + 2 * N2];
-        if (bcmode & BCM_IN) bc_project<R>(bact[wmask(I, J, K, m2)], G, I, J, K, m2, v0, v1, v2);
-      }
-      sx[i] = v0;
-      sx[NB2 + i] = v1;
-      sx[2 * NB2 + i] = v2;
-    }
-    if (OU) {
-      sy[i] = 0;
-      sy[NB2 + i] = 0;
-      sy[2 * NB2 + i] = 0;
-    }
-  }
-  if (DA || NP || OP || NR) {
-    for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
-      const int lx = i % B1, ly = (i / B1) % B1, lz = i / (B1 * B1);
-      const int I = ox + lx, J = oy + ly, K = oz + lz;
-      const bool in = I + J + K <= n;
-      const size_t g = in ? l1[lloc(I, J, K, n)] : 0;
-      if (DA) seta[i] = in ? eta[g] : R(0);
-      if (NP) sp[i] = in ? p[g] : R(0);
-      if (NR) srho[i] = in ? lnrho[g] : R(0);
-      if (OP) syp[i] = 0;
-    }
-  }
-  __syncthreads();
-
-  const int type = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
-  const int px = ox + cx, py = oy + cy, pz = oz + cz;
-  if (px + py + pz <= type_limit(type, n)) {
-    ElemIdx e;
-    elem_indices(type, cx, cy, cz, e);
-    const R* TI = tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10;
-    R gl[3][3];
+  // fu(c, a): velocity component c at local P2 node a;  f1(v, &eta, &p, &rho): P1 values at vertex v
+  template <class FU, class F1>
+  __device__ __forceinline__ void load(const R* TI, const R* G, int type, int px, int py, int pz, int n, FU fu,
+                                       F1 f1) {
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int k = 0; k < 3; ++k) gl[r][k] = TI[3 * r + k];
-    const R wdetF = R(QW) * TI[9];
-    R xv[4][3];
-    if (BLEND) elem_vertices<R>(G, type, px, py, pz, n, xv);
-    R xs[3] = {0, 0, 0};
+    wdetF = R(QW) * TI[9];
     if (BLEND) {
+      elem_vertices<R>(G, type, px, py, pz, n, xv);
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) xs[k] += xv[v][k];
+      for (int k = 0; k < 3; ++k) xs[k] = xv[0][k] + xv[1][k] + xv[2][k] + xv[3][k];
     }
-    R U[3][10];
     if (NU) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int a = 0; a < 10; ++a) U[c][a] = sx[c * NB2 + e.n2i[a]];
-    }
-    R et[4], pp[4], rho[4];
-    R set = 0, spp = 0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if (DA) { et[v] = seta[e.n1i[v]]; set += et[v]; }
-      if (NP) { pp[v] = sp[e.n1i[v]]; spp += pp[v]; }
-      if (NR) rho[v] = srho[e.n1i[v]];
-    }
-    // gradient of ln rho_h in reference coordinates (constant per element)
-    R grr[3] = {0, 0, 0};
-    if (NR) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        grr[k] = (rho[1] - rho[0]) * gl[0][k] + (rho[2] - rho[0]) * gl[1][k] + (rho[3] - rho[0]) * gl[2][k];
-    }
-    // per-component sums of edge values at each vertex
-    R Ev[3][4], base[3][4];
-    if (NU) {
+        for (int a = 0; a < 10; ++a) U[c][a] = fu(c, a);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Ev[c][0] = U[c][4] + U[c][5] + U[c][6];
@@ -318,9 +262,22 @@ __global__ __launch_bounds__(384) void k_stokes(LevelDev L, const R* __restrict_
         for (int i = 0; i < 4; ++i) base[c][i] = R(C1) * U[c][i] + R(4.0 * QB) * Ev[c][i];
       }
     }
-    R Sacc[3][4], Dacc[3][4], Eacc[3][6];
-    R SV[3] = {0, 0, 0}, VQ[3][4];
-    R SP = 0, DP[4];
+    set = 0;
+    spp = 0;
+    R rho[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      R ev = 0, pv = 0, rv = 0;
+      f1(v, ev, pv, rv);
+      if (NE) { et[v] = ev; set += ev; }
+      if (NP) { pp[v] = pv; spp += pv; }
+      if (NR) rho[v] = rv;
+    }
+    if (NR) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        grr[k] = (rho[1] - rho[0]) * gl[0][k] + (rho[2] - rho[0]) * gl[1][k] + (rho[3] - rho[0]) * gl[2][k];
+    }
     if (OU) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -328,165 +285,411 @@ __global__ __launch_bounds__(384) void k_stokes(LevelDev L, const R* __restrict_
         for (int i = 0; i < 4; ++i) Sacc[c][i] = 0;
 #pragma unroll
         for (int k = 0; k < 6; ++k) Eacc[c][k] = 0;
+        SV[c] = 0;
       }
     }
+    SP = 0;
+  }
+
+  template <int q>
+  __device__ __forceinline__ void qp(const R* G) {
+    R xq[3];
+    if (BLEND) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      R xq[3];
-      if (BLEND) {
+      for (int k = 0; k < 3; ++k) xq[k] = R(QB) * xs[k] + R(QA - QB) * xv[q][k];
+    }
+    QGeo<R, BLEND> geo;
+    geo.eval(G, xq, wdetF);
+    const R W = geo.W;
+    // physical gradients of the barycentric coordinates 1..3: J_B^{-T} grad~ lambda_i
+    R Lg[3][3];
+    if (NEED_G || DA || DBT) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) xq[k] = R(QB) * xs[k] + R(QA - QB) * xv[q][k];
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Lg[i][k] = gl[i][k];
+        geo.JinvT(Lg[i]);
       }
-      QGeo<R, BLEND> geo;
-      geo.eval(G, xq, wdetF);
-      const R W = geo.W;
-      R Gm[3][3];
-      if (NEED_G) {
+    }
+    R Gm[3][3];
+    if (NEED_G) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R g4[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g4[i] = base[c][i] + R(KAP) * (i == q ? U[c][i] : U[c][eidx(i, q)]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          Gm[c][k] = (g4[1] - g4[0]) * Lg[0][k] + (g4[2] - g4[0]) * Lg[1][k] + (g4[3] - g4[0]) * Lg[2][k];
+      }
+    }
+    R pq = 0;
+    if (NP) pq = R(QB) * spp + R(QA - QB) * pp[q];
+    if (DA || DBT) {
+      R S[3][3];
+      if (DA) {
+        const R e2 = R(2) * (R(QB) * set + R(QA - QB) * et[q]) * W;
+        const R tr3 = (Gm[0][0] + Gm[1][1] + Gm[2][2]) * R(1.0 / 3.0);
+        S[0][0] = e2 * (Gm[0][0] - tr3);
+        S[1][1] = e2 * (Gm[1][1] - tr3);
+        S[2][2] = e2 * (Gm[2][2] - tr3);
+        S[0][1] = S[1][0] = R(0.5) * e2 * (Gm[0][1] + Gm[1][0]);
+        S[0][2] = S[2][0] = R(0.5) * e2 * (Gm[0][2] + Gm[2][0]);
+        S[1][2] = S[2][1] = R(0.5) * e2 * (Gm[1][2] + Gm[2][1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) S[c][k] = 0;
+      }
+      if (DBT) {
+        const R wp = W * pq;
+        S[0][0] -= wp;
+        S[1][1] -= wp;
+        S[2][2] -= wp;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R t1 = S[c][0] * Lg[0][0] + S[c][1] * Lg[0][1] + S[c][2] * Lg[0][2];
+        const R t2 = S[c][0] * Lg[1][0] + S[c][1] * Lg[1][1] + S[c][2] * Lg[1][2];
+        const R t3 = S[c][0] * Lg[2][0] + S[c][1] * Lg[2][1] + S[c][2] * Lg[2][2];
+        const R t[4] = {-(t1 + t2 + t3), t1, t2, t3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          Sacc[c][i] += t[i];
+          if (i == q) Dacc[c][i] = t[i];
+          else Eacc[c][eidx(i, q) - 4] += t[i];
+        }
+      }
+    }
+    if (NR) {
+      R gr[3] = {grr[0], grr[1], grr[2]};
+      geo.JinvT(gr);
+      if (DC) {
+        R val = DB ? (Gm[0][0] + Gm[1][1] + Gm[2][2]) : R(0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          R g4[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) g4[i] = base[c][i] + R(KAP) * (i == q ? U[c][i] : U[c][eidx(i, q)]);
-#pragma unroll
-          for (int k = 0; k < 3; ++k)
-            Gm[c][k] = (g4[1] - g4[0]) * gl[0][k] + (g4[2] - g4[0]) * gl[1][k] + (g4[3] - g4[0]) * gl[2][k];
-          geo.rowJinv(Gm[c]);
+          const R sv = U[c][0] + U[c][1] + U[c][2] + U[c][3];
+          const R se = U[c][4] + U[c][5] + U[c][6] + U[c][7] + U[c][8] + U[c][9];
+          const R uq = R(NV_OTH) * sv + R(NV_OWN - NV_OTH) * U[c][q] + R(NE_OTH) * se + R(NE_OWN - NE_OTH) * Ev[c][q];
+          val += gr[c] * uq;
         }
-      }
-      R pq = 0;
-      if (NP) pq = R(QB) * spp + R(QA - QB) * pp[q];
-      if (DA || DBT) {
-        R S[3][3];
-        if (DA) {
-          const R e2 = R(2) * (R(QB) * set + R(QA - QB) * et[q]) * W;
-          const R tr3 = (Gm[0][0] + Gm[1][1] + Gm[2][2]) * R(1.0 / 3.0);
-          S[0][0] = e2 * (Gm[0][0] - tr3);
-          S[1][1] = e2 * (Gm[1][1] - tr3);
-          S[2][2] = e2 * (Gm[2][2] - tr3);
-          S[0][1] = S[1][0] = R(0.5) * e2 * (Gm[0][1] + Gm[1][0]);
-          S[0][2] = S[2][0] = R(0.5) * e2 * (Gm[0][2] + Gm[2][0]);
-          S[1][2] = S[2][1] = R(0.5) * e2 * (Gm[1][2] + Gm[2][1]);
-        } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) S[c][k] = 0;
-        }
-        if (DBT) {
-          const R wp = W * pq;
-          S[0][0] -= wp;
-          S[1][1] -= wp;
-          S[2][2] -= wp;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          R T[3] = {S[c][0], S[c][1], S[c][2]};
-          geo.Jinv(T);
-          R t1 = T[0] * gl[0][0] + T[1] * gl[0][1] + T[2] * gl[0][2];
-          R t2 = T[0] * gl[1][0] + T[1] * gl[1][1] + T[2] * gl[1][2];
-          R t3 = T[0] * gl[2][0] + T[1] * gl[2][1] + T[2] * gl[2][2];
-          R t[4] = {-(t1 + t2 + t3), t1, t2, t3};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            Sacc[c][i] += t[i];
-            if (i == q) Dacc[c][i] = t[i];
-            else Eacc[c][eidx(i, q) - 4] += t[i];
-          }
-        }
-      }
-      if (NR) {
-        // grad ln rho_h (physical) = J_B^{-T} grr
-        R gr[3] = {grr[0], grr[1], grr[2]};
-        geo.JinvT(gr);
-        if (DC) {
-          R val = DB ? (Gm[0][0] + Gm[1][1] + Gm[2][2]) : R(0);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            R sv = U[c][0] + U[c][1] + U[c][2] + U[c][3];
-            R se = U[c][4] + U[c][5] + U[c][6] + U[c][7] + U[c][8] + U[c][9];
-            R uq = R(NV_OTH) * sv + R(NV_OWN - NV_OTH) * U[c][q] + R(NE_OTH) * se + R(NE_OWN - NE_OTH) * Ev[c][q];
-            val += gr[c] * uq;
-          }
-          SP += W * val;
-          DP[q] = W * val;
-        }
-        if (DCT) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            R v = -W * pq * gr[c];
-            SV[c] += v;
-            VQ[c][q] = v;
-          }
-        }
-      }
-      if (DB && !DC) {
-        R val = Gm[0][0] + Gm[1][1] + Gm[2][2];
         SP += W * val;
         DP[q] = W * val;
       }
+      if (DCT) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const R v = -W * pq * gr[c];
+          SV[c] += v;
+          VQ[c][q] = v;
+        }
+      }
     }
+    if (DB && !DC) {
+      const R val = Gm[0][0] + Gm[1][1] + Gm[2][2];
+      SP += W * val;
+      DP[q] = W * val;
+    }
+    if (DM) {
+      const R v = W * pq / (R(QB) * set + R(QA - QB) * et[q]);
+      SP += v;
+      DP[q] = v;
+    }
+  }
+
+  // fo(c, a, value): add to velocity output; f1o(v, value): add to P1 output
+  template <class FO, class F1O>
+  __device__ __forceinline__ void store(FO fo, F1O f1o) {
     if (OU) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        R* yc = sy + c * NB2;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           R y = (DA || DBT) ? (R(C1) * Sacc[c][i] + R(KAP) * Dacc[c][i]) : R(0);
           if (DCT) y += R(NV_OTH) * SV[c] + R(NV_OWN - NV_OTH) * VQ[c][i];
-          ldsadd(yc + e.n2i[i], y);
+          fo(c, i, y);
         }
 #pragma unroll
         for (int ed = 0; ed < 6; ++ed) {
           const int i = EV0(ed), j = EV1(ed);
           R y = (DA || DBT) ? (R(4.0 * QB) * (Sacc[c][i] + Sacc[c][j]) + R(KAP) * Eacc[c][ed]) : R(0);
           if (DCT) y += R(NE_OTH) * SV[c] + R(NE_OWN - NE_OTH) * (VQ[c][i] + VQ[c][j]);
-          ldsadd(yc + e.n2i[4 + ed], y);
+          fo(c, 4 + ed, y);
         }
       }
     }
     if (OP) {
+      const R sg = DM ? R(1) : R(-1);   // B and C carry a minus sign
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ldsadd(syp + e.n1i[i], -(R(QB) * SP + R(QA - QB) * DP[i]));
+      for (int i = 0; i < 4; ++i) f1o(i, sg * (R(QB) * SP + R(QA - QB) * DP[i]));
     }
   }
+};
+
+
+// ---- plane-sweep apply --------------------------------------------------------
+// One workgroup sweeps one (macro, strip) along the lattice direction of the
+// fourth macro vertex, layer k = 0 .. of micro-tets at a time.  LDS holds a ring
+// of three P2 planes (2k, 2k+1, 2k+2) and two P1 planes (k, k+1) of inputs and
+// accumulators; after layer k, P2 planes 2k, 2k+1 and P1 plane k are complete
+// and are written out while the next planes are staged into their ring slots.
+// Nodes that only this workgroup touches get plain stores; shared nodes
+// (macro boundary, strip boundary rows) go to slots summed by k_gather.
+__device__ __forceinline__ int ppos(int K, int J, int I, int m, int a) {
+  // position of (I, J) in the strip part (rows J >= a) of plane K of a lattice of side m
+  const int s = m - K;
+  return (J - a) * (s + 1) - ((J * (J - 1) - a * (a - 1)) >> 1) + I;
+}
+
+template <typename R, bool BLEND, int FL>
+__global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
+                                               const R* __restrict__ eta, const R* __restrict__ lnrho,
+                                               R* __restrict__ yu, R* __restrict__ yp, R* __restrict__ sl2,
+                                               R* __restrict__ sl1, int bcmode) {
+  using E = StokesElem<R, BLEND, FL>;
+  constexpr bool NU = E::NU, NP = E::NP, OU = E::OU, OP = E::OP, NR = E::NR, NE = E::NE;
+  // accumulators are FP64 for both precisions: LDS FP64 atomic adds are far
+  // faster than FP32 ones on this hardware (and more accurate)
+  using Acc = double;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const SweepDev& S = L.sw;
+  const int cap2 = S.cap2, cap1 = S.cap1;
+  const int CS = 3 * cap2;   // component stride of the P2 ring
+  Acc* sy = reinterpret_cast<Acc*>(smem_raw);
+  Acc* syp = sy + (OU ? 3 * CS : 0);
+  R* sx = reinterpret_cast<R*>(syp + (OP ? 2 * cap1 : 0));
+  R* seta = sx + (NU ? 3 * CS : 0);
+  R* sp = seta + (NE ? 2 * cap1 : 0);
+  R* srho = sp + (NP ? 2 * cap1 : 0);
+
+  const int strip = blockIdx.x % S.nstrips;
+  const int mac = blockIdx.x / S.nstrips;
+  const int j0 = S.strip[2 * strip];
+  const int n = L.n, m2 = 2 * n;
+  const int* poff2 = S.poff2 + strip * (m2 + 2);
+  const int* poff1 = S.poff1 + strip * (n + 2);
+  const int* eoff = S.eoff + strip * (n + 1);
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const R* G = geo_of<R>(L) + (size_t)mac * 16;
+  const uint8_t* bact = L.bact + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+  const size_t SS2 = (size_t)L.nmacro * S.nsh2;   // slot component stride
+  R* ms2 = sl2 + (size_t)mac * S.nsh2;
+  R* ms1 = sl1 + (size_t)mac * S.nsh1;
+  const int tid = threadIdx.x, bs = blockDim.x;
+
+  auto flush2 = [&](int K, int t) {
+    const int2 en = S.plist2[poff2[K] + t];
+    const int pos = (K % 3) * cap2 + t;
+    if (en.y >= 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ms2[en.y + c * SS2] = R(sy[c * CS + pos]);
+    } else {
+      const int I = en.x & 1023, J = (en.x >> 10) & 1023;
+      const size_t g = l2[lloc(I, J, K, m2)];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) yu[g + c * N2] = R(sy[c * CS + pos]);
+    }
+  };
+  auto load2 = [&](int K, int t) {
+    const int2 en = S.plist2[poff2[K] + t];
+    const int pos = (K % 3) * cap2 + t;
+    if (NU) {
+      const int I = en.x & 1023, J = (en.x >> 10) & 1023;
+      const int mask = wmask(I, J, K, m2);
+      const size_t g = l2[lloc(I, J, K, m2)];
+      R v0 = u[g], v1 = u[g + N2], v2 = u[g + 2 * N2];
+      if ((bcmode & BCM_IN) && mask != 15) bc_project<R>(bact[mask], G, I, J, K, m2, v0, v1, v2);
+      sx[pos] = v0;
+      sx[CS + pos] = v1;
+      sx[2 * CS + pos] = v2;
+    }
+    if (OU) {
+      sy[pos] = 0;
+      sy[CS + pos] = 0;
+      sy[2 * CS + pos] = 0;
+    }
+  };
+  auto flush1 = [&](int k, int t) {
+    const int2 en = S.plist1[poff1[k] + t];
+    const int pos = (k & 1) * cap1 + t;
+    if (en.y >= 0) {
+      ms1[en.y] = R(syp[pos]);
+    } else {
+      const int I = en.x & 1023, J = (en.x >> 10) & 1023;
+      yp[l1[lloc(I, J, k, n)]] = R(syp[pos]);
+    }
+  };
+  auto load1 = [&](int k, int t) {
+    const int2 en = S.plist1[poff1[k] + t];
+    const int pos = (k & 1) * cap1 + t;
+    const int I = en.x & 1023, J = (en.x >> 10) & 1023;
+    const size_t g = l1[lloc(I, J, k, n)];
+    if (NE) seta[pos] = eta[g];
+    if (NP) sp[pos] = p[g];
+    if (NR) srho[pos] = lnrho[g];
+    if (OP) syp[pos] = 0;
+  };
+  auto cnt2 = [&](int K) { return K <= m2 ? poff2[K + 1] - poff2[K] : 0; };
+  auto cnt1 = [&](int k) { return k <= n ? poff1[k + 1] - poff1[k] : 0; };
+  constexpr bool P2 = NU || OU;
+  constexpr bool P1 = NE || NP || NR || OP;
+
+  // initial planes
+  if (P2)
+    for (int K = 0; K < 3; ++K)
+      for (int t = tid; t < cnt2(K); t += bs) load2(K, t);
+  if (P1)
+    for (int k = 0; k < 2; ++k)
+      for (int t = tid; t < cnt1(k); t += bs) load1(k, t);
   __syncthreads();
 
-  if (OU) {
-    for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
-      const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
-      const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
-      if (I + J + K > m2) continue;
-      const int mask = wmask(I, J, K, m2);
-      R v0 = sy[i], v1 = sy[NB2 + i], v2 = sy[2 * NB2 + i];
-      if (bcmode & BCM_OUT) {
-        const int act = bact[mask];
-        if (act == ACT_DIR) continue;
-        bc_project<R>(act, G, I, J, K, m2, v0, v1, v2);
+  const int kmax = n - 1 - j0;
+  for (int k = 0; k <= kmax; ++k) {
+    // micro-tets of layer k
+    const int e1 = eoff[k + 1];
+    for (int ei = eoff[k] + tid; ei < e1; ei += bs) {
+      const int pk = S.elist[ei];
+      const int type = pk & 7, px = (pk >> 3) & 1023, py = pk >> 13;
+      ElemIdx e;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], kk = k + c_toff[type][v][2];
+        e.n1i[v] = (kk & 1) * cap1 + ppos(kk, J, I, n, j0);
+        e.n2i[v] = ((2 * kk) % 3) * cap2 + ppos(2 * kk, 2 * J, 2 * I, m2, 2 * j0);
       }
-      const size_t g = l2[lloc(I, J, K, m2)];
-      const bool excl = mask == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
-      if (excl) {
-        yu[g] = v0;
-        yu[g + N2] = v1;
-        yu[g + 2 * N2] = v2;
-      } else {
-        gadd(yu + g, v0);
-        gadd(yu + g + N2, v1);
-        gadd(yu + g + 2 * N2, v2);
+#pragma unroll
+      for (int ed = 0; ed < 6; ++ed) {
+        const int i = EV0(ed), j = EV1(ed);
+        const int I = 2 * px + c_toff[type][i][0] + c_toff[type][j][0];
+        const int J = 2 * py + c_toff[type][i][1] + c_toff[type][j][1];
+        const int K = 2 * k + c_toff[type][i][2] + c_toff[type][j][2];
+        e.n2i[4 + ed] = (K % 3) * cap2 + ppos(K, J, I, m2, 2 * j0);
+      }
+      E el;
+      el.load(
+          tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, G, type, px, py, k, n,
+          [&](int c, int a) { return sx[c * CS + e.n2i[a]]; },
+          [&](int v, R& ev, R& pv, R& rv) {
+            if (NE) ev = seta[e.n1i[v]];
+            if (NP) pv = sp[e.n1i[v]];
+            if (NR) rv = srho[e.n1i[v]];
+          });
+      el.template qp<0>(G);
+      el.template qp<1>(G);
+      el.template qp<2>(G);
+      el.template qp<3>(G);
+      el.store([&](int c, int a, R v) { ldsadd(sy + c * CS + e.n2i[a], Acc(v)); },
+               [&](int v, R val) { ldsadd(syp + e.n1i[v], Acc(val)); });
+    }
+    __syncthreads();
+    // write out completed planes, stage the next ones into the freed slots
+    if (P2) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int Ko = 2 * k + d, Kn = 2 * k + 3 + d;
+        const int co = OU ? cnt2(Ko) : 0, cn = cnt2(Kn);
+        const int cm = co > cn ? co : cn;
+        for (int t = tid; t < cm; t += bs) {
+          if (t < co) flush2(Ko, t);
+          if (t < cn) load2(Kn, t);
+        }
       }
     }
-  }
-  if (OP) {
-    for (int i = threadIdx.x; i < NB1; i += blockDim.x) {
-      const int lx = i % B1, ly = (i / B1) % B1, lz = i / (B1 * B1);
-      const int I = ox + lx, J = oy + ly, K = oz + lz;
-      if (I + J + K > n) continue;
-      const size_t g = l1[lloc(I, J, K, n)];
-      const bool excl = wmask(I, J, K, n) == 15 && lx > 0 && lx < B1 - 1 && ly > 0 && ly < B1 - 1 && lz > 0 && lz < B1 - 1;
-      if (excl) yp[g] = syp[i];
-      else gadd(yp + g, syp[i]);
+    if (P1) {
+      const int co = OP ? cnt1(k) : 0, cn = cnt1(k + 2);
+      const int cm = co > cn ? co : cn;
+      for (int t = tid; t < cm; t += bs) {
+        if (t < co) flush1(k, t);
+        if (t < cn) load1(k + 2, t);
+      }
     }
+    __syncthreads();
   }
+  if (OU)
+    for (int t = tid; t < cnt2(2 * kmax + 2); t += bs) flush2(2 * kmax + 2, t);
+  if (OP)
+    for (int t = tid; t < cnt1(kmax + 1); t += bs) flush1(kmax + 1, t);
+}
+
+// Element-parallel variant for coarse levels (few micro-tets per macro): one
+// thread per micro-tet of the whole mesh, operands gathered from global memory
+// and results added with global atomics into zero-filled outputs.
+template <typename R, bool BLEND, int FL>
+__global__ __launch_bounds__(256) void k_elemwise(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
+                                                  const R* __restrict__ eta, const R* __restrict__ lnrho,
+                                                  R* __restrict__ yu, R* __restrict__ yp, int bcmode) {
+  using E = StokesElem<R, BLEND, FL>;
+  const int n = L.n, m2 = 2 * n;
+  const int ne = n * n * n;
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)ne * L.nmacro) return;
+  const int mac = (int)(gid / ne);
+  const int pk = L.eall[gid - (long long)mac * ne];
+  const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const R* G = geo_of<R>(L) + (size_t)mac * 16;
+  const uint8_t* bact = L.bact + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+  int I2[10], J2[10], K2[10];
+  size_t g2[10], g1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], K = pz + c_toff[type][v][2];
+    g1[v] = l1[lloc(I, J, K, n)];
+    I2[v] = 2 * I;
+    J2[v] = 2 * J;
+    K2[v] = 2 * K;
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    I2[4 + ed] = (I2[i] + I2[j]) >> 1;
+    J2[4 + ed] = (J2[i] + J2[j]) >> 1;
+    K2[4 + ed] = (K2[i] + K2[j]) >> 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+  E el;
+  el.load(
+      tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, G, type, px, py, pz, n,
+      [&](int c, int a) {
+        R v[3] = {u[g2[a]], u[g2[a] + N2], u[g2[a] + 2 * N2]};
+        if (bcmode & BCM_IN) bc_project<R>(bact[wmask(I2[a], J2[a], K2[a], m2)], G, I2[a], J2[a], K2[a], m2, v[0], v[1], v[2]);
+        return v[c];
+      },
+      [&](int v, R& ev, R& pv, R& rv) {
+        if (E::NE) ev = eta[g1[v]];
+        if (E::NP) pv = p[g1[v]];
+        if (E::NR) rv = lnrho[g1[v]];
+      });
+  el.template qp<0>(G);
+  el.template qp<1>(G);
+  el.template qp<2>(G);
+  el.template qp<3>(G);
+  el.store([&](int c, int a, R v) { gadd(yu + g2[a] + c * N2, v); }, [&](int v, R val) { gadd(yp + g1[v], val); });
+}
+
+// sum the slots of shared nodes: P2 vectors (3 components) or P1 scalars
+template <typename R, int NC>
+__global__ void k_gather(GatherDev gd, const R* __restrict__ sl, size_t sstride, R* __restrict__ y, size_t ystride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= gd.nnodes) return;
+  const int b = gd.ptr[i], e = gd.ptr[i + 1];
+  R v[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] = 0;
+  for (int k = b; k < e; ++k) {
+    const size_t s = (size_t)gd.slot[k];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] += sl[s + c * sstride];
+  }
+  const size_t g = gd.node[i];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) y[g + c * ystride] = v[c];
 }
 
 // ---- diag(A) (no free-slip projection, Sec. 5.2.2) ---------------------------
@@ -908,7 +1111,7 @@ __device__ __forceinline__ void p2w8(const int q[4], int w[10]) {
 template <typename R, int MODE>   // MODE 0 prolongation, 1 restriction
 __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, const R* __restrict__ in,
                                                   R* __restrict__ out, int bcmode) {
-  __shared__ R sc[3 * NB2];
+  __shared__ double sc[3 * NB2];   // FP64 staging / accumulation (fast LDS atomics)
   const int tile = blockIdx.x % Lc.ntiles;
   const int mac = blockIdx.x / Lc.ntiles;
   const int ox = Lc.tiles[3 * tile], oy = Lc.tiles[3 * tile + 1], oz = Lc.tiles[3 * tile + 2];
@@ -957,7 +1160,7 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
         R s = 0;
 #pragma unroll
         for (int a = 0; a < 10; ++a)
-          if (w[a]) s += R(w[a]) * sc[c * NB2 + e.n2i[a]];
+          if (w[a]) s += R(w[a]) * R(sc[c * NB2 + e.n2i[a]]);
         v[c] = s * R(0.125);
       }
       if (bcmode & BCM_OUT) {
@@ -974,10 +1177,10 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
 #pragma unroll
       for (int a = 0; a < 10; ++a) {
         if (!w[a]) continue;
-        const R f = R(w[a]) * R(0.125);
-        ldsadd(sc + e.n2i[a], f * v0);
-        ldsadd(sc + NB2 + e.n2i[a], f * v1);
-        ldsadd(sc + 2 * NB2 + e.n2i[a], f * v2);
+        const double f = w[a] * 0.125;
+        ldsadd(sc + e.n2i[a], f * double(v0));
+        ldsadd(sc + NB2 + e.n2i[a], f * double(v1));
+        ldsadd(sc + 2 * NB2 + e.n2i[a], f * double(v2));
       }
     }
   }
@@ -988,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
       const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
       if (I + J + K > mc2) continue;
       const int mask = wmask(I, J, K, mc2);
-      R v0 = sc[i], v1 = sc[NB2 + i], v2 = sc[2 * NB2 + i];
+      R v0 = R(sc[i]), v1 = R(sc[NB2 + i]), v2 = R(sc[2 * NB2 + i]);
       if (bcmode & BCM_OUT) {
         const int act = bact[mask];
         if (act == ACT_DIR) continue;
@@ -1085,6 +1288,33 @@ __global__ void k_cheb_dir(const R* __restrict__ dinv, const R* __restrict__ r, 
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     d[i] = (c2 == R(0)) ? c1 * dinv[i] * r[i] : c1 * dinv[i] * r[i] + c2 * d[i];
 }
+// Chebyshev smoother pieces (fused vector updates)
+template <typename R>
+__global__ void k_cheb_start(const R* __restrict__ b, const R* __restrict__ t, const R* __restrict__ dinv, R c1,
+                             R* __restrict__ r, R* __restrict__ d, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R ri = t ? b[i] - t[i] : b[i];
+    r[i] = ri;
+    d[i] = c1 * dinv[i] * ri;
+  }
+}
+template <typename R>
+__global__ void k_cheb_step(const R* __restrict__ t, const R* __restrict__ dinv, R c1, R c2, R* __restrict__ r,
+                            R* __restrict__ x, R* __restrict__ d, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R ri = r[i] - t[i];
+    const R di = d[i];
+    r[i] = ri;
+    x[i] += di;
+    d[i] = c1 * dinv[i] * ri + c2 * di;
+  }
+}
+template <typename R>
+__global__ void k_sub(const R* __restrict__ b, const R* __restrict__ t, R* __restrict__ r, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    r[i] = b[i] - t[i];
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_dot(const R* __restrict__ x, const R* __restrict__ y, long long n, double* partial) {
   __shared__ double red[256];
@@ -1112,6 +1342,188 @@ __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ partial,
   if (threadIdx.x == 0) *out = red[0];
 }
 
+static inline int vgrid_fwd(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// ---- device-resident Jacobi-preconditioned CG ----------------------------------
+// Scalars live in a small device array so that iterations need no host round
+// trip; once converged (|r|^2 <= thr) every update kernel returns early.
+enum { CG_RZ = 0, CG_RR, CG_THR, CG_DONE, CG_IT, CG_ALPHA, CG_BETA, CG_NS };
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_init(const R* __restrict__ r, const R* __restrict__ dinv,
+                                                 R* __restrict__ z, long long n, double* part) {
+  __shared__ double red[2][256];
+  double a = 0, b = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R zi = dinv[i] * r[i];
+    z[i] = zi;
+    a += (double)r[i] * (double)r[i];
+    b += (double)r[i] * (double)zi;
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = red[0][0];
+    part[DOT_BLOCKS + blockIdx.x] = red[1][0];
+  }
+}
+
+__device__ __forceinline__ double block_sum(const double* part, int np, double* red) {
+  double s = 0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double v = red[0];
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_cg_init_fin(const double* part, int np, double tol2, double* sc) {
+  __shared__ double red[256];
+  const double rr = block_sum(part, np, red);
+  const double rz = block_sum(part + DOT_BLOCKS, np, red);
+  if (threadIdx.x == 0) {
+    sc[CG_RR] = rr;
+    sc[CG_RZ] = rz;
+    sc[CG_THR] = tol2 * rr;
+    sc[CG_DONE] = (rr == 0.0) ? 1.0 : 0.0;
+    sc[CG_IT] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cg_alpha(const double* part, int np, double* sc) {
+  if (sc[CG_DONE] != 0.0) return;
+  __shared__ double red[256];
+  const double pq = block_sum(part, np, red);
+  if (threadIdx.x == 0) sc[CG_ALPHA] = sc[CG_RZ] / pq;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_update(const double* sc, const R* __restrict__ p, const R* __restrict__ q,
+                                                   const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ r,
+                                                   R* __restrict__ z, long long n, double* part) {
+  if (sc[CG_DONE] != 0.0) return;
+  __shared__ double red[2][256];
+  const R alpha = R(sc[CG_ALPHA]);
+  double a = 0, b = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const R ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    const R zi = dinv[i] * ri;
+    z[i] = zi;
+    a += (double)ri * (double)ri;
+    b += (double)ri * (double)zi;
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = red[0][0];
+    part[DOT_BLOCKS + blockIdx.x] = red[1][0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cg_beta(const double* part, int np, double* sc) {
+  if (sc[CG_DONE] != 0.0) return;
+  __shared__ double red[256];
+  const double rr = block_sum(part, np, red);
+  const double rz = block_sum(part + DOT_BLOCKS, np, red);
+  if (threadIdx.x == 0) {
+    sc[CG_IT] += 1.0;
+    sc[CG_RR] = rr;
+    if (rr <= sc[CG_THR]) {
+      sc[CG_DONE] = 1.0;
+    } else {
+      sc[CG_BETA] = rz / sc[CG_RZ];
+      sc[CG_RZ] = rz;
+    }
+  }
+}
+
+template <typename R>
+__global__ void k_cg_p(const double* sc, const R* __restrict__ z, R* __restrict__ p, long long n) {
+  if (sc[CG_DONE] != 0.0) return;
+  const R beta = R(sc[CG_BETA]);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dot_guard(const double* sc, const R* __restrict__ x, const R* __restrict__ y,
+                                                   long long n, double* partial) {
+  if (sc[CG_DONE] != 0.0) return;
+  __shared__ double red[256];
+  double s = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s += (double)x[i] * (double)y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+static inline int redgrid(long long n) {
+  long long g = (n + 255) / 256;
+  return (int)(g < DOT_BLOCKS ? (g < 1 ? 1 : g) : DOT_BLOCKS);
+}
+
+template <typename R>
+void cg_init(const R* r, const R* dinv, R* z, long long n, double tol, double* part, double* sc, hipStream_t s) {
+  const int nb = redgrid(n);
+  hipLaunchKernelGGL((k_cg_init<R>), dim3(nb), dim3(256), 0, s, r, dinv, z, n, part);
+  hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, part, nb, tol * tol, sc);
+}
+template <typename R>
+void cg_alpha(const R* p, const R* q, long long n, double* part, double* sc, hipStream_t s) {
+  const int nb = redgrid(n);
+  hipLaunchKernelGGL((k_dot_guard<R>), dim3(nb), dim3(256), 0, s, sc, p, q, n, part);
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, part, nb, sc);
+}
+template <typename R>
+void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long long n, double* part, double* sc,
+               hipStream_t s) {
+  const int nb = redgrid(n);
+  hipLaunchKernelGGL((k_cg_update<R>), dim3(nb), dim3(256), 0, s, sc, p, q, dinv, x, r, z, n, part);
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, part, nb, sc);
+}
+template <typename R>
+void cg_pupdate(const R* z, R* p, long long n, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_p<R>), dim3(vgrid_fwd(n)), dim3(256), 0, s, sc, z, p, n);
+}
+#define INST_CG(R)                                                                                              \
+  template void cg_init<R>(const R*, const R*, R*, long long, double, double*, double*, hipStream_t);         \
+  template void cg_alpha<R>(const R*, const R*, long long, double*, double*, hipStream_t);                    \
+  template void cg_update<R>(const R*, const R*, const R*, R*, R*, R*, long long, double*, double*, hipStream_t); \
+  template void cg_pupdate<R>(const R*, R*, long long, const double*, hipStream_t);
+
 // ---- launch wrappers ----------------------------------------------------------------
 static inline int vgrid(long long n) {
   long long g = (n + 255) / 256;
@@ -1120,38 +1532,69 @@ static inline int vgrid(long long n) {
   return (int)g;
 }
 
+size_t sweep_lds_bytes(int FL, int cap2, int cap1, int rb) {
+  const bool NU = FL & (F_A | F_B | F_C), OU = FL & (F_A | F_BT | F_CT);
+  const bool NE = FL & (F_A | F_M), NP = FL & (F_BT | F_CT | F_M), NR = FL & (F_C | F_CT), OP = FL & (F_B | F_C | F_M);
+  // FP64 accumulators, inputs in the working precision
+  size_t acc = (OU ? 9 * (size_t)cap2 : 0) + (OP ? 2 * (size_t)cap1 : 0);
+  size_t in = (NU ? 9 * (size_t)cap2 : 0) + 2 * (size_t)cap1 * ((NE ? 1 : 0) + (NP ? 1 : 0) + (NR ? 1 : 0));
+  return acc * 8 + in * rb;
+}
+
 template <typename R, int FL>
 static void stokes_dispatch(const LevelDev& L, const R* u, const R* p, const R* eta, const R* lnrho, R* yu, R* yp,
-                            int bcmode, hipStream_t s) {
-  dim3 grid((unsigned)(L.ntiles * L.nmacro));
+                            R* sl2, R* sl1, int bcmode, hipStream_t s) {
+  if (L.elemwise) {
+    constexpr bool OU = FL & (F_A | F_BT | F_CT), OP = FL & (F_B | F_C | F_M);
+    if (OU) vfill<R>(yu, R(0), 3 * L.n2, s);
+    if (OP) vfill<R>(yp, R(0), L.n1, s);
+    const long long tot = (long long)L.n * L.n * L.n * L.nmacro;
+    dim3 grid((unsigned)((tot + 255) / 256));
+    if (L.blend)
+      hipLaunchKernelGGL((k_elemwise<R, true, FL>), grid, dim3(256), 0, s, L, u, p, eta, lnrho, yu, yp, bcmode);
+    else
+      hipLaunchKernelGGL((k_elemwise<R, false, FL>), grid, dim3(256), 0, s, L, u, p, eta, lnrho, yu, yp, bcmode);
+    return;
+  }
+  dim3 grid((unsigned)(L.sw.nstrips * L.nmacro));
+  const size_t lds = sweep_lds_bytes(FL, L.sw.cap2, L.sw.cap1, sizeof(R));
   if (L.blend)
-    hipLaunchKernelGGL((k_stokes<R, true, FL>), grid, dim3(384), 0, s, L, u, p, eta, lnrho, yu, yp, bcmode);
+    hipLaunchKernelGGL((k_sweep<R, true, FL>), grid, dim3(256), lds, s, L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode);
   else
-    hipLaunchKernelGGL((k_stokes<R, false, FL>), grid, dim3(384), 0, s, L, u, p, eta, lnrho, yu, yp, bcmode);
+    hipLaunchKernelGGL((k_sweep<R, false, FL>), grid, dim3(256), lds, s, L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode);
 }
 
 template <typename R>
-void launch_stokes(int flags, const LevelDev& L, const R* u, const R* p, const R* eta, const R* lnrho, R* yu, R* yp,
-                   int bcmode, hipStream_t s) {
+void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, const R* p, const R* eta,
+                   const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s) {
   switch (flags) {
-    case F_A: stokes_dispatch<R, F_A>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_BT: stokes_dispatch<R, F_BT>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_BT | F_CT: stokes_dispatch<R, F_BT | F_CT>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_B: stokes_dispatch<R, F_B>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_B | F_C: stokes_dispatch<R, F_B | F_C>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_A | F_BT: stokes_dispatch<R, F_A | F_BT>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_A | F_BT | F_B: stokes_dispatch<R, F_A | F_BT | F_B>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_A | F_BT | F_B | F_C: stokes_dispatch<R, F_A | F_BT | F_B | F_C>(L, u, p, eta, lnrho, yu, yp, bcmode, s); break;
-    case F_A | F_BT | F_CT | F_B:
-      stokes_dispatch<R, F_A | F_BT | F_CT | F_B>(L, u, p, eta, lnrho, yu, yp, bcmode, s);
-      break;
-    default: break;
+#define CASE(F) case F: stokes_dispatch<R, F>(L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode, s); break;
+    CASE(F_A)
+    CASE(F_BT)
+    CASE(F_BT | F_CT)
+    CASE(F_B)
+    CASE(F_B | F_C)
+    CASE(F_M)
+    CASE(F_A | F_BT)
+    CASE(F_A | F_BT | F_B)
+    CASE(F_A | F_BT | F_B | F_C)
+    CASE(F_A | F_BT | F_CT | F_B)
+#undef CASE
+    default: return;
   }
+  const bool OU = flags & (F_A | F_BT | F_CT), OP = flags & (F_B | F_C | F_M);
+  if (OU && L.g2.nnodes > 0 && !L.elemwise)
+    hipLaunchKernelGGL((k_gather<R, 3>), dim3((L.g2.nnodes + 255) / 256), dim3(256), 0, s, L.g2, sl2,
+                       (size_t)L.nmacro * L.sw.nsh2, yu, (size_t)L.n2);
+  if (OP && L.g1.nnodes > 0 && !L.elemwise)
+    hipLaunchKernelGGL((k_gather<R, 1>), dim3((L.g1.nnodes + 255) / 256), dim3(256), 0, s, L.g1, sl1,
+                       (size_t)L.nmacro * L.sw.nsh1, yp, (size_t)L.n1);
+  if (OU && (bcmode & BCM_OUT)) launch_project<R>(bc, L.n2, yu, s);
 }
-template void launch_stokes<double>(int, const LevelDev&, const double*, const double*, const double*, const double*,
-                                    double*, double*, int, hipStream_t);
-template void launch_stokes<float>(int, const LevelDev&, const float*, const float*, const float*, const float*, float*,
-                                   float*, int, hipStream_t);
+template void launch_stokes<double>(int, const LevelDev&, const BcDev&, const double*, const double*, const double*,
+                                    const double*, double*, double*, double*, double*, int, hipStream_t);
+template void launch_stokes<float>(int, const LevelDev&, const BcDev&, const float*, const float*, const float*,
+                                   const float*, float*, float*, float*, float*, int, hipStream_t);
 
 template <typename R>
 void launch_diag(const LevelDev& L, const R* eta, R* d, hipStream_t s) {
@@ -1163,13 +1606,13 @@ template void launch_diag<double>(const LevelDev&, const double*, double*, hipSt
 template void launch_diag<float>(const LevelDev&, const float*, float*, hipStream_t);
 
 template <typename R>
-void launch_mass(const LevelDev& L, const R* eta, const R* p, R* y, hipStream_t s) {
+void launch_mass_bricks(const LevelDev& L, const R* eta, const R* p, R* y, hipStream_t s) {
   dim3 grid((unsigned)(L.ntiles * L.nmacro));
   if (L.blend) hipLaunchKernelGGL((k_mass<R, true, false>), grid, dim3(384), 0, s, L, eta, p, y);
   else hipLaunchKernelGGL((k_mass<R, false, false>), grid, dim3(384), 0, s, L, eta, p, y);
 }
-template void launch_mass<double>(const LevelDev&, const double*, const double*, double*, hipStream_t);
-template void launch_mass<float>(const LevelDev&, const float*, const float*, float*, hipStream_t);
+template void launch_mass_bricks<double>(const LevelDev&, const double*, const double*, double*, hipStream_t);
+template void launch_mass_bricks<float>(const LevelDev&, const float*, const float*, float*, hipStream_t);
 void launch_mass_diag(const LevelDev& L, const double* eta, double* y, hipStream_t s) {
   dim3 grid((unsigned)(L.ntiles * L.nmacro));
   if (L.blend) hipLaunchKernelGGL((k_mass<double, true, true>), grid, dim3(384), 0, s, L, eta, nullptr, y);
@@ -1236,6 +1679,15 @@ void vexp(const double* x, double* y, long long n, hipStream_t s) { hipLaunchKer
 template <typename R> void vcheb_dir(const R* dinv, const R* r, R c1, R c2, R* d, long long n, hipStream_t s) {
   hipLaunchKernelGGL((k_cheb_dir<R>), dim3(vgrid(n)), dim3(256), 0, s, dinv, r, c1, c2, d, n);
 }
+template <typename R> void vcheb_start(const R* b, const R* t, const R* dinv, R c1, R* r, R* d, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_start<R>), dim3(vgrid(n)), dim3(256), 0, s, b, t, dinv, c1, r, d, n);
+}
+template <typename R> void vcheb_step(const R* t, const R* dinv, R c1, R c2, R* r, R* x, R* d, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_step<R>), dim3(vgrid(n)), dim3(256), 0, s, t, dinv, c1, c2, r, x, d, n);
+}
+template <typename R> void vsub(const R* b, const R* t, R* r, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_sub<R>), dim3(vgrid(n)), dim3(256), 0, s, b, t, r, n);
+}
 template <typename R> void vdot(const R* x, const R* y, long long n, double* partial, double* out, hipStream_t s) {
   long long g = (n + 255) / 256;
   int nb = (int)(g < DOT_BLOCKS ? (g < 1 ? 1 : g) : DOT_BLOCKS);
@@ -1255,10 +1707,15 @@ void vsum_partials(double* partial, int np, double* out, hipStream_t s) {
   template void vmul<R>(const R*, const R*, R*, long long, hipStream_t);           \
   template void vinvert<R>(const R*, R*, long long, hipStream_t);                  \
   template void vcheb_dir<R>(const R*, const R*, R, R, R*, long long, hipStream_t); \
-  template void vdot<R>(const R*, const R*, long long, double*, double*, hipStream_t);
+  template void vdot<R>(const R*, const R*, long long, double*, double*, hipStream_t);         \
+  template void vcheb_start<R>(const R*, const R*, const R*, R, R*, R*, long long, hipStream_t); \
+  template void vcheb_step<R>(const R*, const R*, R, R, R*, R*, R*, long long, hipStream_t);    \
+  template void vsub<R>(const R*, const R*, R*, long long, hipStream_t);
 INST_V(double)
 INST_V(float)
 template void vconvert<double, float>(const double*, float*, long long, hipStream_t);
+INST_CG(double)
+INST_CG(float)
 template void vconvert<float, double>(const float*, double*, long long, hipStream_t);
 
 }  // namespace stk

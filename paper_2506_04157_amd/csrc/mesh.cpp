@@ -411,6 +411,117 @@ Level build_level(const MacroMesh& mm, const Topology& top, int L) {
   return lv;
 }
 
+Sweep build_sweep(int n, int nstrips) {
+  Sweep sw;
+  const int m2 = 2 * n;
+  if (nstrips > n) nstrips = n;
+  if (nstrips < 1) nstrips = 1;
+  // balance element counts: cube row py holds about (n - py)(n - py + 1)/2 cubes
+  std::vector<double> w(n);
+  double tot = 0;
+  for (int j = 0; j < n; ++j) tot += (w[j] = 0.5 * (n - j) * (n - j + 1));
+  std::vector<int> cuts = {0};
+  double acc = 0;
+  for (int j = 0; j < n && (int)cuts.size() < nstrips; ++j) {
+    acc += w[j];
+    if (acc >= tot * cuts.size() / nstrips && j + 1 < n) cuts.push_back(j + 1);
+  }
+  cuts.push_back(n);
+  sw.nstrips = (int)cuts.size() - 1;
+  for (int s = 0; s < sw.nstrips; ++s) {
+    sw.strip.push_back(cuts[s]);
+    sw.strip.push_back(cuts[s + 1]);
+  }
+  auto is_cut = [&](int j) {   // internal strip boundary row (P1 units)
+    for (int s = 1; s < sw.nstrips; ++s)
+      if (cuts[s] == j) return true;
+    return false;
+  };
+  int nsh2 = 0, nsh1 = 0;
+  for (int st = 0; st < sw.nstrips; ++st) {
+    const int j0 = cuts[st], j1 = cuts[st + 1];
+    for (int K = 0; K <= m2; ++K) {
+      sw.poff2.push_back((int)sw.plist2.size() / 2);
+      int cnt = 0;
+      for (int J = 2 * j0; J <= std::min(2 * j1, m2 - K); ++J)
+        for (int I = 0; I <= m2 - K - J; ++I) {
+          const bool bnd = (m2 - I - J - K) == 0 || I == 0 || J == 0 || K == 0;
+          const bool shared = bnd || ((J % 2) == 0 && is_cut(J / 2));
+          sw.plist2.push_back(I | (J << 10) | (K << 20));
+          sw.plist2.push_back(shared ? nsh2++ : -1);
+          ++cnt;
+        }
+      sw.cap2 = std::max(sw.cap2, cnt);
+    }
+    sw.poff2.push_back((int)sw.plist2.size() / 2);
+    for (int k = 0; k <= n; ++k) {
+      sw.poff1.push_back((int)sw.plist1.size() / 2);
+      int cnt = 0;
+      for (int J = j0; J <= std::min(j1, n - k); ++J)
+        for (int I = 0; I <= n - k - J; ++I) {
+          const bool bnd = (n - I - J - k) == 0 || I == 0 || J == 0 || k == 0;
+          const bool shared = bnd || is_cut(J);
+          sw.plist1.push_back(I | (J << 10) | (k << 20));
+          sw.plist1.push_back(shared ? nsh1++ : -1);
+          ++cnt;
+        }
+      sw.cap1 = std::max(sw.cap1, cnt);
+    }
+    sw.poff1.push_back((int)sw.plist1.size() / 2);
+    for (int k = 0; k < n; ++k) {
+      sw.eoff.push_back((int)sw.elist.size());
+      for (int t = 0; t < 6; ++t) {
+        const int lim = t == 0 ? n - 1 : (t == 5 ? n - 3 : n - 2);
+        for (int py = j0; py < j1; ++py)
+          for (int px = 0; px + py + k <= lim; ++px) sw.elist.push_back(t | (px << 3) | (py << 13));
+      }
+    }
+    sw.eoff.push_back((int)sw.elist.size());
+  }
+  sw.nsh2 = nsh2;
+  sw.nsh1 = nsh1;
+  return sw;
+}
+
+void build_gather(const MacroMesh& mm, const Level& lv, const Sweep& sw, int which, std::vector<uint32_t>& node,
+                  std::vector<int>& ptr, std::vector<int>& slot) {
+  const int nm = mm.nm();
+  const int m = which == 2 ? 2 * lv.n : lv.n;
+  const int64_t nloc = which == 2 ? lv.nloc2 : lv.nloc1;
+  const std::vector<uint32_t>& l2g = which == 2 ? lv.l2g2 : lv.l2g1;
+  const std::vector<int>& pl = which == 2 ? sw.plist2 : sw.plist1;
+  const int nsh = which == 2 ? sw.nsh2 : sw.nsh1;
+  const int64_t ntot = which == 2 ? lv.n2 : lv.n1;
+  // local (entry -> loc) for the shared entries
+  std::vector<std::pair<int, int>> sh;   // (loc, slot)
+  for (size_t e = 0; e < pl.size() / 2; ++e) {
+    if (pl[2 * e + 1] < 0) continue;
+    const int pk = pl[2 * e];
+    const int I = pk & 1023, J = (pk >> 10) & 1023, K = pk >> 20;
+    sh.push_back({(int)lattice_loc(I, J, K, m), pl[2 * e + 1]});
+  }
+  std::vector<int> cnt(ntot + 1, 0);
+  for (int mc = 0; mc < nm; ++mc)
+    for (auto& e : sh) cnt[l2g[(size_t)mc * nloc + e.first] + 1]++;
+  // compact: only nodes with at least one slot
+  node.clear();
+  ptr.assign(1, 0);
+  std::vector<int> pos(ntot, -1);
+  for (int64_t g = 0; g < ntot; ++g)
+    if (cnt[g + 1] > 0) {
+      pos[g] = ptr.back();
+      node.push_back((uint32_t)g);
+      ptr.push_back(ptr.back() + cnt[g + 1]);
+    }
+  slot.assign(ptr.back(), 0);
+  for (int mc = 0; mc < nm; ++mc)
+    for (auto& e : sh) {
+      const uint32_t g = l2g[(size_t)mc * nloc + e.first];
+      slot[pos[g]++] = (int)((int64_t)mc * nsh + e.second);
+    }
+  // pos[g] now points past the node's range; slots are in (macro, slot) order
+}
+
 void level_coords(const MacroMesh& mm, const Topology& top, const Level& lv, int which, double* X,
                   uint8_t* flags) {
   const int nm = mm.nm();

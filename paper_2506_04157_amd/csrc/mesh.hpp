@@ -74,6 +74,27 @@ struct Level {
 
 constexpr int TILE = 4;                    // cubes per brick side
 
+// Plane-sweep decomposition of one macro-tet (the same for every macro of a
+// level): the cube rows py are split into strips; a workgroup sweeps one
+// (macro, strip) layer by layer along the third lattice direction.  Nodes on
+// the macro boundary or on a strip boundary row are "shared": their partial
+// sums go to per-(macro, strip, node) slots that a gather pass adds up.
+struct Sweep {
+  int nstrips = 1;
+  std::vector<int> strip;      // j0, j1 (cube rows [j0, j1)) per strip
+  // P2 / P1 plane lists per (strip, plane): entries (packed I | J<<10 | K<<20, slot or -1)
+  std::vector<int> plist2, poff2, plist1, poff1;
+  // elements per (strip, layer): packed type | px<<3 | py<<13
+  std::vector<int> elist, eoff;
+  int nsh2 = 0, nsh1 = 0;      // shared slots per macro
+  int cap2 = 0, cap1 = 0;      // largest plane list (LDS ring slot size)
+};
+Sweep build_sweep(int n, int nstrips);
+// Gather lists of the shared nodes: for each shared global node, the slots
+// (macro * nsh + slot) holding its partial sums.  which = 2 (P2) or 1 (P1).
+void build_gather(const MacroMesh& mm, const Level& lv, const Sweep& sw, int which, std::vector<uint32_t>& node,
+                  std::vector<int>& ptr, std::vector<int>& slot);
+
 Level build_level(const MacroMesh& mm, const Topology& top, int L);
 // Blended coordinates (3 per node, nullable) and boundary kinds (nullable) of
 // the P2 (which = 2) or P1 (which = 1) nodes of a level.

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -108,6 +109,12 @@ struct LevelData {
   DBuf<double> tinv, nrm, eta, dinv;
   DBuf<float> tinvf, nrmf, etaf, dinvf;
   DBuf<int> tiles;
+  Sweep sw;
+  DBuf<int> eall;
+  DBuf<int> sw_strip, sw_plist2, sw_poff2, sw_plist1, sw_poff1, sw_elist, sw_eoff, g2ptr, g2slot, g1ptr, g1slot;
+  DBuf<uint32_t> g2node, g1node;
+  DBuf<double> sl2_64, sl1_64;   // slot buffers of the sweep kernels
+  DBuf<float> sl2_32, sl1_32;
   double lo = 0, hi = 0;
   bool bounds_set = false;
   Pool<double> p64, q64;   // velocity-size / pressure-size work vectors
@@ -116,6 +123,8 @@ struct LevelData {
   template <class R> Pool<R>& ppool();
   template <class R> const R* etap() const;
   template <class R> const R* dinvp() const;
+  template <class R> R* sl2();
+  template <class R> R* sl1();
 };
 template <> Pool<double>& LevelData::pool<double>() { return p64; }
 template <> Pool<float>& LevelData::pool<float>() { return p32; }
@@ -125,6 +134,22 @@ template <> const double* LevelData::etap<double>() const { return eta.p; }
 template <> const float* LevelData::etap<float>() const { return etaf.p; }
 template <> const double* LevelData::dinvp<double>() const { return dinv.p; }
 template <> const float* LevelData::dinvp<float>() const { return dinvf.p; }
+template <> double* LevelData::sl2<double>() {
+  sl2_64.alloc((size_t)3 * d.nmacro * sw.nsh2);
+  return sl2_64.p;
+}
+template <> float* LevelData::sl2<float>() {
+  sl2_32.alloc((size_t)3 * d.nmacro * sw.nsh2);
+  return sl2_32.p;
+}
+template <> double* LevelData::sl1<double>() {
+  sl1_64.alloc((size_t)d.nmacro * sw.nsh1);
+  return sl1_64.p;
+}
+template <> float* LevelData::sl1<float>() {
+  sl1_32.alloc((size_t)d.nmacro * sw.nsh1);
+  return sl1_32.p;
+}
 
 // indices into the per-level velocity work pools
 enum { W_B = 0, W_X, W_R, W_D, W_T, W_CG_R, W_CG_Z, W_CG_P, W_CG_Q, W_U0, W_U1, W_U2, W_U3, W_U4, W_U5,
@@ -144,6 +169,7 @@ struct stk_ctx {
   DBuf<uint8_t> bact, own;
   hipStream_t s = nullptr;
   DBuf<double> dotbuf;
+  DBuf<double> cgbuf;      // device CG scalars
   double* hpin = nullptr;
   bool ready = false;
   bool has_rho = false;
@@ -153,6 +179,7 @@ struct stk_ctx {
   stk_report* rep = nullptr;
   // FGMRES storage
   DBuf<double> fg;
+  bool verbose = std::getenv("STK_VERBOSE") != nullptr;   // progress lines on stderr
   int L() const { return desc.level; }
   int lmin() const { return desc.min_level; }
   LevelData& at(int l) { return *lv[l]; }
@@ -170,8 +197,8 @@ long long n1of(Ctx& c, int l) { return c.at(l).h.n1; }
 
 template <class R>
 double dot(Ctx& c, const R* x, const R* y, long long n) {
-  vdot<R>(x, y, n, c.dotbuf.p, c.dotbuf.p + DOT_BLOCKS, c.s);
-  HIPCHK(hipMemcpyAsync(c.hpin, c.dotbuf.p + DOT_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  vdot<R>(x, y, n, c.dotbuf.p, c.dotbuf.p + 2 * DOT_BLOCKS, c.s);
+  HIPCHK(hipMemcpyAsync(c.hpin, c.dotbuf.p + 2 * DOT_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, c.s));
   HIPCHK(hipStreamSynchronize(c.s));
   return *c.hpin;
 }
@@ -203,34 +230,35 @@ void project_mean(Ctx& c, R* p) {
 
 // ---- operator applies (outputs overwritten) ---------------------------------
 template <class R>
-void applyA(Ctx& c, int l, const R* x, R* y, int bc) {
+void sweep(Ctx& c, int l, int flags, const R* u, const R* p, const R* eta, const R* rho, R* yu, R* yp, int bc) {
   LevelData& L = c.at(l);
-  vfill<R>(y, R(0), 3 * L.h.n2, c.s);
-  launch_stokes<R>(F_A, L.d, x, nullptr, L.etap<R>(), nullptr, y, nullptr, bc, c.s);
+  launch_stokes<R>(flags, L.d, L.bc, u, p, eta, rho, yu, yp, L.sl2<R>(), L.sl1<R>(), bc, c.s);
+}
+template <class R>
+void applyA(Ctx& c, int l, const R* x, R* y, int bc) {
+  sweep<R>(c, l, F_A, x, nullptr, c.at(l).etap<R>(), nullptr, y, nullptr, bc);
 }
 template <class R>
 void applyB(Ctx& c, int l, const R* u, R* q, bool withC, int bc) {
-  LevelData& L = c.at(l);
   REQUIRE(!withC || (c.has_rho && l == c.L()), "C block needs ln rho on the finest level");
-  vfill<R>(q, R(0), L.h.n1, c.s);
-  launch_stokes<R>(withC ? (F_B | F_C) : F_B, L.d, u, nullptr, nullptr, c.rho<R>(), nullptr, q, bc, c.s);
+  sweep<R>(c, l, withC ? (F_B | F_C) : F_B, u, nullptr, nullptr, c.rho<R>(), nullptr, q, bc);
 }
 template <class R>
 void applyBt(Ctx& c, int l, const R* p, R* y, bool withCt, int bc) {
-  LevelData& L = c.at(l);
   REQUIRE(!withCt || (c.has_rho && l == c.L()), "C block needs ln rho on the finest level");
-  vfill<R>(y, R(0), 3 * L.h.n2, c.s);
-  launch_stokes<R>(withCt ? (F_BT | F_CT) : F_BT, L.d, nullptr, p, nullptr, c.rho<R>(), y, nullptr, bc, c.s);
+  sweep<R>(c, l, withCt ? (F_BT | F_CT) : F_BT, nullptr, p, nullptr, c.rho<R>(), y, nullptr, bc);
+}
+template <class R>
+void applyMass(Ctx& c, int l, const R* p, R* q) {
+  sweep<R>(c, l, F_M, nullptr, p, c.at(l).etap<R>(), nullptr, nullptr, q, 0);
 }
 // K [u;p] on the finest level, velocity projected on both sides
 template <class R>
 void applyK(Ctx& c, const R* u, const R* p, R* yu, R* yp, bool transpose, int bc) {
-  LevelData& L = c.at(c.L());
-  vfill<R>(yu, R(0), 3 * L.h.n2, c.s);
-  vfill<R>(yp, R(0), L.h.n1, c.s);
+  const int l = c.L();
   int fl = F_A | F_BT | F_B;
   if (c.has_rho) fl |= transpose ? F_CT : F_C;
-  launch_stokes<R>(fl, L.d, u, p, L.etap<R>(), c.rho<R>(), yu, yp, bc, c.s);
+  sweep<R>(c, l, fl, u, p, c.at(l).etap<R>(), c.rho<R>(), yu, yp, bc);
 }
 
 // ---- Chebyshev smoother (Jacobi preconditioned) -------------------------------
@@ -244,31 +272,59 @@ void chebyshev(Ctx& c, int l, const R* b, R* x, int steps, int deg, bool xzero) 
   R* t = L.pool<R>().get(W_T, N, c.s);
   const R* dinv = L.dinvp<R>();
   for (int st = 0; st < steps; ++st) {
+    // r = P (b - A x): b is projected and A's output too, so no extra projection
     if (xzero && st == 0) {
-      vcopy<R>(b, r, N, c.s);
+      vcheb_start<R>(b, nullptr, dinv, R(1.0 / theta), r, d, N, c.s);
     } else {
       applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
-      vcopy<R>(b, r, N, c.s);
-      vaxpy<R>(R(-1), t, r, N, c.s);
+      vcheb_start<R>(b, t, dinv, R(1.0 / theta), r, d, N, c.s);
     }
-    project<R>(c, l, r);
-    vcheb_dir<R>(dinv, r, R(1.0 / theta), R(0), d, N, c.s);
     project<R>(c, l, d);
     double rho_old = 1.0 / sigma;
-    for (int k = 1; k <= deg; ++k) {
-      vaxpy<R>(R(1), d, x, N, c.s);
-      if (k == deg) break;
+    for (int k = 1; k < deg; ++k) {
+      // x += d; r -= A d; d = 2 rho/delta D^-1 r + rho rho_old d
       applyA<R>(c, l, d, t, BCM_IN | BCM_OUT);
-      vaxpy<R>(R(-1), t, r, N, c.s);
       const double rho = 1.0 / (2.0 * sigma - rho_old);
-      vcheb_dir<R>(dinv, r, R(2.0 * rho / delta), R(rho * rho_old), d, N, c.s);
+      vcheb_step<R>(t, dinv, R(2.0 * rho / delta), R(rho * rho_old), r, x, d, N, c.s);
       project<R>(c, l, d);
       rho_old = rho;
     }
+    vaxpy<R>(R(1), d, x, N, c.s);
   }
 }
 
 // ---- coarse grid: Jacobi-preconditioned CG in FP64 (Sec. 5.2.2, tol_coarse) ---
+// Jacobi-preconditioned CG with device-resident scalars (no host round trip
+// per iteration); the host looks at the convergence flag every CG_CHUNK
+// iterations.  apply(p, q) computes q = A p; proj(v) projects in place (it
+// must be an orthogonal projection commuting with the residual's range).
+template <class R, class Apply, class Proj>
+int dev_pcg(Ctx& c, long long N, Apply apply, Proj proj, const R* dinv, const R* b, R* x, R* r, R* z, R* p, R* q,
+            double tol, int maxit, int chunk) {
+  double* part = c.dotbuf.p;
+  double* sc = c.cgbuf.p;
+  vfill<R>(x, R(0), N, c.s);
+  vcopy<R>(b, r, N, c.s);
+  proj(r);
+  cg_init<R>(r, dinv, z, N, tol, part, sc, c.s);
+  proj(z);
+  vcopy<R>(z, p, N, c.s);
+  int it = 0;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      apply(p, q);
+      cg_alpha<R>(p, q, N, part, sc, c.s);
+      cg_update<R>(p, q, dinv, x, r, z, N, part, sc, c.s);
+      proj(z);
+      cg_pupdate<R>(z, p, N, sc, c.s);
+    }
+    it += chunk;
+    HIPCHK(hipMemcpyAsync(c.hpin, sc, CGS_N * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    if (c.hpin[CGS_DONE] != 0.0 || it >= maxit) return (int)c.hpin[CGS_IT];
+  }
+}
+
 void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit) {
   const int l = c.lmin();
   LevelData& L = c.at(l);
@@ -278,27 +334,10 @@ void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit) {
   double* z = P.get(W_C_Z, N, c.s);
   double* p = P.get(W_C_P, N, c.s);
   double* q = P.get(W_C_Q, N, c.s);
-  vfill<double>(x, 0.0, N, c.s);
-  vcopy<double>(b, r, N, c.s);
-  project<double>(c, l, r);
-  const double nb = nrm2<double>(c, r, N);
-  if (nb == 0.0) return;
-  vmul<double>(L.dinv.p, r, z, N, c.s);
-  project<double>(c, l, z);
-  vcopy<double>(z, p, N, c.s);
-  double rz = dot<double>(c, r, z, N);
-  for (int it = 1; it <= maxit; ++it) {
-    applyA<double>(c, l, p, q, BCM_IN | BCM_OUT);
-    const double alpha = rz / dot<double>(c, p, q, N);
-    vaxpy<double>(alpha, p, x, N, c.s);
-    vaxpy<double>(-alpha, q, r, N, c.s);
-    if (nrm2<double>(c, r, N) <= tol * nb) break;
-    vmul<double>(L.dinv.p, r, z, N, c.s);
-    project<double>(c, l, z);
-    const double rz2 = dot<double>(c, r, z, N);
-    vaxpby<double>(1.0, z, rz2 / rz, p, N, c.s);
-    rz = rz2;
-  }
+  const int its = dev_pcg<double>(
+      c, N, [&](const double* pp, double* qq) { applyA<double>(c, l, pp, qq, BCM_IN | BCM_OUT); },
+      [&](double* v) { project<double>(c, l, v); }, L.dinv.p, b, x, r, z, p, q, tol, maxit, 8);
+  if (c.rep) c.rep->coarse_its += its;
 }
 
 template <class R>
@@ -332,8 +371,7 @@ void vcycle(Ctx& c, int l, const R* b, R* x, int steps, int deg) {
   R* r = L.pool<R>().get(W_R, N, c.s);
   R* t = L.pool<R>().get(W_T, N, c.s);
   applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
-  vcopy<R>(b, r, N, c.s);
-  vaxpy<R>(R(-1), t, r, N, c.s);
+  vsub<R>(b, t, r, N, c.s);
   R* bc = C.pool<R>().get(W_B, Nc, c.s);
   R* xc = C.pool<R>().get(W_X, Nc, c.s);
   vfill<R>(bc, R(0), Nc, c.s);
@@ -391,25 +429,10 @@ void solve_mass(Ctx& c, const R* b, R* x) {
   R* p = Q.get(Q_7, n1, c.s);
   R* q = Q.get(Q_8, n1, c.s);
   R* z = Q.get(Q_9, n1, c.s);
-  vfill<R>(x, R(0), n1, c.s);
-  vcopy<R>(b, r, n1, c.s);
-  const double nb = nrm2<R>(c, r, n1);
-  if (nb == 0.0) return;
-  vmul<R>(md, r, z, n1, c.s);
-  vcopy<R>(z, p, n1, c.s);
-  double rz = dot<R>(c, r, z, n1);
-  for (int it = 1; it <= c.par.max_inner * 10; ++it) {
-    vfill<R>(q, R(0), n1, c.s);
-    launch_mass<R>(L.d, L.etap<R>(), p, q, c.s);
-    const double alpha = rz / dot<R>(c, p, q, n1);
-    vaxpy<R>(R(alpha), p, x, n1, c.s);
-    vaxpy<R>(R(-alpha), q, r, n1, c.s);
-    if (nrm2<R>(c, r, n1) <= c.par.tol_invmass * nb) break;
-    vmul<R>(md, r, z, n1, c.s);
-    const double rz2 = dot<R>(c, r, z, n1);
-    vaxpby<R>(R(1), z, R(rz2 / rz), p, n1, c.s);
-    rz = rz2;
-  }
+  const int its = dev_pcg<R>(
+      c, n1, [&](const R* pp, R* qq) { applyMass<R>(c, l, pp, qq); }, [](R*) {}, md, b, x, r, z, p, q,
+      c.par.tol_invmass, c.par.max_inner * 10, n1 > 1000000 ? 1 : 4);
+  if (c.rep) c.rep->mass_its += its;
 }
 
 // S_C p = B Ac^-1 B^T p, with Ac one V-cycle (m_V, deg_V)
@@ -608,6 +631,11 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
       ++total;
       j_used = j + 1;
       if (c.rep && c.rep->history_len < 256) c.rep->history[c.rep->history_len++] = std::fabs(g[j + 1]) / nb;
+      if (c.verbose) {
+        std::fprintf(stderr, "[stk] fgmres it %d rel %.3e  (A its %d, S its %d)\n", total, std::fabs(g[j + 1]) / nb,
+                     c.rep ? c.rep->a_cg_its : -1, c.rep ? c.rep->s_cg_its : -1);
+        std::fflush(stderr);
+      }
       if (std::fabs(g[j + 1]) <= target) break;
     }
     // x += Z y
@@ -670,6 +698,57 @@ void upload_level(Ctx& c, int l) {
   d.bact = c.bact.p;
   d.own = c.own.p;
   d.tiles = L.tiles.p;
+  // plane-sweep tables: as many strips as needed to keep the fused FP64
+  // kernel's LDS ring within 64 KiB
+  for (int ns = 1;; ns *= 2) {
+    L.sw = build_sweep(h.n, ns);
+    if (sweep_lds_bytes(F_A | F_BT | F_B | F_C, L.sw.cap2, L.sw.cap1, 8) <= 65536 || ns >= h.n) break;
+  }
+  {
+    std::vector<int> ea;
+    for (int t = 0; t < 6; ++t) {
+      const int lim = t == 0 ? h.n - 1 : (t == 5 ? h.n - 3 : h.n - 2);
+      for (int pz = 0; pz < h.n; ++pz)
+        for (int py = 0; py < h.n; ++py)
+          for (int px = 0; px + py + pz <= lim; ++px) ea.push_back(t | (px << 3) | (py << 13) | (pz << 23));
+    }
+    L.eall.upload(ea);
+    d.eall = L.eall.p;
+    d.elemwise = h.n <= 2;
+  }
+  L.sw_strip.upload(L.sw.strip);
+  L.sw_plist2.upload(L.sw.plist2);
+  L.sw_poff2.upload(L.sw.poff2);
+  L.sw_plist1.upload(L.sw.plist1);
+  L.sw_poff1.upload(L.sw.poff1);
+  L.sw_elist.upload(L.sw.elist);
+  L.sw_eoff.upload(L.sw.eoff);
+  d.sw.nstrips = L.sw.nstrips;
+  d.sw.cap2 = L.sw.cap2;
+  d.sw.cap1 = L.sw.cap1;
+  d.sw.nsh2 = L.sw.nsh2;
+  d.sw.nsh1 = L.sw.nsh1;
+  d.sw.strip = L.sw_strip.p;
+  d.sw.plist2 = (const int2*)L.sw_plist2.p;
+  d.sw.poff2 = L.sw_poff2.p;
+  d.sw.plist1 = (const int2*)L.sw_plist1.p;
+  d.sw.poff1 = L.sw_poff1.p;
+  d.sw.elist = L.sw_elist.p;
+  d.sw.eoff = L.sw_eoff.p;
+  {
+    std::vector<uint32_t> node;
+    std::vector<int> ptr, slot;
+    build_gather(c.mm, h, L.sw, 2, node, ptr, slot);
+    L.g2node.upload(node);
+    L.g2ptr.upload(ptr);
+    L.g2slot.upload(slot);
+    d.g2 = GatherDev{(int)node.size(), L.g2node.p, L.g2ptr.p, L.g2slot.p};
+    build_gather(c.mm, h, L.sw, 1, node, ptr, slot);
+    L.g1node.upload(node);
+    L.g1ptr.upload(ptr);
+    L.g1slot.upload(slot);
+    d.g1 = GatherDev{(int)node.size(), L.g1node.p, L.g1ptr.p, L.g1slot.p};
+  }
   // boundary lists
   std::vector<uint32_t> dir, fs;
   std::vector<double> nrm;
@@ -876,7 +955,8 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
       c->lv[l]->h = build_level(c->mm, c->top, l);
       upload_level(*c, l);
     }
-    c->dotbuf.alloc(DOT_BLOCKS + 8);
+    c->dotbuf.alloc(2 * DOT_BLOCKS + 8);
+    c->cgbuf.alloc(16);
     HIPCHK(hipHostMalloc((void**)&c->hpin, 64, hipHostMallocDefault));
     HIPCHK(hipDeviceSynchronize());
     *out = c.release();
@@ -991,12 +1071,8 @@ int stk_apply_mass(stk_ctx* ctx, int level, int prec, const void* p, void* q) {
     need_ready(ctx);
     check_level(ctx, level);
     REQUIRE(p && q, "null vector");
-    LevelData& L = ctx->at(level);
-    PREC_DISPATCH(prec,
-                  (vfill<double>((double*)q, 0.0, L.h.n1, ctx->s),
-                   launch_mass<double>(L.d, L.eta.p, (const double*)p, (double*)q, ctx->s)),
-                  (vfill<float>((float*)q, 0.f, L.h.n1, ctx->s),
-                   launch_mass<float>(L.d, L.etaf.p, (const float*)p, (float*)q, ctx->s)));
+    PREC_DISPATCH(prec, applyMass<double>(*ctx, level, (const double*)p, (double*)q),
+                  applyMass<float>(*ctx, level, (const float*)p, (float*)q));
     HIPCHK(hipGetLastError());
   });
 }
@@ -1164,31 +1240,47 @@ int stk_gradient(stk_ctx* ctx, const double* u, const double* lu, double scale, 
   });
 }
 
-int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_per_apply) {
+int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_apply,
+                     double* ms_kernel) {
   return guard([&] {
     need_ready(ctx);
     check_level(ctx, level);
-    REQUIRE(x && y && ms_per_apply && reps >= 1, "bad argument");
+    REQUIRE(x && y && ms_apply && reps >= 1, "bad argument");
+    REQUIRE(prec == 32 || prec == 64, "prec must be 32 or 64");
     LevelData& L = ctx->at(level);
-    hipEvent_t e0, e1;
+    hipEvent_t e0, e1, e2;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventCreate(&e2));
+    // whole operator: sweep + gather + projection
     HIPCHK(hipEventRecord(e0, ctx->s));
     for (int i = 0; i < reps; ++i) {
-      if (prec == 64)
-        launch_stokes<double>(F_A, L.d, (const double*)x, nullptr, L.eta.p, nullptr, (double*)y, nullptr,
-                              BCM_IN | BCM_OUT, ctx->s);
-      else
-        launch_stokes<float>(F_A, L.d, (const float*)x, nullptr, L.etaf.p, nullptr, (float*)y, nullptr,
-                             BCM_IN | BCM_OUT, ctx->s);
+      if (prec == 64) applyA<double>(*ctx, level, (const double*)x, (double*)y, BCM_IN | BCM_OUT);
+      else applyA<float>(*ctx, level, (const float*)x, (float*)y, BCM_IN | BCM_OUT);
     }
     HIPCHK(hipEventRecord(e1, ctx->s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    // the sweep kernel alone (gather lists emptied)
+    LevelDev d = L.d;
+    d.g2.nnodes = 0;
+    BcDev nobc{};
+    for (int i = 0; i < reps; ++i) {
+      if (prec == 64)
+        launch_stokes<double>(F_A, d, nobc, (const double*)x, nullptr, L.eta.p, nullptr, (double*)y, nullptr,
+                              L.sl2<double>(), L.sl1<double>(), BCM_IN, ctx->s);
+      else
+        launch_stokes<float>(F_A, d, nobc, (const float*)x, nullptr, L.etaf.p, nullptr, (float*)y, nullptr,
+                             L.sl2<float>(), L.sl1<float>(), BCM_IN, ctx->s);
+    }
+    HIPCHK(hipEventRecord(e2, ctx->s));
+    HIPCHK(hipEventSynchronize(e2));
+    float a = 0, b = 0;
+    HIPCHK(hipEventElapsedTime(&a, e0, e1));
+    HIPCHK(hipEventElapsedTime(&b, e1, e2));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *ms_per_apply = ms / reps;
+    (void)hipEventDestroy(e2);
+    *ms_apply = a / reps;
+    if (ms_kernel) *ms_kernel = b / reps;
   });
 }
 
