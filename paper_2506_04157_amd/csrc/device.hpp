@@ -38,6 +38,22 @@ struct GatherDev {
   const int* slot;
 };
 
+// P1 mass stencil of a level: per-macro rows over the 15 lattice directions
+// (the node itself and its 14 lattice neighbours), assembled once per
+// viscosity field; macro-boundary rows are partial and summed by a gather.
+constexpr int NDIR1D = 15;
+struct StencilDev {
+  int on;                 // 1: the stencil apply is used for this level
+  int nsh;                // slots per macro
+  const short* nb;        // [15][nloc1] neighbour local index (the node itself where absent)
+  const int* dst;         // [nloc1] slot of macro-boundary nodes, -1 for macro-interior nodes
+  const int* inc_ptr;     // [nloc1 + 1] micro-tets containing each node
+  const int2* inc;        // (packed type | px<<3 | py<<13 | pz<<23, vertex | direction codes)
+  const double* c64;      // [nmacro][15][nloc1]
+  const float* c32;
+  GatherDev g;
+};
+
 struct LevelDev {
   int n;                  // P1 lattice side 2^L (P2 side 2n)
   int nloc2, nloc1;       // lattice points per macro
@@ -57,6 +73,7 @@ struct LevelDev {
   GatherDev g2, g1;
   int elemwise;           // 1: element-parallel kernel (coarse levels)
   const int* eall;        // all micro-tets of a macro: type | px<<3 | py<<13 | pz<<23
+  StencilDev ms;          // P1 mass stencil
 };
 
 // Boundary node lists of a level (for vector projections).
@@ -82,6 +99,13 @@ void launch_diag(const LevelDev& L, const R* eta, R* d, hipStream_t s);
 template <typename R>
 void launch_mass_bricks(const LevelDev& L, const R* eta, const R* p, R* y, hipStream_t s);
 void launch_mass_diag(const LevelDev& L, const double* eta, double* y, hipStream_t s);
+// assemble the P1 mass stencil coefficients (FP64, and an FP32 copy) from eta
+void launch_mass_stencil_build(const LevelDev& L, const double* eta, double* c64, float* c32, hipStream_t s);
+// y = M_{1/eta} p with the assembled stencil; slots: nmacro * L.ms.nsh values
+template <typename R>
+void launch_mass_stencil(const LevelDev& L, const R* p, R* y, R* slots, hipStream_t s);
+// LDS bytes of the stencil apply
+size_t mass_stencil_lds_bytes(int nloc1, int real_bytes);
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s);
 void launch_gradient(const LevelDev& L, const double* eta, const double* u, const double* lam,
                      double* gm, double* gT, double scale, hipStream_t s);

@@ -692,6 +692,101 @@ __global__ void k_gather(GatherDev gd, const R* __restrict__ sl, size_t sstride,
   for (int c = 0; c < NC; ++c) y[g + c * ystride] = v[c];
 }
 
+// ---- P1 mass stencil of M_{1/eta} (Sec. 5.2.3) --------------------------------
+// Assembly: one thread per (macro, local P1 node) sums, over the micro-tets that
+// contain the node in a fixed order, the element entries of its row,
+//   M_vw = sum_q W_q psi_v(x_q) psi_w(x_q) / eta_h(x_q),
+// into the lattice direction of each vertex w.  FP64, no atomics.
+template <bool BLEND>
+__global__ __launch_bounds__(256) void k_mass_stencil_build(LevelDev L, const double* __restrict__ eta,
+                                                            double* __restrict__ c64, float* __restrict__ c32) {
+  const int nloc = L.nloc1, n = L.n;
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)nloc * L.nmacro) return;
+  const int mac = (int)(gid / nloc), t = (int)(gid - (long long)mac * nloc);
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * nloc;
+  const double* G = L.geo + (size_t)mac * 16;
+  double acc[NDIR1D];
+#pragma unroll
+  for (int d = 0; d < NDIR1D; ++d) acc[d] = 0.0;
+  const int k1 = L.ms.inc_ptr[t + 1];
+  for (int k = L.ms.inc_ptr[t]; k < k1; ++k) {
+    const int2 e = L.ms.inc[k];
+    const unsigned ex = (unsigned)e.x;
+    const int type = ex & 7, px = (ex >> 3) & 1023, py = (ex >> 13) & 1023, pz = ex >> 23;
+    const int v = e.y & 3;
+    double et[4], set = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      et[w] = eta[l1[lloc(px + c_toff[type][w][0], py + c_toff[type][w][1], pz + c_toff[type][w][2], n)]];
+      set += et[w];
+    }
+    const double* TI = L.tinv + ((size_t)mac * 6 + type) * 10;
+    const double wdetF = QW * TI[9];
+    double xv[4][3], xs[3] = {0.0, 0.0, 0.0};
+    if (BLEND) {
+      elem_vertices<double>(G, type, px, py, pz, n, xv);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) xs[r] = xv[0][r] + xv[1][r] + xv[2][r] + xv[3][r];
+    }
+    double sq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double xq[3] = {0.0, 0.0, 0.0};
+      if (BLEND) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) xq[r] = QB * xs[r] + (QA - QB) * xv[q][r];
+      }
+      QGeo<double, BLEND> geo;
+      geo.eval(G, xq, wdetF);
+      sq[q] = geo.W / (QB * set + (QA - QB) * et[q]);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      double m = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m += sq[q] * (v == q ? QA : QB) * (w == q ? QA : QB);
+      const int d = (e.y >> (2 + 4 * w)) & 15;
+#pragma unroll
+      for (int dd = 0; dd < NDIR1D; ++dd)
+        if (dd == d) acc[dd] += m;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < NDIR1D; ++d) {
+    const size_t o = ((size_t)mac * NDIR1D + d) * nloc + t;
+    c64[o] = acc[d];
+    c32[o] = (float)acc[d];
+  }
+}
+
+template <typename R> __device__ __forceinline__ const R* mcoef_of(const LevelDev& L);
+template <> __device__ __forceinline__ const double* mcoef_of<double>(const LevelDev& L) { return L.ms.c64; }
+template <> __device__ __forceinline__ const float* mcoef_of<float>(const LevelDev& L) { return L.ms.c32; }
+
+// Apply: one workgroup per macro stages p of its P1 lattice in LDS and forms
+// each row of the stencil (FP64 sums in a fixed order); macro-interior rows
+// are final, macro-boundary rows go to slots summed by k_gather.
+template <typename R>
+__global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __restrict__ p, R* __restrict__ y,
+                                                      R* __restrict__ sl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* sp = reinterpret_cast<R*>(smem_raw);
+  const int nloc = L.nloc1, mac = blockIdx.x;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * nloc;
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) sp[t] = p[l1[t]];
+  __syncthreads();
+  const R* c = mcoef_of<R>(L) + (size_t)mac * NDIR1D * nloc;
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIR1D; ++d) acc += (double)c[(size_t)d * nloc + t] * (double)sp[L.ms.nb[d * nloc + t]];
+    const int slot = L.ms.dst[t];
+    if (slot < 0) y[l1[t]] = R(acc);
+    else sl[(size_t)mac * L.ms.nsh + slot] = R(acc);
+  }
+}
+
 // ---- diag(A) (no free-slip projection, Sec. 5.2.2) ---------------------------
 template <typename R, bool BLEND>
 __global__ __launch_bounds__(384) void k_diag(LevelDev L, const R* __restrict__ eta, R* __restrict__ dout) {
@@ -1618,6 +1713,24 @@ void launch_mass_diag(const LevelDev& L, const double* eta, double* y, hipStream
   if (L.blend) hipLaunchKernelGGL((k_mass<double, true, true>), grid, dim3(384), 0, s, L, eta, nullptr, y);
   else hipLaunchKernelGGL((k_mass<double, false, true>), grid, dim3(384), 0, s, L, eta, nullptr, y);
 }
+
+void launch_mass_stencil_build(const LevelDev& L, const double* eta, double* c64, float* c32, hipStream_t s) {
+  const long long nt = (long long)L.nloc1 * L.nmacro;
+  dim3 grid((unsigned)((nt + 255) / 256));
+  if (L.blend) hipLaunchKernelGGL((k_mass_stencil_build<true>), grid, dim3(256), 0, s, L, eta, c64, c32);
+  else hipLaunchKernelGGL((k_mass_stencil_build<false>), grid, dim3(256), 0, s, L, eta, c64, c32);
+}
+size_t mass_stencil_lds_bytes(int nloc1, int real_bytes) { return (size_t)nloc1 * real_bytes; }
+template <typename R>
+void launch_mass_stencil(const LevelDev& L, const R* p, R* y, R* slots, hipStream_t s) {
+  hipLaunchKernelGGL((k_mass_stencil<R>), dim3((unsigned)L.nmacro), dim3(256),
+                     mass_stencil_lds_bytes(L.nloc1, sizeof(R)), s, L, p, y, slots);
+  if (L.ms.g.nnodes > 0)
+    hipLaunchKernelGGL((k_gather<R, 1>), dim3((L.ms.g.nnodes + 255) / 256), dim3(256), 0, s, L.ms.g, slots,
+                       (size_t)0, y, (size_t)0);
+}
+template void launch_mass_stencil<double>(const LevelDev&, const double*, double*, double*, hipStream_t);
+template void launch_mass_stencil<float>(const LevelDev&, const float*, float*, float*, hipStream_t);
 
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s) {
   dim3 grid((unsigned)(L.ntiles * L.nmacro));

@@ -557,3 +557,78 @@ void level_coords(const MacroMesh& mm, const Topology& top, const Level& lv, int
 }
 
 }  // namespace stk
+
+namespace stk {
+
+P1Stencil build_p1_stencil(int n) {
+  P1Stencil st;
+  // directions: the node itself, then every vertex difference that occurs in a micro-tet type
+  std::vector<std::array<int, 3>> dirs = {{0, 0, 0}};
+  auto dir_of = [&](int a, int b, int c) {
+    for (size_t d = 0; d < dirs.size(); ++d)
+      if (dirs[d][0] == a && dirs[d][1] == b && dirs[d][2] == c) return (int)d;
+    return -1;
+  };
+  for (int t = 0; t < 6; ++t)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        if (i == j) continue;
+        const int a = TYPE_OFF[t][j][0] - TYPE_OFF[t][i][0], b = TYPE_OFF[t][j][1] - TYPE_OFF[t][i][1],
+                  c = TYPE_OFF[t][j][2] - TYPE_OFF[t][i][2];
+        if (dir_of(a, b, c) < 0) dirs.push_back({a, b, c});
+      }
+  if ((int)dirs.size() != NDIR1) throw std::runtime_error("unexpected lattice edge directions");
+  for (int d = 0; d < NDIR1; ++d)
+    for (int k = 0; k < 3; ++k) st.dir[d][k] = dirs[d][k];
+  const int64_t nloc = (int64_t)(n + 1) * (n + 2) * (n + 3) / 6;
+  st.nb.assign((size_t)NDIR1 * nloc, 0);
+  for (int K = 0; K <= n; ++K)
+    for (int J = 0; J + K <= n; ++J)
+      for (int I = 0; I + J + K <= n; ++I) {
+        const int64_t t = lattice_loc(I, J, K, n);
+        for (int d = 0; d < NDIR1; ++d) {
+          const int a = I + dirs[d][0], b = J + dirs[d][1], c = K + dirs[d][2];
+          const bool in = a >= 0 && b >= 0 && c >= 0 && a + b + c <= n;
+          st.nb[(size_t)d * nloc + t] = (int16_t)(in ? lattice_loc(a, b, c, n) : t);
+        }
+      }
+  // slots: those of a one-strip sweep (exactly the macro-boundary nodes)
+  st.slots = build_sweep(n, 1);
+  st.nsh = st.slots.nsh1;
+  st.dst.assign(nloc, -1);
+  for (size_t e = 0; e < st.slots.plist1.size() / 2; ++e) {
+    const int pk = st.slots.plist1[2 * e];
+    st.dst[lattice_loc(pk & 1023, (pk >> 10) & 1023, pk >> 20, n)] = st.slots.plist1[2 * e + 1];
+  }
+  // micro-tets containing each node, in a fixed order
+  std::vector<std::vector<std::pair<int, int>>> inc(nloc);
+  for (int t = 0; t < 6; ++t) {
+    const int lim = t == 0 ? n - 1 : (t == 5 ? n - 3 : n - 2);
+    for (int pz = 0; pz < n; ++pz)
+      for (int py = 0; py < n; ++py)
+        for (int px = 0; px + py + pz <= lim; ++px) {
+          const int pk = t | (px << 3) | (py << 13) | (pz << 23);
+          for (int v = 0; v < 4; ++v) {
+            int code = v;
+            for (int w = 0; w < 4; ++w) {
+              const int d = dir_of(TYPE_OFF[t][w][0] - TYPE_OFF[t][v][0], TYPE_OFF[t][w][1] - TYPE_OFF[t][v][1],
+                                   TYPE_OFF[t][w][2] - TYPE_OFF[t][v][2]);
+              code |= d << (2 + 4 * w);
+            }
+            inc[lattice_loc(px + TYPE_OFF[t][v][0], py + TYPE_OFF[t][v][1], pz + TYPE_OFF[t][v][2], n)].push_back(
+                {pk, code});
+          }
+        }
+  }
+  st.inc_ptr.assign(1, 0);
+  for (int64_t t = 0; t < nloc; ++t) {
+    for (auto& e : inc[t]) {
+      st.inc.push_back(e.first);
+      st.inc.push_back(e.second);
+    }
+    st.inc_ptr.push_back((int)(st.inc.size() / 2));
+  }
+  return st;
+}
+
+}  // namespace stk

@@ -95,6 +95,22 @@ Sweep build_sweep(int n, int nstrips);
 void build_gather(const MacroMesh& mm, const Level& lv, const Sweep& sw, int which, std::vector<uint32_t>& node,
                   std::vector<int>& ptr, std::vector<int>& slot);
 
+// Lattice tables of the P1 mass stencil of one level (the same for every
+// macro): a P1 lattice node couples with itself and its 14 lattice
+// neighbours; direction 0 is the node itself.
+constexpr int NDIR1 = 15;
+struct P1Stencil {
+  int dir[NDIR1][3];           // lattice offset of each direction
+  std::vector<int16_t> nb;     // [NDIR1][nloc1] neighbour local index, the node itself where absent
+  std::vector<int> dst;        // [nloc1] slot of macro-boundary nodes, -1 for macro-interior ones
+  std::vector<int> inc_ptr;    // [nloc1 + 1] micro-tets containing each node
+  std::vector<int> inc;        // pairs: packed type | px<<3 | py<<13 | pz<<23, and
+                               //        vertex v | (direction of vertex w) << (2 + 4 w)
+  int nsh = 0;                 // slots per macro
+  Sweep slots;                 // one-strip sweep whose P1 slots the stencil shares
+};
+P1Stencil build_p1_stencil(int n);
+
 Level build_level(const MacroMesh& mm, const Topology& top, int L);
 // Blended coordinates (3 per node, nullable) and boundary kinds (nullable) of
 // the P2 (which = 2) or P1 (which = 1) nodes of a level.

@@ -115,6 +115,13 @@ struct LevelData {
   DBuf<uint32_t> g2node, g1node;
   DBuf<double> sl2_64, sl1_64;   // slot buffers of the sweep kernels
   DBuf<float> sl2_32, sl1_32;
+  // P1 mass stencil: lattice tables, gather lists, coefficients, slots
+  DBuf<int16_t> ms_nb;
+  DBuf<int> ms_dst, ms_incptr, ms_inc, ms_gptr, ms_gslot;
+  DBuf<uint32_t> ms_gnode;
+  DBuf<double> ms_c64, ms_sl64;
+  DBuf<float> ms_c32, ms_sl32;
+  template <class R> R* msl();
   double lo = 0, hi = 0;
   bool bounds_set = false;
   Pool<double> p64, q64;   // velocity-size / pressure-size work vectors
@@ -149,6 +156,15 @@ template <> double* LevelData::sl1<double>() {
 template <> float* LevelData::sl1<float>() {
   sl1_32.alloc((size_t)d.nmacro * sw.nsh1);
   return sl1_32.p;
+}
+
+template <> double* LevelData::msl<double>() {
+  ms_sl64.alloc((size_t)d.nmacro * d.ms.nsh);
+  return ms_sl64.p;
+}
+template <> float* LevelData::msl<float>() {
+  ms_sl32.alloc((size_t)d.nmacro * d.ms.nsh);
+  return ms_sl32.p;
 }
 
 // indices into the per-level velocity work pools
@@ -250,7 +266,9 @@ void applyBt(Ctx& c, int l, const R* p, R* y, bool withCt, int bc) {
 }
 template <class R>
 void applyMass(Ctx& c, int l, const R* p, R* q) {
-  sweep<R>(c, l, F_M, nullptr, p, c.at(l).etap<R>(), nullptr, nullptr, q, 0);
+  LevelData& L = c.at(l);
+  if (L.d.ms.on) launch_mass_stencil<R>(L.d, p, q, L.msl<R>(), c.s);
+  else sweep<R>(c, l, F_M, nullptr, p, L.etap<R>(), nullptr, nullptr, q, 0);
 }
 // K [u;p] on the finest level, velocity projected on both sides
 template <class R>
@@ -749,6 +767,30 @@ void upload_level(Ctx& c, int l) {
     L.g1slot.upload(slot);
     d.g1 = GatherDev{(int)node.size(), L.g1node.p, L.g1ptr.p, L.g1slot.p};
   }
+  // P1 mass stencil (used where a macro's P1 lattice fits the LDS staging)
+  {
+    P1Stencil ps = build_p1_stencil(h.n);
+    L.ms_nb.upload(ps.nb);
+    L.ms_dst.upload(ps.dst);
+    L.ms_incptr.upload(ps.inc_ptr);
+    L.ms_inc.upload(ps.inc);
+    std::vector<uint32_t> node;
+    std::vector<int> ptr, slot;
+    build_gather(c.mm, h, ps.slots, 1, node, ptr, slot);
+    L.ms_gnode.upload(node);
+    L.ms_gptr.upload(ptr);
+    L.ms_gslot.upload(slot);
+    StencilDev& m = d.ms;
+    m.on = mass_stencil_lds_bytes((int)h.nloc1, 8) <= 65536;
+    m.nsh = ps.nsh;
+    m.nb = L.ms_nb.p;
+    m.dst = L.ms_dst.p;
+    m.inc_ptr = L.ms_incptr.p;
+    m.inc = (const int2*)L.ms_inc.p;
+    m.c64 = nullptr;
+    m.c32 = nullptr;
+    m.g = GatherDev{(int)node.size(), L.ms_gnode.p, L.ms_gptr.p, L.ms_gslot.p};
+  }
   // boundary lists
   std::vector<uint32_t> dir, fs;
   std::vector<double> nrm;
@@ -862,6 +904,17 @@ void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const s
       L.lo = par->cheb_lo * lam;
       L.hi = par->cheb_hi * lam;
     }
+  }
+  // P1 mass stencils
+  for (int l = c.lmin(); l <= Lf; ++l) {
+    LevelData& L = c.at(l);
+    if (!L.d.ms.on) continue;
+    const size_t nc = (size_t)L.d.nmacro * NDIR1D * L.h.nloc1;
+    L.ms_c64.alloc(nc);
+    L.ms_c32.alloc(nc);
+    L.d.ms.c64 = L.ms_c64.p;
+    L.d.ms.c32 = L.ms_c32.p;
+    launch_mass_stencil_build(L.d, L.eta.p, L.ms_c64.p, L.ms_c32.p, c.s);
   }
   // inverse diagonal of M_{1/eta} (Jacobi preconditioner of its CG)
   {
