@@ -30,6 +30,10 @@ struct SweepDev {
   const int* poff1;    // per strip: n + 2 offsets
   const int* elist;    // packed type | px<<3 | py<<13
   const int* eoff;     // per strip: n + 1 offsets
+  const int4* etab;    // per element: 2 int4 of LDS ring positions and the type (see mesh.hpp)
+  int ne2, ne1;        // plane-list entries per macro (all strips)
+  const uint32_t* g2tab;   // [nmacro][ne2] global P2 node of every plane-list entry
+  const uint32_t* g1tab;   // [nmacro][ne1] global P1 node of every plane-list entry
 };
 struct GatherDev {
   int nnodes;
@@ -74,6 +78,8 @@ struct LevelDev {
   int elemwise;           // 1: element-parallel kernel (coarse levels)
   const int* eall;        // all micro-tets of a macro: type | px<<3 | py<<13 | pz<<23
   StencilDev ms;          // P1 mass stencil
+  const int4* xtab;       // grid-transfer table with this level as the coarse one (2 int4 per entry)
+  const int* xoff;        // per tile: first entry
 };
 
 // Boundary node lists of a level (for vector projections).
@@ -92,6 +98,45 @@ struct BcDev {
 template <typename R>
 void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, const R* p, const R* eta,
                    const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s);
+// LDS layout of the sweep kernel (byte offsets, 16-byte aligned):
+//   sy   [3 cap2][3] double  P2 accumulators             (velocity output)
+//   syp  [2 cap1]    double  P1 accumulators             (pressure-type output)
+//   s1   [2 cap1][4] R       P1 node: x~ (3), eta
+//   sx   [3 cap2][3] R       P2 inputs                   (velocity input)
+//   sp, srho [2 cap1] R      P1 inputs p, ln rho
+//   sg2  [3 cap2], sg1 [2 cap1] int  global node index, or ~slot for shared nodes
+//   sti  [64] R              per-type rows grad lambda_1..3 and |det J_F| of the macro
+struct SweepLds {
+  unsigned sy, syp, s1, sx, sp, srho, sg2, sg1, sti, total;
+};
+__host__ __device__ inline unsigned lds_align16(unsigned x) { return (x + 15u) & ~15u; }
+__host__ __device__ inline SweepLds sweep_lds(int FL, int cap2, int cap1, int rb) {
+  const bool NU = FL & (F_A | F_B | F_C), OU = FL & (F_A | F_BT | F_CT);
+  const bool NP = FL & (F_BT | F_CT | F_M), NR = FL & (F_C | F_CT), OP = FL & (F_B | F_C | F_M);
+  const unsigned c2 = (unsigned)cap2, c1 = (unsigned)cap1, r = (unsigned)rb;
+  SweepLds o;
+  unsigned at = 0;
+  o.sy = at;
+  at = lds_align16(at + (OU ? 9u * c2 * 8u : 0u));
+  o.syp = at;
+  at = lds_align16(at + (OP ? 2u * c1 * 8u : 0u));
+  o.s1 = at;
+  at = lds_align16(at + 8u * c1 * r);
+  o.sx = at;
+  at = lds_align16(at + (NU ? 9u * c2 * r : 0u));
+  o.sp = at;
+  at = lds_align16(at + (NP ? 2u * c1 * r : 0u));
+  o.srho = at;
+  at = lds_align16(at + (NR ? 2u * c1 * r : 0u));
+  o.sg2 = at;
+  at = lds_align16(at + ((NU || OU) ? 3u * c2 * 4u : 0u));
+  o.sg1 = at;
+  at = lds_align16(at + 2u * c1 * 4u);
+  o.sti = at;
+  at = lds_align16(at + 64u * r);
+  o.total = at;
+  return o;
+}
 // LDS bytes of the sweep kernel for a flag set
 size_t sweep_lds_bytes(int flags, int cap2, int cap1, int real_bytes);
 template <typename R>
@@ -113,6 +158,13 @@ template <typename R>
 void launch_prolong(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, int bcmode, hipStream_t s);
 template <typename R>
 void launch_restrict(const LevelDev& Lc, const LevelDev& Lf, const R* rf, R* rc, int bcmode, hipStream_t s);
+// ef += P ec (projected as bcmode & BCM_OUT says)
+template <typename R>
+void launch_prolong_add(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, int bcmode, hipStream_t s);
+// rc = P^T (bf - tf); rc zero-filled by the caller
+template <typename R>
+void launch_restrict_diff(const LevelDev& Lc, const LevelDev& Lf, const R* bf, const R* tf, R* rc, int bcmode,
+                          hipStream_t s);
 template <typename R>
 void launch_inject(const LevelDev& Lc, const LevelDev& Lf, const R* vf, R* vc, hipStream_t s);
 template <typename R>

@@ -46,15 +46,6 @@ __constant__ int c_toff[6][4][3] = {
     {{0, 1, 0}, {1, 0, 1}, {0, 0, 1}, {1, 0, 0}},
     {{1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}},
 };
-// inverse of the integer vertex-difference matrix of each type (unimodular)
-__constant__ int c_tlinv[6][3][3] = {
-    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
-    {{0, 0, 1}, {0, -1, -1}, {1, 1, 0}},
-    {{0, -1, 0}, {1, 1, 0}, {0, 1, 1}},
-    {{1, 0, 0}, {0, 1, 1}, {-1, -1, 0}},
-    {{1, 1, 1}, {-1, -1, 0}, {0, -1, -1}},
-    {{0, -1, 0}, {-1, 0, 0}, {1, 1, 1}},
-};
 
 // local edge e = (EV0[e], EV1[e]); node index 4 + e
 #define EV0(e) ((e) < 3 ? 0 : ((e) < 5 ? 1 : 2))
@@ -233,17 +224,21 @@ struct StokesElem {
   R Sacc[3][4], Dacc[3][4], Eacc[3][6];
   R SV[3], VQ[3][4], SP, DP[4];
 
+  // TI: rows grad lambda_1..3 of the affine micro-tet and |det J_F|;
+  // fx(v, k): coordinate k of reference vertex v (used with blending);
   // fu(c, a): velocity component c at local P2 node a;  f1(v, &eta, &p, &rho): P1 values at vertex v
-  template <class FU, class F1>
-  __device__ __forceinline__ void load(const R* TI, const R* G, int type, int px, int py, int pz, int n, FU fu,
-                                       F1 f1) {
+  template <class FX, class FU, class F1>
+  __device__ __forceinline__ void load(const R* TI, FX fx, FU fu, F1 f1) {
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int k = 0; k < 3; ++k) gl[r][k] = TI[3 * r + k];
     wdetF = R(QW) * TI[9];
     if (BLEND) {
-      elem_vertices<R>(G, type, px, py, pz, n, xv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xv[v][k] = fx(v, k);
 #pragma unroll
       for (int k = 0; k < 3; ++k) xs[k] = xv[0][k] + xv[1][k] + xv[2][k] + xv[3][k];
     }
@@ -436,11 +431,6 @@ struct StokesElem {
 // and are written out while the next planes are staged into their ring slots.
 // Nodes that only this workgroup touches get plain stores; shared nodes
 // (macro boundary, strip boundary rows) go to slots summed by k_gather.
-__device__ __forceinline__ int ppos(int K, int J, int I, int m, int a) {
-  // position of (I, J) in the strip part (rows J >= a) of plane K of a lattice of side m
-  const int s = m - K;
-  return (J - a) * (s + 1) - ((J * (J - 1) - a * (a - 1)) >> 1) + I;
-}
 
 template <typename R, bool BLEND, int FL>
 __global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
@@ -449,19 +439,28 @@ __global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__
                                                R* __restrict__ sl1, int bcmode) {
   using E = StokesElem<R, BLEND, FL>;
   constexpr bool NU = E::NU, NP = E::NP, OU = E::OU, OP = E::OP, NR = E::NR, NE = E::NE;
+  constexpr bool P2 = NU || OU;
   // accumulators are FP64 for both precisions: LDS FP64 atomic adds are far
   // faster than FP32 ones on this hardware (and more accurate)
   using Acc = double;
+  constexpr int NB2 = 4, NB1 = 2;   // plane entries per thread and batch
+  // fetch the first loads of the plane traffic ahead (FP32 A-apply only: it
+  // is limited to three workgroups per CU by LDS anyway; the other variants
+  // would lose occupancy to the extra registers)
+  constexpr bool PF = sizeof(R) == 4 && FL == F_A;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const SweepDev& S = L.sw;
   const int cap2 = S.cap2, cap1 = S.cap1;
-  const int CS = 3 * cap2;   // component stride of the P2 ring
-  Acc* sy = reinterpret_cast<Acc*>(smem_raw);
-  Acc* syp = sy + (OU ? 3 * CS : 0);
-  R* sx = reinterpret_cast<R*>(syp + (OP ? 2 * cap1 : 0));
-  R* seta = sx + (NU ? 3 * CS : 0);
-  R* sp = seta + (NE ? 2 * cap1 : 0);
-  R* srho = sp + (NP ? 2 * cap1 : 0);
+  const SweepLds lay = sweep_lds(FL, cap2, cap1, sizeof(R));
+  Acc* sy = reinterpret_cast<Acc*>(smem_raw + lay.sy);
+  Acc* syp = reinterpret_cast<Acc*>(smem_raw + lay.syp);
+  R* s1 = reinterpret_cast<R*>(smem_raw + lay.s1);
+  R* sx = reinterpret_cast<R*>(smem_raw + lay.sx);
+  R* sp = reinterpret_cast<R*>(smem_raw + lay.sp);
+  R* srho = reinterpret_cast<R*>(smem_raw + lay.srho);
+  int* sg2 = reinterpret_cast<int*>(smem_raw + lay.sg2);
+  int* sg1 = reinterpret_cast<int*>(smem_raw + lay.sg1);
+  R* sti = reinterpret_cast<R*>(smem_raw + lay.sti);
 
   const int strip = blockIdx.x % S.nstrips;
   const int mac = blockIdx.x / S.nstrips;
@@ -470,8 +469,8 @@ __global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__
   const int* poff2 = S.poff2 + strip * (m2 + 2);
   const int* poff1 = S.poff1 + strip * (n + 2);
   const int* eoff = S.eoff + strip * (n + 1);
-  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
-  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const uint32_t* G2t = S.g2tab + (size_t)mac * S.ne2;
+  const uint32_t* G1t = S.g1tab + (size_t)mac * S.ne1;
   const R* G = geo_of<R>(L) + (size_t)mac * 16;
   const uint8_t* bact = L.bact + (size_t)mac * 16;
   const size_t N2 = (size_t)L.n2;
@@ -479,139 +478,243 @@ __global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__
   R* ms2 = sl2 + (size_t)mac * S.nsh2;
   R* ms1 = sl1 + (size_t)mac * S.nsh1;
   const int tid = threadIdx.x, bs = blockDim.x;
+  const R in = R(1) / R(n);
 
-  auto flush2 = [&](int K, int t) {
-    const int2 en = S.plist2[poff2[K] + t];
-    const int pos = (K % 3) * cap2 + t;
-    if (en.y >= 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ms2[en.y + c * SS2] = R(sy[c * CS + pos]);
-    } else {
-      const int I = en.x & 1023, J = (en.x >> 10) & 1023;
-      const size_t g = l2[lloc(I, J, K, m2)];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) yu[g + c * N2] = R(sy[c * CS + pos]);
-    }
-  };
-  auto load2 = [&](int K, int t) {
-    const int2 en = S.plist2[poff2[K] + t];
-    const int pos = (K % 3) * cap2 + t;
-    if (NU) {
-      const int I = en.x & 1023, J = (en.x >> 10) & 1023;
-      const int mask = wmask(I, J, K, m2);
-      const size_t g = l2[lloc(I, J, K, m2)];
-      R v0 = u[g], v1 = u[g + N2], v2 = u[g + 2 * N2];
-      if ((bcmode & BCM_IN) && mask != 15) bc_project<R>(bact[mask], G, I, J, K, m2, v0, v1, v2);
-      sx[pos] = v0;
-      sx[CS + pos] = v1;
-      sx[2 * CS + pos] = v2;
-    }
-    if (OU) {
-      sy[pos] = 0;
-      sy[CS + pos] = 0;
-      sy[2 * CS + pos] = 0;
-    }
-  };
-  auto flush1 = [&](int k, int t) {
-    const int2 en = S.plist1[poff1[k] + t];
-    const int pos = (k & 1) * cap1 + t;
-    if (en.y >= 0) {
-      ms1[en.y] = R(syp[pos]);
-    } else {
-      const int I = en.x & 1023, J = (en.x >> 10) & 1023;
-      yp[l1[lloc(I, J, k, n)]] = R(syp[pos]);
-    }
-  };
-  auto load1 = [&](int k, int t) {
-    const int2 en = S.plist1[poff1[k] + t];
-    const int pos = (k & 1) * cap1 + t;
-    const int I = en.x & 1023, J = (en.x >> 10) & 1023;
-    const size_t g = l1[lloc(I, J, k, n)];
-    if (NE) seta[pos] = eta[g];
-    if (NP) sp[pos] = p[g];
-    if (NR) srho[pos] = lnrho[g];
-    if (OP) syp[pos] = 0;
-  };
-  auto cnt2 = [&](int K) { return K <= m2 ? poff2[K + 1] - poff2[K] : 0; };
-  auto cnt1 = [&](int k) { return k <= n ? poff1[k + 1] - poff1[k] : 0; };
-  constexpr bool P2 = NU || OU;
-  constexpr bool P1 = NE || NP || NR || OP;
+  auto cnt2 = [&](int K) { return (K >= 0 && K <= m2) ? poff2[K + 1] - poff2[K] : 0; };
+  auto cnt1 = [&](int k) { return (k >= 0 && k <= n) ? poff1[k + 1] - poff1[k] : 0; };
 
-  // initial planes
-  if (P2)
-    for (int K = 0; K < 3; ++K)
-      for (int t = tid; t < cnt2(K); t += bs) load2(K, t);
-  if (P1)
-    for (int k = 0; k < 2; ++k)
-      for (int t = tid; t < cnt1(k); t += bs) load1(k, t);
+  // Plane traffic of one step: P2 planes Kf0/Kf1 are written out and planes
+  // Kl0/Kl1 staged into the same ring slots (Kl = Kf mod 3); P1 plane kf is
+  // written out and plane kl staged into its slot.  A thread owns a ring
+  // position for both the write-out and the staging.  Entries are handled in
+  // batches of NB2 (P2) and NB1 (P1) per thread so that each thread issues
+  // all its loads of one kind before it waits for any.  The plane-list entry
+  // and its global node index (first loads) of the first batch may have been
+  // fetched ahead, during the element loop (Pre).
+  struct Pre {
+    int2 e2[NB2];
+    int g2[NB2];
+    int2 e1[NB1];
+    int g1[NB1];
+  };
+  struct Counts {
+    int f0, f1, c0, c1, n0, nn1, slot0, slot1, tot2, ff, cl, tot1, slotp;
+  };
+  auto counts = [&](int Kf0, int Kf1, int Kl0, int Kl1, int kf, int kl) {
+    Counts q;
+    q.f0 = OU ? cnt2(Kf0) : 0;
+    q.f1 = OU ? cnt2(Kf1) : 0;
+    q.c0 = P2 ? cnt2(Kl0) : 0;
+    q.c1 = P2 ? cnt2(Kl1) : 0;
+    q.n0 = q.f0 > q.c0 ? q.f0 : q.c0;
+    q.nn1 = q.f1 > q.c1 ? q.f1 : q.c1;
+    q.slot0 = ((Kl0 >= 0 ? Kl0 : Kf0) % 3) * cap2;
+    q.slot1 = ((Kl1 >= 0 ? Kl1 : Kf1) % 3) * cap2;
+    q.tot2 = P2 ? q.n0 + q.nn1 : 0;
+    q.ff = OP ? cnt1(kf) : 0;
+    q.cl = cnt1(kl);
+    q.tot1 = q.ff > q.cl ? q.ff : q.cl;
+    q.slotp = ((kl >= 0 ? kl : kf) & 1) * cap1;
+    return q;
+  };
+  // plane-list index of the entry a P2 item stages (-1: none)
+  auto item2 = [&](const Counts& q, int t, int Kl0, int Kl1, int& pos, int& K, int& q_, bool& b) {
+    b = t >= q.n0;
+    q_ = b ? t - q.n0 : t;
+    pos = (b ? q.slot1 : q.slot0) + q_;
+    K = b ? Kl1 : Kl0;
+    return (t < q.tot2 && q_ < (b ? q.c1 : q.c0)) ? poff2[K] + q_ : -1;
+  };
+  auto fetch = [&](Pre& pf, int Kf0, int Kf1, int Kl0, int Kl1, int kf, int kl) {
+    const Counts q = counts(Kf0, Kf1, Kl0, Kl1, kf, kl);
+#pragma unroll
+    for (int i = 0; i < NB2; ++i) {
+      int pos, K, qq;
+      bool b;
+      const int lt = item2(q, i * bs + tid, Kl0, Kl1, pos, K, qq, b);
+      pf.e2[i] = lt >= 0 ? S.plist2[lt] : make_int2(0, -1);
+      pf.g2[i] = lt >= 0 ? (int)G2t[lt] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < NB1; ++i) {
+      const int t = i * bs + tid;
+      const int lt = (t < q.tot1 && t < q.cl) ? poff1[kl] + t : -1;
+      pf.e1[i] = lt >= 0 ? S.plist1[lt] : make_int2(0, -1);
+      pf.g1[i] = lt >= 0 ? (int)G1t[lt] : -1;
+    }
+  };
+  auto planes = [&](int Kf0, int Kf1, int Kl0, int Kl1, int kf, int kl, const Pre* pre) {
+    const Counts q = counts(Kf0, Kf1, Kl0, Kl1, kf, kl);
+    for (int base2 = 0, base1 = 0; base2 < q.tot2 || base1 < q.tot1; base2 += NB2 * bs, base1 += NB1 * bs) {
+      const bool usepre = pre != nullptr && base2 == 0;
+      int pos2[NB2], lt2[NB2], K2[NB2];
+      int pos1[NB1], lt1[NB1];
+#pragma unroll
+      for (int i = 0; i < NB2; ++i) {
+        const int t = base2 + i * bs + tid;
+        int qq;
+        bool b;
+        lt2[i] = item2(q, t, Kl0, Kl1, pos2[i], K2[i], qq, b);
+        if (OU && t < q.tot2 && qq < (b ? q.f1 : q.f0)) {   // write out the completed node
+          const int pos = pos2[i];
+          const int g = sg2[pos];
+          if (g >= 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yu[(size_t)g + c * N2] = R(sy[3 * pos + c]);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ms2[(size_t)(~g) + c * SS2] = R(sy[3 * pos + c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NB1; ++i) {
+        const int t = base1 + i * bs + tid;
+        pos1[i] = q.slotp + t;
+        lt1[i] = -1;
+        if (t < q.tot1) {
+          const int pos = pos1[i];
+          if (OP && t < q.ff) {
+            const int g = sg1[pos];
+            if (g >= 0) yp[g] = R(syp[pos]);
+            else ms1[~g] = R(syp[pos]);
+          }
+          if (t < q.cl) lt1[i] = poff1[kl] + t;
+        }
+      }
+      // plane-list entries and global node indices (fetched ahead for the first batch)
+      int2 en2[NB2], en1[NB1];
+      int g2[NB2], g1[NB1];
+      if (usepre) {
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+          en2[i] = pre->e2[i];
+          g2[i] = pre->g2[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NB1; ++i) {
+          en1[i] = pre->e1[i];
+          g1[i] = pre->g1[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+          en2[i] = lt2[i] >= 0 ? S.plist2[lt2[i]] : make_int2(0, -1);
+          g2[i] = lt2[i] >= 0 ? (int)G2t[lt2[i]] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < NB1; ++i) {
+          en1[i] = lt1[i] >= 0 ? S.plist1[lt1[i]] : make_int2(0, -1);
+          g1[i] = lt1[i] >= 0 ? (int)G1t[lt1[i]] : 0;
+        }
+      }
+      // values
+      R v2[NB2][3], e1v[NB1], p1v[NB1], r1v[NB1];
+#pragma unroll
+      for (int i = 0; i < NB2; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v2[i][c] = (NU && lt2[i] >= 0) ? u[(size_t)g2[i] + c * N2] : R(0);
+#pragma unroll
+      for (int i = 0; i < NB1; ++i) {
+        e1v[i] = (NE && lt1[i] >= 0) ? eta[g1[i]] : R(0);
+        p1v[i] = (NP && lt1[i] >= 0) ? p[g1[i]] : R(0);
+        r1v[i] = (NR && lt1[i] >= 0) ? lnrho[g1[i]] : R(0);
+      }
+      // into the ring
+#pragma unroll
+      for (int i = 0; i < NB2; ++i) {
+        if (lt2[i] < 0) continue;
+        const int pos = pos2[i];
+        if (NU) {
+          const int I = en2[i].x & 1023, J = (en2[i].x >> 10) & 1023;
+          const int mask = wmask(I, J, K2[i], m2);
+          if ((bcmode & BCM_IN) && mask != 15) bc_project<R>(bact[mask], G, I, J, K2[i], m2, v2[i][0], v2[i][1], v2[i][2]);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sx[3 * pos + c] = v2[i][c];
+        }
+        if (OU) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sy[3 * pos + c] = 0;
+        }
+        sg2[pos] = en2[i].y >= 0 ? ~en2[i].y : g2[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NB1; ++i) {
+        if (lt1[i] < 0) continue;
+        const int pos = pos1[i];
+        const int I = en1[i].x & 1023, J = (en1[i].x >> 10) & 1023;
+        const R a = R(I) * in, b = R(J) * in, cc = R(kl) * in;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) s1[4 * pos + r] = G[r] + G[3 + 3 * r] * a + G[4 + 3 * r] * b + G[5 + 3 * r] * cc;
+        s1[4 * pos + 3] = e1v[i];
+        if (NP) sp[pos] = p1v[i];
+        if (NR) srho[pos] = r1v[i];
+        if (OP) syp[pos] = 0;
+        sg1[pos] = en1[i].y >= 0 ? ~en1[i].y : g1[i];
+      }
+    }
+  };
+
+  // per-type affine data of this macro, and the first planes
+  {
+    const R* TIg = tinv_of<R>(L) + (size_t)mac * 60;
+    for (int i = tid; i < 60; i += bs) sti[i] = TIg[i];
+  }
+  planes(-1, -1, 0, 1, -1, 0, nullptr);
+  planes(-1, -1, 2, -1, -1, 1, nullptr);
   __syncthreads();
+  Pre pf;
 
   const int kmax = n - 1 - j0;
   for (int k = 0; k <= kmax; ++k) {
-    // micro-tets of layer k
+    // micro-tets of layer k; the next element's table entry is fetched one
+    // iteration ahead
     const int e1 = eoff[k + 1];
-    for (int ei = eoff[k] + tid; ei < e1; ei += bs) {
-      const int pk = S.elist[ei];
-      const int type = pk & 7, px = (pk >> 3) & 1023, py = pk >> 13;
-      ElemIdx e;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], kk = k + c_toff[type][v][2];
-        e.n1i[v] = (kk & 1) * cap1 + ppos(kk, J, I, n, j0);
-        e.n2i[v] = ((2 * kk) % 3) * cap2 + ppos(2 * kk, 2 * J, 2 * I, m2, 2 * j0);
+    int ei = eoff[k] + tid;
+    int4 ta = make_int4(0, 0, 0, 0), tb = ta;
+    if (ei < e1) {
+      ta = S.etab[2 * ei];
+      tb = S.etab[2 * ei + 1];
+    }
+    // first loads of the next plane traffic, in flight during the element loop
+    if (PF) fetch(pf, 2 * k, 2 * k + 1, 2 * k + 3, 2 * k + 4, k, k + 2);
+    for (; ei < e1; ei += bs) {
+      const int4 ca = ta, cb = tb;
+      if (ei + bs < e1) {
+        ta = S.etab[2 * (ei + bs)];
+        tb = S.etab[2 * (ei + bs) + 1];
       }
+      const unsigned w[7] = {(unsigned)ca.x, (unsigned)ca.y, (unsigned)ca.z, (unsigned)ca.w,
+                             (unsigned)cb.x, (unsigned)cb.y, (unsigned)cb.z};
+      int n2i[10], n1i[4];
 #pragma unroll
-      for (int ed = 0; ed < 6; ++ed) {
-        const int i = EV0(ed), j = EV1(ed);
-        const int I = 2 * px + c_toff[type][i][0] + c_toff[type][j][0];
-        const int J = 2 * py + c_toff[type][i][1] + c_toff[type][j][1];
-        const int K = 2 * k + c_toff[type][i][2] + c_toff[type][j][2];
-        e.n2i[4 + ed] = (K % 3) * cap2 + ppos(K, J, I, m2, 2 * j0);
-      }
+      for (int a = 0; a < 10; ++a) n2i[a] = (a & 1) ? (int)(w[a >> 1] >> 16) : (int)(w[a >> 1] & 0xffffu);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) n1i[v] = (v & 1) ? (int)(w[5 + (v >> 1)] >> 16) : (int)(w[5 + (v >> 1)] & 0xffffu);
+      const int type = cb.w;
       E el;
       el.load(
-          tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, G, type, px, py, k, n,
-          [&](int c, int a) { return sx[c * CS + e.n2i[a]]; },
+          sti + type * 10, [&](int v, int r) { return s1[4 * n1i[v] + r]; },
+          [&](int c, int a) { return sx[3 * n2i[a] + c]; },
           [&](int v, R& ev, R& pv, R& rv) {
-            if (NE) ev = seta[e.n1i[v]];
-            if (NP) pv = sp[e.n1i[v]];
-            if (NR) rv = srho[e.n1i[v]];
+            if (NE) ev = s1[4 * n1i[v] + 3];
+            if (NP) pv = sp[n1i[v]];
+            if (NR) rv = srho[n1i[v]];
           });
       el.template qp<0>(G);
       el.template qp<1>(G);
       el.template qp<2>(G);
       el.template qp<3>(G);
-      el.store([&](int c, int a, R v) { ldsadd(sy + c * CS + e.n2i[a], Acc(v)); },
-               [&](int v, R val) { ldsadd(syp + e.n1i[v], Acc(val)); });
+      el.store([&](int c, int a, R v) { ldsadd(sy + 3 * n2i[a] + c, Acc(v)); },
+               [&](int v, R val) { ldsadd(syp + n1i[v], Acc(val)); });
     }
     __syncthreads();
-    // write out completed planes, stage the next ones into the freed slots
-    if (P2) {
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const int Ko = 2 * k + d, Kn = 2 * k + 3 + d;
-        const int co = OU ? cnt2(Ko) : 0, cn = cnt2(Kn);
-        const int cm = co > cn ? co : cn;
-        for (int t = tid; t < cm; t += bs) {
-          if (t < co) flush2(Ko, t);
-          if (t < cn) load2(Kn, t);
-        }
-      }
-    }
-    if (P1) {
-      const int co = OP ? cnt1(k) : 0, cn = cnt1(k + 2);
-      const int cm = co > cn ? co : cn;
-      for (int t = tid; t < cm; t += bs) {
-        if (t < co) flush1(k, t);
-        if (t < cn) load1(k + 2, t);
-      }
-    }
+    // write out the completed planes, stage the next ones into their slots
+    planes(2 * k, 2 * k + 1, 2 * k + 3, 2 * k + 4, k, k + 2, PF ? &pf : nullptr);
     __syncthreads();
   }
-  if (OU)
-    for (int t = tid; t < cnt2(2 * kmax + 2); t += bs) flush2(2 * kmax + 2, t);
-  if (OP)
-    for (int t = tid; t < cnt1(kmax + 1); t += bs) flush1(kmax + 1, t);
+  // last planes (P2 plane 2 kmax + 2, P1 plane kmax + 1)
+  planes(2 * kmax + 2, -1, -1, -1, kmax + 1, -1, nullptr);
 }
 
 // Element-parallel variant for coarse levels (few micro-tets per macro): one
@@ -653,9 +756,11 @@ __global__ __launch_bounds__(256) void k_elemwise(LevelDev L, const R* __restric
   }
 #pragma unroll
   for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+  R xv[4][3];
+  if (BLEND) elem_vertices<R>(G, type, px, py, pz, n, xv);
   E el;
   el.load(
-      tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, G, type, px, py, pz, n,
+      tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, [&](int v, int k) { return xv[v][k]; },
       [&](int c, int a) {
         R v[3] = {u[g2[a]], u[g2[a] + N2], u[g2[a] + 2 * N2]};
         if (bcmode & BCM_IN) bc_project<R>(bact[wmask(I2[a], J2[a], K2[a], m2)], G, I2[a], J2[a], K2[a], m2, v[0], v[1], v[2]);
@@ -1169,43 +1274,18 @@ __global__ __launch_bounds__(384) void k_rhs_grad(LevelDev L, const double* __re
 // quarter units; its coarse micro-tet is "up" for |f| <= 4, one of the four
 // octahedron tets for 4 < |f| <= 8 (first one containing it), "down" above.
 // Prolongation evaluates the coarse P2 basis there (weights are multiples of
-// 1/8); restriction is the transpose.  Each fine node is handled by the brick
-// of its coarse cube in its owning macro only.
-struct Bary4 {
-  int type, q[4];   // barycentric coordinates times 4
-};
-
-__device__ __forceinline__ Bary4 locate(int fx, int fy, int fz) {
-  Bary4 b;
-  const int s = fx + fy + fz;
-  int t0, t1;
-  if (s <= 4) { t0 = 0; t1 = 0; }
-  else if (s <= 8) { t0 = 1; t1 = 4; }
-  else { t0 = 5; t1 = 5; }
-  for (int t = t0; t <= t1; ++t) {
-    const int rx = fx - 4 * c_toff[t][0][0], ry = fy - 4 * c_toff[t][0][1], rz = fz - 4 * c_toff[t][0][2];
-    int l1 = c_tlinv[t][0][0] * rx + c_tlinv[t][0][1] * ry + c_tlinv[t][0][2] * rz;
-    int l2 = c_tlinv[t][1][0] * rx + c_tlinv[t][1][1] * ry + c_tlinv[t][1][2] * rz;
-    int l3 = c_tlinv[t][2][0] * rx + c_tlinv[t][2][1] * ry + c_tlinv[t][2][2] * rz;
-    int l0 = 4 - l1 - l2 - l3;
-    b.type = t;
-    b.q[0] = l0; b.q[1] = l1; b.q[2] = l2; b.q[3] = l3;
-    if (l0 >= 0 && l1 >= 0 && l2 >= 0 && l3 >= 0) break;
-  }
-  return b;
-}
-
-// P2 basis values times 8 at barycentric coordinates q/4
-__device__ __forceinline__ void p2w8(const int q[4], int w[10]) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) w[i] = q[i] * (q[i] - 2);       // 8 * lam(2 lam - 1)
-#pragma unroll
-  for (int e = 0; e < 6; ++e) w[4 + e] = 2 * q[EV0(e)] * q[EV1(e)];   // 8 * 4 lam_i lam_j
-}
-
-template <typename R, int MODE>   // MODE 0 prolongation, 1 restriction
+// 1/8, tabulated per level on the host); restriction is the transpose.  Each
+// fine node is handled by the brick of its coarse cube in its owning macro
+// only.
+// MODE 0: out = P in;  1: out = P^T in;  2: out += P in;  3: out = P^T (in - in2).
+// One workgroup per (macro, coarse brick): the brick's coarse P2 values are
+// staged in LDS (prolongation) or accumulated there in FP64 (restriction);
+// the fine points of the brick and their nonzero coarse weights come from the
+// level's transfer table.
+template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, const R* __restrict__ in,
-                                                  R* __restrict__ out, int bcmode) {
+                                                  const R* __restrict__ in2, R* __restrict__ out, int bcmode) {
+  constexpr bool PRO = MODE == 0 || MODE == 2;
   __shared__ double sc[3 * NB2];   // FP64 staging / accumulation (fast LDS atomics)
   const int tile = blockIdx.x % Lc.ntiles;
   const int mac = blockIdx.x / Lc.ntiles;
@@ -1221,7 +1301,7 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
     const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
     const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
     R v0 = 0, v1 = 0, v2 = 0;
-    if (MODE == 0 && I + J + K <= mc2) {
+    if (PRO && I + J + K <= mc2) {
       const size_t g = l2c[lloc(I, J, K, mc2)];
       v0 = in[g];
       v1 = in[g + Nc];
@@ -1232,54 +1312,64 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
     sc[2 * NB2 + i] = v2;
   }
   __syncthreads();
-  const int lo[3] = {ox > 0 ? 1 : 0, oy > 0 ? 1 : 0, oz > 0 ? 1 : 0};
-  for (int i = threadIdx.x; i < BF * BF * BF; i += blockDim.x) {
-    const int ax = i % BF, ay = (i / BF) % BF, az = i / (BF * BF);
-    if (ax < lo[0] || ay < lo[1] || az < lo[2]) continue;
-    const int JX = 4 * ox + ax, JY = 4 * oy + ay, JZ = 4 * oz + az;
-    if (JX + JY + JZ > mf2) continue;
+  const int e1 = Lc.xoff[tile + 1];
+  for (int e = Lc.xoff[tile] + threadIdx.x; e < e1; e += blockDim.x) {
+    const int4 ta = Lc.xtab[2 * e], tb = Lc.xtab[2 * e + 1];
+    const int JX = ta.x & 1023, JY = (ta.x >> 10) & 1023, JZ = (ta.x >> 20) & 1023;
     const int mask = wmask(JX, JY, JZ, mf2);
     if (!own[mask]) continue;
-    // coarse cube and local quarter position
-    const int px = JX > 0 ? (JX - 1) >> 2 : 0, py = JY > 0 ? (JY - 1) >> 2 : 0, pz = JZ > 0 ? (JZ - 1) >> 2 : 0;
-    const Bary4 b = locate(JX - 4 * px, JY - 4 * py, JZ - 4 * pz);
-    int w[10];
-    p2w8(b.q, w);
-    ElemIdx e;
-    elem_indices(b.type, px - ox, py - oy, pz - oz, e);
+    const int nnz = ta.y;
+    const unsigned wd[5] = {(unsigned)ta.z, (unsigned)ta.w, (unsigned)tb.x, (unsigned)tb.y, (unsigned)tb.z};
     const size_t gf = l2f[lloc(JX, JY, JZ, mf2)];
-    if (MODE == 0) {
-      R v[3];
+    if (PRO) {
+      R v[3] = {0, 0, 0};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        R s = 0;
+      for (int j = 0; j < 10; ++j) {
+        if (j < nnz) {
+          const unsigned f = (wd[j >> 1] >> (16 * (j & 1))) & 0x3fffu;
+          const int idx = (int)(f & 1023u), w = (int)(f >> 10) - 1;
 #pragma unroll
-        for (int a = 0; a < 10; ++a)
-          if (w[a]) s += R(w[a]) * R(sc[c * NB2 + e.n2i[a]]);
-        v[c] = s * R(0.125);
+          for (int c = 0; c < 3; ++c) v[c] += R(w) * R(sc[c * NB2 + idx]);
+        }
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] *= R(0.125);
       if (bcmode & BCM_OUT) {
         // fine node class = coarse sub-simplex class (same macro, nested)
         const int act = Lf.bact[(size_t)mac * 16 + mask];
         bc_project<R>(act, G, JX, JY, JZ, mf2, v[0], v[1], v[2]);
       }
-      out[gf] = v[0];
-      out[gf + Nf] = v[1];
-      out[gf + 2 * Nf] = v[2];
+      if (MODE == 2) {
+        out[gf] += v[0];
+        out[gf + Nf] += v[1];
+        out[gf + 2 * Nf] += v[2];
+      } else {
+        out[gf] = v[0];
+        out[gf + Nf] = v[1];
+        out[gf + 2 * Nf] = v[2];
+      }
     } else {
       R v0 = in[gf], v1 = in[gf + Nf], v2 = in[gf + 2 * Nf];
+      if (MODE == 3) {
+        v0 -= in2[gf];
+        v1 -= in2[gf + Nf];
+        v2 -= in2[gf + 2 * Nf];
+      }
       if (bcmode & BCM_IN) bc_project<R>(Lf.bact[(size_t)mac * 16 + mask], G, JX, JY, JZ, mf2, v0, v1, v2);
 #pragma unroll
-      for (int a = 0; a < 10; ++a) {
-        if (!w[a]) continue;
-        const double f = w[a] * 0.125;
-        ldsadd(sc + e.n2i[a], f * double(v0));
-        ldsadd(sc + NB2 + e.n2i[a], f * double(v1));
-        ldsadd(sc + 2 * NB2 + e.n2i[a], f * double(v2));
+      for (int j = 0; j < 10; ++j) {
+        if (j < nnz) {
+          const unsigned f = (wd[j >> 1] >> (16 * (j & 1))) & 0x3fffu;
+          const int idx = (int)(f & 1023u);
+          const double wf = ((int)(f >> 10) - 1) * 0.125;
+          ldsadd(sc + idx, wf * double(v0));
+          ldsadd(sc + NB2 + idx, wf * double(v1));
+          ldsadd(sc + 2 * NB2 + idx, wf * double(v2));
+        }
       }
     }
   }
-  if (MODE == 1) {
+  if (!PRO) {
     __syncthreads();
     for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
       const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
@@ -1627,14 +1717,7 @@ static inline int vgrid(long long n) {
   return (int)g;
 }
 
-size_t sweep_lds_bytes(int FL, int cap2, int cap1, int rb) {
-  const bool NU = FL & (F_A | F_B | F_C), OU = FL & (F_A | F_BT | F_CT);
-  const bool NE = FL & (F_A | F_M), NP = FL & (F_BT | F_CT | F_M), NR = FL & (F_C | F_CT), OP = FL & (F_B | F_C | F_M);
-  // FP64 accumulators, inputs in the working precision
-  size_t acc = (OU ? 9 * (size_t)cap2 : 0) + (OP ? 2 * (size_t)cap1 : 0);
-  size_t in = (NU ? 9 * (size_t)cap2 : 0) + 2 * (size_t)cap1 * ((NE ? 1 : 0) + (NP ? 1 : 0) + (NR ? 1 : 0));
-  return acc * 8 + in * rb;
-}
+size_t sweep_lds_bytes(int FL, int cap2, int cap1, int rb) { return sweep_lds(FL, cap2, cap1, rb).total; }
 
 template <typename R, int FL>
 static void stokes_dispatch(const LevelDev& L, const R* u, const R* p, const R* eta, const R* lnrho, R* yu, R* yp,
@@ -1751,13 +1834,30 @@ void launch_gradient(const LevelDev& L, const double* eta, const double* u, cons
 template <typename R>
 void launch_prolong(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, int bcmode, hipStream_t s) {
   dim3 grid((unsigned)(Lc.ntiles * Lc.nmacro));
-  hipLaunchKernelGGL((k_transfer<R, 0>), grid, dim3(256), 0, s, Lc, Lf, ec, ef, bcmode);
+  hipLaunchKernelGGL((k_transfer<R, 0>), grid, dim3(256), 0, s, Lc, Lf, ec, nullptr, ef, bcmode);
 }
 template <typename R>
 void launch_restrict(const LevelDev& Lc, const LevelDev& Lf, const R* rf, R* rc, int bcmode, hipStream_t s) {
   dim3 grid((unsigned)(Lc.ntiles * Lc.nmacro));
-  hipLaunchKernelGGL((k_transfer<R, 1>), grid, dim3(256), 0, s, Lc, Lf, rf, rc, bcmode);
+  hipLaunchKernelGGL((k_transfer<R, 1>), grid, dim3(256), 0, s, Lc, Lf, rf, nullptr, rc, bcmode);
 }
+template <typename R>
+void launch_prolong_add(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, int bcmode, hipStream_t s) {
+  dim3 grid((unsigned)(Lc.ntiles * Lc.nmacro));
+  hipLaunchKernelGGL((k_transfer<R, 2>), grid, dim3(256), 0, s, Lc, Lf, ec, nullptr, ef, bcmode);
+}
+template <typename R>
+void launch_restrict_diff(const LevelDev& Lc, const LevelDev& Lf, const R* bf, const R* tf, R* rc, int bcmode,
+                          hipStream_t s) {
+  dim3 grid((unsigned)(Lc.ntiles * Lc.nmacro));
+  hipLaunchKernelGGL((k_transfer<R, 3>), grid, dim3(256), 0, s, Lc, Lf, bf, tf, rc, bcmode);
+}
+template void launch_prolong_add<double>(const LevelDev&, const LevelDev&, const double*, double*, int, hipStream_t);
+template void launch_prolong_add<float>(const LevelDev&, const LevelDev&, const float*, float*, int, hipStream_t);
+template void launch_restrict_diff<double>(const LevelDev&, const LevelDev&, const double*, const double*, double*,
+                                           int, hipStream_t);
+template void launch_restrict_diff<float>(const LevelDev&, const LevelDev&, const float*, const float*, float*, int,
+                                          hipStream_t);
 template void launch_prolong<double>(const LevelDev&, const LevelDev&, const double*, double*, int, hipStream_t);
 template void launch_prolong<float>(const LevelDev&, const LevelDev&, const float*, float*, int, hipStream_t);
 template void launch_restrict<double>(const LevelDev&, const LevelDev&, const double*, double*, int, hipStream_t);

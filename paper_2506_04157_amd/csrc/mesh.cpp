@@ -480,6 +480,39 @@ Sweep build_sweep(int n, int nstrips) {
   }
   sw.nsh2 = nsh2;
   sw.nsh1 = nsh1;
+  // LDS ring positions of every element's nodes: position of (I, J) within the
+  // strip part (rows J >= a) of plane K of a lattice of side m, plus the slot
+  if (3 * sw.cap2 > 65535 || 2 * sw.cap1 > 65535) throw std::runtime_error("sweep ring exceeds 16-bit positions");
+  auto ppos = [](int K, int J, int I, int m, int a) {
+    const int s = m - K;
+    return (J - a) * (s + 1) - (J * (J - 1) - a * (a - 1)) / 2 + I;
+  };
+  sw.etab.reserve(sw.elist.size() * 8);
+  for (int st = 0; st < sw.nstrips; ++st) {
+    const int j0 = cuts[st];
+    for (int k = 0; k < n; ++k)
+      for (int e = sw.eoff[st * (n + 1) + k]; e < sw.eoff[st * (n + 1) + k + 1]; ++e) {
+        const int pk = sw.elist[e];
+        const int t = pk & 7, px = (pk >> 3) & 1023, py = pk >> 13;
+        int p2[10], p1[4];
+        for (int v = 0; v < 4; ++v) {
+          const int I = px + TYPE_OFF[t][v][0], J = py + TYPE_OFF[t][v][1], K = k + TYPE_OFF[t][v][2];
+          p1[v] = (K % 2) * sw.cap1 + ppos(K, J, I, n, j0);
+          p2[v] = ((2 * K) % 3) * sw.cap2 + ppos(2 * K, 2 * J, 2 * I, m2, 2 * j0);
+        }
+        for (int ed = 0; ed < 6; ++ed) {
+          const int a = EDGE_V[ed][0], b = EDGE_V[ed][1];
+          const int I = 2 * px + TYPE_OFF[t][a][0] + TYPE_OFF[t][b][0];
+          const int J = 2 * py + TYPE_OFF[t][a][1] + TYPE_OFF[t][b][1];
+          const int K = 2 * k + TYPE_OFF[t][a][2] + TYPE_OFF[t][b][2];
+          p2[4 + ed] = (K % 3) * sw.cap2 + ppos(K, J, I, m2, 2 * j0);
+        }
+        for (int w = 0; w < 5; ++w) sw.etab.push_back(p2[2 * w] | (p2[2 * w + 1] << 16));
+        sw.etab.push_back(p1[0] | (p1[1] << 16));
+        sw.etab.push_back(p1[2] | (p1[3] << 16));
+        sw.etab.push_back(t);
+      }
+  }
   return sw;
 }
 
@@ -629,6 +662,85 @@ P1Stencil build_p1_stencil(int n) {
     st.inc_ptr.push_back((int)(st.inc.size() / 2));
   }
   return st;
+}
+
+}  // namespace stk
+
+namespace stk {
+
+TransferTable build_transfer_table(const Level& coarse) {
+  TransferTable tt;
+  const int nc = coarse.n, mf2 = 4 * nc;
+  constexpr int B2h = 2 * TILE + 1, BFh = 4 * TILE + 1;
+  // inverse of the (unimodular) vertex-difference matrix of each type
+  int tinv[6][3][3];
+  for (int t = 0; t < 6; ++t) {
+    double M[3][3], Mi[3][3], det;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) M[r][c] = TYPE_OFF[t][c + 1][r] - TYPE_OFF[t][0][r];
+    inv3(M, Mi, &det);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) tinv[t][r][c] = (int)std::lround(Mi[r][c]);
+  }
+  const int ntiles = (int)coarse.tiles.size() / 3;
+  for (int ti = 0; ti < ntiles; ++ti) {
+    tt.off.push_back((int)(tt.tab.size() / 8));
+    const int ox = coarse.tiles[3 * ti], oy = coarse.tiles[3 * ti + 1], oz = coarse.tiles[3 * ti + 2];
+    const int lox = ox > 0, loy = oy > 0, loz = oz > 0;
+    for (int az = loz; az < BFh; ++az)
+      for (int ay = loy; ay < BFh; ++ay)
+        for (int ax = lox; ax < BFh; ++ax) {
+          const int JX = 4 * ox + ax, JY = 4 * oy + ay, JZ = 4 * oz + az;
+          if (JX + JY + JZ > mf2) continue;
+          // coarse cube and quarter position inside it
+          const int px = JX > 0 ? (JX - 1) >> 2 : 0, py = JY > 0 ? (JY - 1) >> 2 : 0, pz = JZ > 0 ? (JZ - 1) >> 2 : 0;
+          const int fx = JX - 4 * px, fy = JY - 4 * py, fz = JZ - 4 * pz;
+          const int sum = fx + fy + fz;
+          const int t0 = sum <= 4 ? 0 : (sum <= 8 ? 1 : 5), t1 = sum <= 4 ? 0 : (sum <= 8 ? 4 : 5);
+          int type = -1, q[4] = {0, 0, 0, 0};
+          for (int t = t0; t <= t1 && type < 0; ++t) {
+            const int rx = fx - 4 * TYPE_OFF[t][0][0], ry = fy - 4 * TYPE_OFF[t][0][1], rz = fz - 4 * TYPE_OFF[t][0][2];
+            int l[4];
+            for (int r = 0; r < 3; ++r) l[r + 1] = tinv[t][r][0] * rx + tinv[t][r][1] * ry + tinv[t][r][2] * rz;
+            l[0] = 4 - l[1] - l[2] - l[3];
+            if (l[0] >= 0 && l[1] >= 0 && l[2] >= 0 && l[3] >= 0) {
+              type = t;
+              for (int r = 0; r < 4; ++r) q[r] = l[r];
+            }
+          }
+          if (type < 0) throw std::runtime_error("transfer table: point outside every coarse micro-tet");
+          // P2 basis values times 8, and the brick-local indices of the coarse nodes
+          int w[10], idx[10];
+          for (int i = 0; i < 4; ++i) w[i] = q[i] * (q[i] - 2);
+          for (int e = 0; e < 6; ++e) w[4 + e] = 2 * q[EDGE_V[e][0]] * q[EDGE_V[e][1]];
+          const int cx = px - ox, cy = py - oy, cz = pz - oz;
+          for (int v = 0; v < 4; ++v) {
+            const int a = 2 * (cx + TYPE_OFF[type][v][0]), b = 2 * (cy + TYPE_OFF[type][v][1]),
+                      c = 2 * (cz + TYPE_OFF[type][v][2]);
+            idx[v] = a + B2h * (b + B2h * c);
+          }
+          for (int e = 0; e < 6; ++e) {
+            const int i = EDGE_V[e][0], j = EDGE_V[e][1];
+            const int a = 2 * cx + TYPE_OFF[type][i][0] + TYPE_OFF[type][j][0];
+            const int b = 2 * cy + TYPE_OFF[type][i][1] + TYPE_OFF[type][j][1];
+            const int c = 2 * cz + TYPE_OFF[type][i][2] + TYPE_OFF[type][j][2];
+            idx[4 + e] = a + B2h * (b + B2h * c);
+          }
+          int packed[10], nnz = 0;
+          for (int a = 0; a < 10; ++a)
+            if (w[a] != 0) {
+              if (idx[a] < 0 || idx[a] >= B2h * B2h * B2h) throw std::runtime_error("transfer table: index");
+              packed[nnz++] = idx[a] | ((w[a] + 1) << 10);
+            }
+          for (int a = nnz; a < 10; ++a) packed[a] = 0;
+          tt.tab.push_back(JX | (JY << 10) | (JZ << 20));
+          tt.tab.push_back(nnz);
+          for (int k = 0; k < 5; ++k) tt.tab.push_back(packed[2 * k] | (packed[2 * k + 1] << 16));
+          tt.tab.push_back(0);
+        }
+  }
+  tt.off.push_back((int)(tt.tab.size() / 8));
+  return tt;
 }
 
 }  // namespace stk

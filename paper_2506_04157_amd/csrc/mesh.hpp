@@ -86,6 +86,11 @@ struct Sweep {
   std::vector<int> plist2, poff2, plist1, poff1;
   // elements per (strip, layer): packed type | px<<3 | py<<13
   std::vector<int> elist, eoff;
+  // per element (same order as elist), 8 ints: the LDS ring positions of its
+  // 10 P2 nodes (16 bits each, vertices then edges 01,02,03,12,13,23; words
+  // 0-4), of its 4 P1 vertices (words 5-6), and its type (word 7).  P2 plane K
+  // lives in ring slot K % 3 (cap2 entries each), P1 plane k in slot k % 2.
+  std::vector<int> etab;
   int nsh2 = 0, nsh1 = 0;      // shared slots per macro
   int cap2 = 0, cap1 = 0;      // largest plane list (LDS ring slot size)
 };
@@ -110,6 +115,19 @@ struct P1Stencil {
   Sweep slots;                 // one-strip sweep whose P1 slots the stencil shares
 };
 P1Stencil build_p1_stencil(int n);
+
+// Grid-transfer table of a coarse level (the same for every macro): for each
+// brick (tile) of the coarse level, the fine P2 lattice points it handles, in
+// lattice order, with the coarse P2 nodes whose basis functions are nonzero
+// there.  8 ints per entry: fine point I | J<<10 | K<<20; number of nonzero
+// weights (<= 10); five words of two 16-bit fields (brick-local coarse node
+// index, 10 bits | (8 * weight + 1) << 10), in the coarse micro-tet's node
+// order; padding.
+struct TransferTable {
+  std::vector<int> tab;
+  std::vector<int> off;   // per tile: first entry (ntiles + 1)
+};
+TransferTable build_transfer_table(const Level& coarse);
 
 Level build_level(const MacroMesh& mm, const Topology& top, int L);
 // Blended coordinates (3 per node, nullable) and boundary kinds (nullable) of

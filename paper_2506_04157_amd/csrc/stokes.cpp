@@ -111,8 +111,9 @@ struct LevelData {
   DBuf<int> tiles;
   Sweep sw;
   DBuf<int> eall;
-  DBuf<int> sw_strip, sw_plist2, sw_poff2, sw_plist1, sw_poff1, sw_elist, sw_eoff, g2ptr, g2slot, g1ptr, g1slot;
-  DBuf<uint32_t> g2node, g1node;
+  DBuf<int> xt_tab, xt_off;   // grid-transfer table (this level coarse)
+  DBuf<int> sw_strip, sw_plist2, sw_poff2, sw_plist1, sw_poff1, sw_elist, sw_eoff, sw_etab, g2ptr, g2slot, g1ptr, g1slot;
+  DBuf<uint32_t> g2node, g1node, sw_g2tab, sw_g1tab;
   DBuf<double> sl2_64, sl1_64;   // slot buffers of the sweep kernels
   DBuf<float> sl2_32, sl1_32;
   // P1 mass stencil: lattice tables, gather lists, coefficients, slots
@@ -386,17 +387,14 @@ void vcycle(Ctx& c, int l, const R* b, R* x, int steps, int deg) {
   const long long N = 3 * L.h.n2, Nc = 3 * C.h.n2;
   vfill<R>(x, R(0), N, c.s);
   chebyshev<R>(c, l, b, x, steps, deg, true);
-  R* r = L.pool<R>().get(W_R, N, c.s);
   R* t = L.pool<R>().get(W_T, N, c.s);
   applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
-  vsub<R>(b, t, r, N, c.s);
   R* bc = C.pool<R>().get(W_B, Nc, c.s);
   R* xc = C.pool<R>().get(W_X, Nc, c.s);
   vfill<R>(bc, R(0), Nc, c.s);
-  launch_restrict<R>(C.d, L.d, r, bc, BCM_IN | BCM_OUT, c.s);
+  launch_restrict_diff<R>(C.d, L.d, b, t, bc, BCM_IN | BCM_OUT, c.s);   // R (b - A x)
   vcycle<R>(c, l - 1, bc, xc, steps, deg);
-  launch_prolong<R>(C.d, L.d, xc, t, BCM_OUT, c.s);
-  vaxpy<R>(R(1), t, x, N, c.s);
+  launch_prolong_add<R>(C.d, L.d, xc, x, BCM_OUT, c.s);                 // x += P x_c
   chebyshev<R>(c, l, b, x, steps, deg, false);
   if (c.rep) c.rep->vcycles += (l == c.L());
 }
@@ -741,6 +739,7 @@ void upload_level(Ctx& c, int l) {
   L.sw_poff1.upload(L.sw.poff1);
   L.sw_elist.upload(L.sw.elist);
   L.sw_eoff.upload(L.sw.eoff);
+  L.sw_etab.upload(L.sw.etab);
   d.sw.nstrips = L.sw.nstrips;
   d.sw.cap2 = L.sw.cap2;
   d.sw.cap1 = L.sw.cap1;
@@ -753,6 +752,34 @@ void upload_level(Ctx& c, int l) {
   d.sw.poff1 = L.sw_poff1.p;
   d.sw.elist = L.sw_elist.p;
   d.sw.eoff = L.sw_eoff.p;
+  d.sw.etab = (const int4*)L.sw_etab.p;
+  {
+    // global node of every plane-list entry of every macro, in plane-list order
+    const int nm = c.mm.nm();
+    const size_t ne2 = L.sw.plist2.size() / 2, ne1 = L.sw.plist1.size() / 2;
+    std::vector<uint32_t> t2(ne2 * nm), t1(ne1 * nm);
+    std::vector<int64_t> loc2(ne2), loc1(ne1);
+    for (size_t e = 0; e < ne2; ++e) {
+      const int pk = L.sw.plist2[2 * e];
+      loc2[e] = lattice_loc(pk & 1023, (pk >> 10) & 1023, pk >> 20, 2 * h.n);
+    }
+    for (size_t e = 0; e < ne1; ++e) {
+      const int pk = L.sw.plist1[2 * e];
+      loc1[e] = lattice_loc(pk & 1023, (pk >> 10) & 1023, pk >> 20, h.n);
+    }
+    for (int mc = 0; mc < nm; ++mc) {
+      const uint32_t* a2 = h.l2g2.data() + (size_t)mc * h.nloc2;
+      const uint32_t* a1 = h.l2g1.data() + (size_t)mc * h.nloc1;
+      for (size_t e = 0; e < ne2; ++e) t2[(size_t)mc * ne2 + e] = a2[loc2[e]];
+      for (size_t e = 0; e < ne1; ++e) t1[(size_t)mc * ne1 + e] = a1[loc1[e]];
+    }
+    L.sw_g2tab.upload(t2);
+    L.sw_g1tab.upload(t1);
+    d.sw.ne2 = (int)ne2;
+    d.sw.ne1 = (int)ne1;
+    d.sw.g2tab = L.sw_g2tab.p;
+    d.sw.g1tab = L.sw_g1tab.p;
+  }
   {
     std::vector<uint32_t> node;
     std::vector<int> ptr, slot;
@@ -766,6 +793,14 @@ void upload_level(Ctx& c, int l) {
     L.g1ptr.upload(ptr);
     L.g1slot.upload(slot);
     d.g1 = GatherDev{(int)node.size(), L.g1node.p, L.g1ptr.p, L.g1slot.p};
+  }
+  // grid-transfer table (this level as the coarse one)
+  {
+    TransferTable tt = build_transfer_table(h);
+    L.xt_tab.upload(tt.tab);
+    L.xt_off.upload(tt.off);
+    d.xtab = (const int4*)L.xt_tab.p;
+    d.xoff = L.xt_off.p;
   }
   // P1 mass stencil (used where a macro's P1 lattice fits the LDS staging)
   {
