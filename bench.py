@@ -109,7 +109,94 @@ def cpu_baseline(nt=3, nr=1, level=1):
             "seconds": dt}
 
 
+def _rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+ROOF_KERNEL = "k_sweep<float, true, 1>"
+
+
+def summarize_profile(d, out, cmd):
+    """Text summary of a rocprofv3 --kernel-trace --stats run: the kernels by
+    total time and, from the trace, the roofline kernel's launches grouped by
+    grid size (the finest level has the largest grid)."""
+    lines = [f"# rocprofv3 kernel summary", f"# command: {cmd}", ""]
+    stats = _rows(os.path.join(d, "run_kernel_stats.csv"))
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    lines.append(f"total kernel time {tot / 1e9:.3f} s over {len(stats)} kernels")
+    lines.append(f"{'total_s':>9} {'calls':>8} {'avg_us':>10} {'pct':>6}  kernel")
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:30]:
+        lines.append(f"{float(r['TotalDurationNs']) / 1e9:9.3f} {int(r['Calls']):8d} "
+                     f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}  {r['Name'][:110]}")
+    tr = os.path.join(d, "run_kernel_trace.csv")
+    if os.path.exists(tr):
+        import csv
+        groups = {}
+        with open(tr) as fh:
+            for r in csv.DictReader(fh):
+                if ROOF_KERNEL not in r["Kernel_Name"]:
+                    continue
+                g = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
+                dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                s_, c_ = groups.get(g, (0, 0))
+                groups[g] = (s_ + dt, c_ + 1)
+        lines += ["", f"{ROOF_KERNEL} launches by grid size (work-items):"]
+        for g in sorted(groups, reverse=True):
+            s_, c_ = groups[g]
+            lines.append(f"  grid {g:>10d}: {c_:6d} launches, average {s_ / c_ / 1e3:10.1f} us")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_traffic(dfetch, dwrite, n_u, out, cmd):
+    """HBM bytes per launch of the roofline kernel at the finest level from
+    FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by the ratio of
+    known bytes to the counter's reading on the plain copy of n_u floats that
+    bench.py --apply-only performs before the timings."""
+    def per_kernel(d, counter):
+        acc = {}
+        for r in _rows(os.path.join(d, "run_counter_collection.csv")):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Kernel_Name"], int(r["Grid_Size"]))
+            acc.setdefault(key, []).append(float(r["Counter_Value"]))
+        return acc
+    f, w = per_kernel(dfetch, "FETCH_SIZE"), per_kernel(dwrite, "WRITE_SIZE")
+    known = 4.0 * n_u
+    def copy_kib(acc):
+        # the copy kernel reading/writing the most bytes is the calibration copy
+        cands = [(sum(v) / len(v), k) for k, v in acc.items() if "copyBuffer" in k[0] or "copy" in k[0].lower()]
+        return max(cands)[0]
+    kf, kw = known / (copy_kib(f) * 1024.0), known / (copy_kib(w) * 1024.0)
+    def roof(acc):
+        cands = [(k[1], sum(v) / len(v)) for k, v in acc.items() if ROOF_KERNEL in k[0]]
+        return max(cands)[1]
+    fb, wb = roof(f) * 1024.0 * kf, roof(w) * 1024.0 * kw
+    lines = ["# HBM traffic of the roofline kernel (finest level, largest grid)",
+             f"# fetch command: {cmd[0]}", f"# write command: {cmd[1]}",
+             f"kernel: {ROOF_KERNEL}",
+             f"kernel_source_sha256_16: {kernel_sha()}",
+             f"copy_bytes_known: {known:.0f}",
+             f"fetch_scale: {kf:.4f}", f"write_scale: {kw:.4f}",
+             f"fetch_bytes_per_launch: {fb:.0f}", f"write_bytes_per_launch: {wb:.0f}",
+             f"hbm_bytes_per_launch: {fb + wb:.0f}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
+        # bench.py --summarize-profile DIR OUT "COMMAND"
+        summarize_profile(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
+        # bench.py --summarize-traffic FETCH_DIR WRITE_DIR N_U OUT "FETCH_CMD" "WRITE_CMD"
+        summarize_traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], (sys.argv[6], sys.argv[7]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
