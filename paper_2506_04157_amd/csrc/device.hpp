@@ -191,16 +191,17 @@ template <typename R> void vsub(const R* b, const R* t, R* r, long long n, hipSt
 template <typename R> void vdot(const R* x, const R* y, long long n, double* partial, double* out, hipStream_t s);
 void vsum_partials(double* partial, int np, double* out, hipStream_t s);
 constexpr int DOT_BLOCKS = 1024;
-// device-resident Jacobi CG pieces (scalars in sc[]: see kernels.hip)
+// device-resident Jacobi CG pieces (scalars in sc[], partial sums in part[],
+// 5 * DOT_BLOCKS doubles; iteration i uses parity i & 1: see kernels.hip)
 enum { CGS_RZ = 0, CGS_RR, CGS_THR, CGS_DONE, CGS_IT, CGS_ALPHA, CGS_BETA, CGS_N };
 template <typename R>
 void cg_init(const R* r, const R* dinv, R* z, long long n, double tol, double* part, double* sc, hipStream_t s);
 template <typename R>
-void cg_alpha(const R* p, const R* q, long long n, double* part, double* sc, hipStream_t s);
+void cg_dot(const R* p, const R* q, long long n, double* part, const double* sc, hipStream_t s);
 template <typename R>
-void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long long n, double* part, double* sc,
-               hipStream_t s);
+void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long long n, double* part, const double* sc,
+               int parity, hipStream_t s);
 template <typename R>
-void cg_pupdate(const R* z, R* p, long long n, const double* sc, hipStream_t s);
+void cg_pupdate(const R* z, R* p, long long n, double* part, double* sc, int parity, hipStream_t s);
 
 }  // namespace stk

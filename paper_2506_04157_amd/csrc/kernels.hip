@@ -721,14 +721,13 @@ __global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__
 // thread per micro-tet of the whole mesh, operands gathered from global memory
 // and results added with global atomics into zero-filled outputs.
 template <typename R, bool BLEND, int FL>
-__global__ __launch_bounds__(256) void k_elemwise(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
-                                                  const R* __restrict__ eta, const R* __restrict__ lnrho,
-                                                  R* __restrict__ yu, R* __restrict__ yp, int bcmode) {
+__device__ __forceinline__ void elemwise_one(const LevelDev& L, long long gid, const R* __restrict__ u,
+                                             const R* __restrict__ p, const R* __restrict__ eta,
+                                             const R* __restrict__ lnrho, R* __restrict__ yu, R* __restrict__ yp,
+                                             int bcmode) {
   using E = StokesElem<R, BLEND, FL>;
   const int n = L.n, m2 = 2 * n;
   const int ne = n * n * n;
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (gid >= (long long)ne * L.nmacro) return;
   const int mac = (int)(gid / ne);
   const int pk = L.eall[gid - (long long)mac * ne];
   const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
@@ -758,14 +757,21 @@ __global__ __launch_bounds__(256) void k_elemwise(LevelDev L, const R* __restric
   for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
   R xv[4][3];
   if (BLEND) elem_vertices<R>(G, type, px, py, pz, n, xv);
+  // velocity at the 10 nodes, projected once per node (macro-interior nodes need none)
+  R uv[10][3];
+  if (E::NU) {
+#pragma unroll
+    for (int a = 0; a < 10; ++a) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uv[a][c] = u[g2[a] + c * N2];
+      const int mask = wmask(I2[a], J2[a], K2[a], m2);
+      if ((bcmode & BCM_IN) && mask != 15) bc_project<R>(bact[mask], G, I2[a], J2[a], K2[a], m2, uv[a][0], uv[a][1], uv[a][2]);
+    }
+  }
   E el;
   el.load(
       tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, [&](int v, int k) { return xv[v][k]; },
-      [&](int c, int a) {
-        R v[3] = {u[g2[a]], u[g2[a] + N2], u[g2[a] + 2 * N2]};
-        if (bcmode & BCM_IN) bc_project<R>(bact[wmask(I2[a], J2[a], K2[a], m2)], G, I2[a], J2[a], K2[a], m2, v[0], v[1], v[2]);
-        return v[c];
-      },
+      [&](int c, int a) { return uv[a][c]; },
       [&](int v, R& ev, R& pv, R& rv) {
         if (E::NE) ev = eta[g1[v]];
         if (E::NP) pv = p[g1[v]];
@@ -776,6 +782,15 @@ __global__ __launch_bounds__(256) void k_elemwise(LevelDev L, const R* __restric
   el.template qp<2>(G);
   el.template qp<3>(G);
   el.store([&](int c, int a, R v) { gadd(yu + g2[a] + c * N2, v); }, [&](int v, R val) { gadd(yp + g1[v], val); });
+}
+
+template <typename R, bool BLEND, int FL>
+__global__ __launch_bounds__(256) void k_elemwise(LevelDev L, const R* __restrict__ u, const R* __restrict__ p,
+                                                  const R* __restrict__ eta, const R* __restrict__ lnrho,
+                                                  R* __restrict__ yu, R* __restrict__ yp, int bcmode) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)L.n * L.n * L.n * L.nmacro) return;
+  elemwise_one<R, BLEND, FL>(L, gid, u, p, eta, lnrho, yu, yp, bcmode);
 }
 
 // sum the slots of shared nodes: P2 vectors (3 components) or P1 scalars
@@ -1527,44 +1542,16 @@ __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ partial,
   if (threadIdx.x == 0) *out = red[0];
 }
 
-static inline int vgrid_fwd(long long n) {
-  long long g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  return (int)g;
-}
 
 // ---- device-resident Jacobi-preconditioned CG ----------------------------------
-// Scalars live in a small device array so that iterations need no host round
-// trip; once converged (|r|^2 <= thr) every update kernel returns early.
+// Scalars and partial sums live on the device so that iterations need no host
+// round trip.  Partial-sum layout (DOT_BLOCKS = NB): [0, NB) p.q; then for
+// parity 0 and 1: [NB + 2 NB k, +NB) r.r and [2 NB + 2 NB k, +NB) r.z.
+// Iteration i writes the r.r / r.z partials of parity i & 1 and reads those of
+// the other parity as the previous r.z; every block sums the partials itself
+// (same order in every block), so no separate scalar kernels are needed.  Once
+// converged (|r|^2 <= thr) every kernel returns early.
 enum { CG_RZ = 0, CG_RR, CG_THR, CG_DONE, CG_IT, CG_ALPHA, CG_BETA, CG_NS };
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_cg_init(const R* __restrict__ r, const R* __restrict__ dinv,
-                                                 R* __restrict__ z, long long n, double* part) {
-  __shared__ double red[2][256];
-  double a = 0, b = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const R zi = dinv[i] * r[i];
-    z[i] = zi;
-    a += (double)r[i] * (double)r[i];
-    b += (double)r[i] * (double)zi;
-  }
-  red[0][threadIdx.x] = a;
-  red[1][threadIdx.x] = b;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + o];
-      red[1][threadIdx.x] += red[1][threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = red[0][0];
-    part[DOT_BLOCKS + blockIdx.x] = red[1][0];
-  }
-}
 
 __device__ __forceinline__ double block_sum(const double* part, int np, double* red) {
   double s = 0;
@@ -1579,44 +1566,7 @@ __device__ __forceinline__ double block_sum(const double* part, int np, double* 
   __syncthreads();
   return v;
 }
-
-__global__ __launch_bounds__(256) void k_cg_init_fin(const double* part, int np, double tol2, double* sc) {
-  __shared__ double red[256];
-  const double rr = block_sum(part, np, red);
-  const double rz = block_sum(part + DOT_BLOCKS, np, red);
-  if (threadIdx.x == 0) {
-    sc[CG_RR] = rr;
-    sc[CG_RZ] = rz;
-    sc[CG_THR] = tol2 * rr;
-    sc[CG_DONE] = (rr == 0.0) ? 1.0 : 0.0;
-    sc[CG_IT] = 0.0;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_cg_alpha(const double* part, int np, double* sc) {
-  if (sc[CG_DONE] != 0.0) return;
-  __shared__ double red[256];
-  const double pq = block_sum(part, np, red);
-  if (threadIdx.x == 0) sc[CG_ALPHA] = sc[CG_RZ] / pq;
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_cg_update(const double* sc, const R* __restrict__ p, const R* __restrict__ q,
-                                                   const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ r,
-                                                   R* __restrict__ z, long long n, double* part) {
-  if (sc[CG_DONE] != 0.0) return;
-  __shared__ double red[2][256];
-  const R alpha = R(sc[CG_ALPHA]);
-  double a = 0, b = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const R ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    const R zi = dinv[i] * ri;
-    z[i] = zi;
-    a += (double)ri * (double)ri;
-    b += (double)ri * (double)zi;
-  }
+__device__ __forceinline__ void block_partials(double a, double b, double* pa, double* pb, double (*red)[256]) {
   red[0][threadIdx.x] = a;
   red[1][threadIdx.x] = b;
   __syncthreads();
@@ -1628,39 +1578,44 @@ __global__ __launch_bounds__(256) void k_cg_update(const double* sc, const R* __
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = red[0][0];
-    part[DOT_BLOCKS + blockIdx.x] = red[1][0];
+    pa[blockIdx.x] = red[0][0];
+    pb[blockIdx.x] = red[1][0];
   }
 }
+__device__ __forceinline__ double* cg_rr(double* part, int parity) { return part + DOT_BLOCKS + 2 * DOT_BLOCKS * parity; }
+__device__ __forceinline__ double* cg_rz(double* part, int parity) { return cg_rr(part, parity) + DOT_BLOCKS; }
 
-__global__ __launch_bounds__(256) void k_cg_beta(const double* part, int np, double* sc) {
-  if (sc[CG_DONE] != 0.0) return;
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_init(const R* __restrict__ r, const R* __restrict__ dinv,
+                                                 R* __restrict__ z, long long n, double* part) {
+  __shared__ double red[2][256];
+  double a = 0, b = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R zi = dinv[i] * r[i];
+    z[i] = zi;
+    a += (double)r[i] * (double)r[i];
+    b += (double)r[i] * (double)zi;
+  }
+  block_partials(a, b, cg_rr(part, 1), cg_rz(part, 1), red);   // "previous" parity of iteration 0
+}
+
+__global__ __launch_bounds__(256) void k_cg_init_fin(double* part, int np, double tol2, double* sc) {
   __shared__ double red[256];
-  const double rr = block_sum(part, np, red);
-  const double rz = block_sum(part + DOT_BLOCKS, np, red);
+  const double rr = block_sum(cg_rr(part, 1), np, red);
+  const double rz = block_sum(cg_rz(part, 1), np, red);
   if (threadIdx.x == 0) {
-    sc[CG_IT] += 1.0;
     sc[CG_RR] = rr;
-    if (rr <= sc[CG_THR]) {
-      sc[CG_DONE] = 1.0;
-    } else {
-      sc[CG_BETA] = rz / sc[CG_RZ];
-      sc[CG_RZ] = rz;
-    }
+    sc[CG_RZ] = rz;
+    sc[CG_THR] = tol2 * rr;
+    sc[CG_DONE] = (rr == 0.0) ? 1.0 : 0.0;
+    sc[CG_IT] = 0.0;
   }
 }
 
+// partials of p.q
 template <typename R>
-__global__ void k_cg_p(const double* sc, const R* __restrict__ z, R* __restrict__ p, long long n) {
-  if (sc[CG_DONE] != 0.0) return;
-  const R beta = R(sc[CG_BETA]);
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_dot_guard(const double* sc, const R* __restrict__ x, const R* __restrict__ y,
-                                                   long long n, double* partial) {
+__global__ __launch_bounds__(256) void k_cg_dot(const double* sc, const R* __restrict__ x, const R* __restrict__ y,
+                                                long long n, double* part) {
   if (sc[CG_DONE] != 0.0) return;
   __shared__ double red[256];
   double s = 0;
@@ -1672,7 +1627,55 @@ __global__ __launch_bounds__(256) void k_dot_guard(const double* sc, const R* __
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// alpha = r.z / p.q;  x += alpha p;  r -= alpha q;  z = D^-1 r;  partials of r.r, r.z
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_update(const double* sc, const R* __restrict__ p, const R* __restrict__ q,
+                                                   const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ r,
+                                                   R* __restrict__ z, long long n, double* part, int np, int parity) {
+  if (sc[CG_DONE] != 0.0) return;
+  __shared__ double red[2][256];
+  const double pq = block_sum(part, np, red[0]);
+  const double rz = block_sum(cg_rz(part, parity ^ 1), np, red[0]);
+  const R alpha = R(rz / pq);
+  double a = 0, b = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const R ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    const R zi = dinv[i] * ri;
+    z[i] = zi;
+    a += (double)ri * (double)ri;
+    b += (double)ri * (double)zi;
+  }
+  block_partials(a, b, cg_rr(part, parity), cg_rz(part, parity), red);
+}
+
+// convergence test; beta = r.z / previous r.z;  p = z + beta p
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_p(double* sc, const R* __restrict__ z, R* __restrict__ p, long long n,
+                                              double* part, int np, int parity) {
+  if (sc[CG_DONE] != 0.0) return;
+  __shared__ double red[256];
+  const double rr = block_sum(cg_rr(part, parity), np, red);
+  const double rz = block_sum(cg_rz(part, parity), np, red);
+  const double rzo = block_sum(cg_rz(part, parity ^ 1), np, red);
+  const bool done = rr <= sc[CG_THR];
+  __syncthreads();   // every block has read the scalars before block 0 updates them
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[CG_IT] += 1.0;
+    sc[CG_RR] = rr;
+    sc[CG_RZ] = rz;
+  }
+  if (done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[CG_DONE] = 1.0;
+    return;
+  }
+  const R beta = R(rz / rzo);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
 }
 
 static inline int redgrid(long long n) {
@@ -1687,27 +1690,26 @@ void cg_init(const R* r, const R* dinv, R* z, long long n, double tol, double* p
   hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, part, nb, tol * tol, sc);
 }
 template <typename R>
-void cg_alpha(const R* p, const R* q, long long n, double* part, double* sc, hipStream_t s) {
-  const int nb = redgrid(n);
-  hipLaunchKernelGGL((k_dot_guard<R>), dim3(nb), dim3(256), 0, s, sc, p, q, n, part);
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, part, nb, sc);
+void cg_dot(const R* p, const R* q, long long n, double* part, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_dot<R>), dim3(redgrid(n)), dim3(256), 0, s, sc, p, q, n, part);
 }
 template <typename R>
-void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long long n, double* part, double* sc,
-               hipStream_t s) {
+void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long long n, double* part, const double* sc,
+               int parity, hipStream_t s) {
   const int nb = redgrid(n);
-  hipLaunchKernelGGL((k_cg_update<R>), dim3(nb), dim3(256), 0, s, sc, p, q, dinv, x, r, z, n, part);
-  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, part, nb, sc);
+  hipLaunchKernelGGL((k_cg_update<R>), dim3(nb), dim3(256), 0, s, sc, p, q, dinv, x, r, z, n, part, nb, parity);
 }
 template <typename R>
-void cg_pupdate(const R* z, R* p, long long n, const double* sc, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_p<R>), dim3(vgrid_fwd(n)), dim3(256), 0, s, sc, z, p, n);
+void cg_pupdate(const R* z, R* p, long long n, double* part, double* sc, int parity, hipStream_t s) {
+  const int nb = redgrid(n);
+  hipLaunchKernelGGL((k_cg_p<R>), dim3(nb), dim3(256), 0, s, sc, z, p, n, part, nb, parity);
 }
-#define INST_CG(R)                                                                                              \
-  template void cg_init<R>(const R*, const R*, R*, long long, double, double*, double*, hipStream_t);         \
-  template void cg_alpha<R>(const R*, const R*, long long, double*, double*, hipStream_t);                    \
-  template void cg_update<R>(const R*, const R*, const R*, R*, R*, R*, long long, double*, double*, hipStream_t); \
-  template void cg_pupdate<R>(const R*, R*, long long, const double*, hipStream_t);
+#define INST_CG(R)                                                                                                \
+  template void cg_init<R>(const R*, const R*, R*, long long, double, double*, double*, hipStream_t);           \
+  template void cg_dot<R>(const R*, const R*, long long, double*, const double*, hipStream_t);                 \
+  template void cg_update<R>(const R*, const R*, const R*, R*, R*, R*, long long, double*, const double*, int,  \
+                             hipStream_t);                                                                      \
+  template void cg_pupdate<R>(const R*, R*, long long, double*, double*, int, hipStream_t);
 
 // ---- launch wrappers ----------------------------------------------------------------
 static inline int vgrid(long long n) {

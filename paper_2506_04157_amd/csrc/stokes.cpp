@@ -187,6 +187,7 @@ struct stk_ctx {
   hipStream_t s = nullptr;
   DBuf<double> dotbuf;
   DBuf<double> cgbuf;      // device CG scalars
+  DBuf<double> cgpart;     // device CG partial sums
   double* hpin = nullptr;
   bool ready = false;
   bool has_rho = false;
@@ -320,7 +321,7 @@ void chebyshev(Ctx& c, int l, const R* b, R* x, int steps, int deg, bool xzero) 
 template <class R, class Apply, class Proj>
 int dev_pcg(Ctx& c, long long N, Apply apply, Proj proj, const R* dinv, const R* b, R* x, R* r, R* z, R* p, R* q,
             double tol, int maxit, int chunk) {
-  double* part = c.dotbuf.p;
+  double* part = c.cgpart.p;
   double* sc = c.cgbuf.p;
   vfill<R>(x, R(0), N, c.s);
   vcopy<R>(b, r, N, c.s);
@@ -331,11 +332,12 @@ int dev_pcg(Ctx& c, long long N, Apply apply, Proj proj, const R* dinv, const R*
   int it = 0;
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
+      const int parity = (it + k) & 1;
       apply(p, q);
-      cg_alpha<R>(p, q, N, part, sc, c.s);
-      cg_update<R>(p, q, dinv, x, r, z, N, part, sc, c.s);
+      cg_dot<R>(p, q, N, part, sc, c.s);
+      cg_update<R>(p, q, dinv, x, r, z, N, part, sc, parity, c.s);
       proj(z);
-      cg_pupdate<R>(z, p, N, sc, c.s);
+      cg_pupdate<R>(z, p, N, part, sc, parity, c.s);
     }
     it += chunk;
     HIPCHK(hipMemcpyAsync(c.hpin, sc, CGS_N * sizeof(double), hipMemcpyDeviceToHost, c.s));
@@ -1045,6 +1047,7 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
     }
     c->dotbuf.alloc(2 * DOT_BLOCKS + 8);
     c->cgbuf.alloc(16);
+    c->cgpart.alloc(5 * DOT_BLOCKS);
     HIPCHK(hipHostMalloc((void**)&c->hpin, 64, hipHostMallocDefault));
     HIPCHK(hipDeviceSynchronize());
     *out = c.release();
