@@ -43,17 +43,21 @@ struct GatherDev {
 };
 
 // P1 mass stencil of a level: per-macro rows over the 15 lattice directions
-// (the node itself and its 14 lattice neighbours), assembled once per
-// viscosity field; macro-boundary rows are partial and summed by a gather.
+// (the node itself, 7 positive directions and their negatives), assembled
+// once per viscosity field; macro-boundary rows are partial and summed by a
+// gather.  The per-macro matrix is symmetric, so only the node itself and the
+// 7 positive directions are stored: the coefficient of node t in direction
+// -d is the one of its neighbour j = t - d in direction d.
 constexpr int NDIR1D = 15;
+constexpr int NSTORE1 = 8;
 struct StencilDev {
   int on;                 // 1: the stencil apply is used for this level
   int nsh;                // slots per macro
-  const short* nb;        // [15][nloc1] neighbour local index (the node itself where absent)
+  const short* nb;        // [15][nloc1] neighbour local index (nloc1 where absent)
   const int* dst;         // [nloc1] slot of macro-boundary nodes, -1 for macro-interior nodes
   const int* inc_ptr;     // [nloc1 + 1] micro-tets containing each node
   const int2* inc;        // (packed type | px<<3 | py<<13 | pz<<23, vertex | direction codes)
-  const double* c64;      // [nmacro][15][nloc1]
+  const double* c64;      // [nmacro][8][nloc1 + 1], last column zero
   const float* c32;
   GatherDev g;
 };
@@ -151,6 +155,7 @@ template <typename R>
 void launch_mass_stencil(const LevelDev& L, const R* p, R* y, R* slots, hipStream_t s);
 // LDS bytes of the stencil apply
 size_t mass_stencil_lds_bytes(int nloc1, int real_bytes);
+// coefficients per level: nmacro * NSTORE1 * (nloc1 + 1)
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s);
 void launch_gradient(const LevelDev& L, const double* eta, const double* u, const double* lam,
                      double* gm, double* gT, double scale, hipStream_t s);

@@ -872,11 +872,18 @@ __global__ __launch_bounds__(256) void k_mass_stencil_build(LevelDev L, const do
         if (dd == d) acc[dd] += m;
     }
   }
+  // the node itself and the positive directions; a zero column past the end
+  // stands for absent neighbours
+  const size_t ld = (size_t)nloc + 1;
 #pragma unroll
-  for (int d = 0; d < NDIR1D; ++d) {
-    const size_t o = ((size_t)mac * NDIR1D + d) * nloc + t;
+  for (int d = 0; d < NSTORE1; ++d) {
+    const size_t o = ((size_t)mac * NSTORE1 + d) * ld + t;
     c64[o] = acc[d];
     c32[o] = (float)acc[d];
+    if (t == 0) {
+      c64[o + nloc] = 0.0;
+      c32[o + nloc] = 0.0f;
+    }
   }
 }
 
@@ -893,14 +900,20 @@ __global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __res
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sp = reinterpret_cast<R*>(smem_raw);
   const int nloc = L.nloc1, mac = blockIdx.x;
+  const size_t ld = (size_t)nloc + 1;
   const uint32_t* l1 = L.l2g1 + (size_t)mac * nloc;
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) sp[t] = p[l1[t]];
+  if (threadIdx.x == 0) sp[nloc] = R(0);
   __syncthreads();
-  const R* c = mcoef_of<R>(L) + (size_t)mac * NDIR1D * nloc;
+  const R* c = mcoef_of<R>(L) + (size_t)mac * NSTORE1 * ld;
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-    double acc = 0.0;
+    double acc = (double)c[t] * (double)sp[t];
 #pragma unroll
-    for (int d = 0; d < NDIR1D; ++d) acc += (double)c[(size_t)d * nloc + t] * (double)sp[L.ms.nb[d * nloc + t]];
+    for (int d = 1; d < NSTORE1; ++d) {
+      const int jp = L.ms.nb[d * nloc + t], jm = L.ms.nb[(d + 7) * nloc + t];
+      acc += (double)c[d * ld + t] * (double)sp[jp];
+      acc += (double)c[d * ld + jm] * (double)sp[jm];
+    }
     const int slot = L.ms.dst[t];
     if (slot < 0) y[l1[t]] = R(acc);
     else sl[(size_t)mac * L.ms.nsh + slot] = R(acc);
@@ -1301,6 +1314,7 @@ template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, const R* __restrict__ in,
                                                   const R* __restrict__ in2, R* __restrict__ out, int bcmode) {
   constexpr bool PRO = MODE == 0 || MODE == 2;
+  constexpr int NB = 4;   // fine points per thread and batch (all loads of a batch in flight together)
   __shared__ double sc[3 * NB2];   // FP64 staging / accumulation (fast LDS atomics)
   const int tile = blockIdx.x % Lc.ntiles;
   const int mac = blockIdx.x / Lc.ntiles;
@@ -1312,74 +1326,111 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
   const uint8_t* bact = Lc.bact + (size_t)mac * 16;
   const uint8_t* own = Lf.own + (size_t)mac * 16;
   const size_t Nc = (size_t)Lc.n2, Nf = (size_t)Lf.n2;
-  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
-    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
-    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
-    R v0 = 0, v1 = 0, v2 = 0;
-    if (PRO && I + J + K <= mc2) {
-      const size_t g = l2c[lloc(I, J, K, mc2)];
-      v0 = in[g];
-      v1 = in[g + Nc];
-      v2 = in[g + 2 * Nc];
+  {
+    // coarse brick: staged values (prolongation) or zeroed accumulators
+    constexpr int NS = (NB2 + 255) / 256;
+    size_t g[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+      const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+      g[k] = (PRO && i < NB2 && I + J + K <= mc2) ? (size_t)l2c[lloc(I, J, K, mc2)] : ~(size_t)0;
     }
-    sc[i] = v0;
-    sc[NB2 + i] = v1;
-    sc[2 * NB2 + i] = v2;
+    R v[NS][3];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[k][c] = g[k] != ~(size_t)0 ? in[g[k] + c * Nc] : R(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < NB2) {
+        sc[i] = v[k][0];
+        sc[NB2 + i] = v[k][1];
+        sc[2 * NB2 + i] = v[k][2];
+      }
+    }
   }
   __syncthreads();
-  const int e1 = Lc.xoff[tile + 1];
-  for (int e = Lc.xoff[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const int4 ta = Lc.xtab[2 * e], tb = Lc.xtab[2 * e + 1];
-    const int JX = ta.x & 1023, JY = (ta.x >> 10) & 1023, JZ = (ta.x >> 20) & 1023;
-    const int mask = wmask(JX, JY, JZ, mf2);
-    if (!own[mask]) continue;
-    const int nnz = ta.y;
-    const unsigned wd[5] = {(unsigned)ta.z, (unsigned)ta.w, (unsigned)tb.x, (unsigned)tb.y, (unsigned)tb.z};
-    const size_t gf = l2f[lloc(JX, JY, JZ, mf2)];
-    if (PRO) {
-      R v[3] = {0, 0, 0};
+  const int e0 = Lc.xoff[tile], e1 = Lc.xoff[tile + 1];
+  for (int base = e0; base < e1; base += NB * 256) {
+    int4 ta[NB], tb[NB];
+    bool ok[NB];
 #pragma unroll
-      for (int j = 0; j < 10; ++j) {
-        if (j < nnz) {
-          const unsigned f = (wd[j >> 1] >> (16 * (j & 1))) & 0x3fffu;
-          const int idx = (int)(f & 1023u), w = (int)(f >> 10) - 1;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) v[c] += R(w) * R(sc[c * NB2 + idx]);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] *= R(0.125);
-      if (bcmode & BCM_OUT) {
-        // fine node class = coarse sub-simplex class (same macro, nested)
-        const int act = Lf.bact[(size_t)mac * 16 + mask];
-        bc_project<R>(act, G, JX, JY, JZ, mf2, v[0], v[1], v[2]);
-      }
-      if (MODE == 2) {
-        out[gf] += v[0];
-        out[gf + Nf] += v[1];
-        out[gf + 2 * Nf] += v[2];
+    for (int k = 0; k < NB; ++k) {
+      const int e = base + k * 256 + threadIdx.x;
+      ok[k] = e < e1;
+      if (ok[k]) {
+        ta[k] = Lc.xtab[2 * e];
+        tb[k] = Lc.xtab[2 * e + 1];
       } else {
-        out[gf] = v[0];
-        out[gf + Nf] = v[1];
-        out[gf + 2 * Nf] = v[2];
+        ta[k] = make_int4(0, 0, 0, 0);
+        tb[k] = ta[k];
       }
-    } else {
-      R v0 = in[gf], v1 = in[gf + Nf], v2 = in[gf + 2 * Nf];
-      if (MODE == 3) {
-        v0 -= in2[gf];
-        v1 -= in2[gf + Nf];
-        v2 -= in2[gf + 2 * Nf];
-      }
-      if (bcmode & BCM_IN) bc_project<R>(Lf.bact[(size_t)mac * 16 + mask], G, JX, JY, JZ, mf2, v0, v1, v2);
+    }
+    size_t gf[NB];
+    int mask[NB];
 #pragma unroll
-      for (int j = 0; j < 10; ++j) {
-        if (j < nnz) {
-          const unsigned f = (wd[j >> 1] >> (16 * (j & 1))) & 0x3fffu;
-          const int idx = (int)(f & 1023u);
-          const double wf = ((int)(f >> 10) - 1) * 0.125;
-          ldsadd(sc + idx, wf * double(v0));
-          ldsadd(sc + NB2 + idx, wf * double(v1));
-          ldsadd(sc + 2 * NB2 + idx, wf * double(v2));
+    for (int k = 0; k < NB; ++k) {
+      const int JX = ta[k].x & 1023, JY = (ta[k].x >> 10) & 1023, JZ = (ta[k].x >> 20) & 1023;
+      mask[k] = wmask(JX, JY, JZ, mf2);
+      ok[k] = ok[k] && own[mask[k]];
+      gf[k] = ok[k] ? (size_t)l2f[lloc(JX, JY, JZ, mf2)] : 0;
+    }
+    R v[NB][3];
+    if (!PRO || MODE == 2) {
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[k][c] = ok[k] ? (MODE == 2 ? out : in)[gf[k] + c * Nf] : R(0);
+      if (MODE == 3) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[k][c] -= ok[k] ? in2[gf[k] + c * Nf] : R(0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (!ok[k]) continue;
+      const int JX = ta[k].x & 1023, JY = (ta[k].x >> 10) & 1023, JZ = (ta[k].x >> 20) & 1023;
+      const int nnz = ta[k].y;
+      const unsigned wd[5] = {(unsigned)ta[k].z, (unsigned)ta[k].w, (unsigned)tb[k].x, (unsigned)tb[k].y,
+                              (unsigned)tb[k].z};
+      if (PRO) {
+        R w3[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+          if (j < nnz) {
+            const unsigned f = (wd[j >> 1] >> (16 * (j & 1))) & 0x3fffu;
+            const int idx = (int)(f & 1023u), w = (int)(f >> 10) - 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) w3[c] += R(w) * R(sc[c * NB2 + idx]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w3[c] *= R(0.125);
+        if (bcmode & BCM_OUT) {
+          // fine node class = coarse sub-simplex class (same macro, nested)
+          const int act = Lf.bact[(size_t)mac * 16 + mask[k]];
+          bc_project<R>(act, G, JX, JY, JZ, mf2, w3[0], w3[1], w3[2]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[gf[k] + c * Nf] = (MODE == 2 ? v[k][c] : R(0)) + w3[c];
+      } else {
+        if (bcmode & BCM_IN)
+          bc_project<R>(Lf.bact[(size_t)mac * 16 + mask[k]], G, JX, JY, JZ, mf2, v[k][0], v[k][1], v[k][2]);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+          if (j < nnz) {
+            const unsigned f = (wd[j >> 1] >> (16 * (j & 1))) & 0x3fffu;
+            const int idx = (int)(f & 1023u);
+            const double wf = ((int)(f >> 10) - 1) * 0.125;
+            ldsadd(sc + idx, wf * double(v[k][0]));
+            ldsadd(sc + NB2 + idx, wf * double(v[k][1]));
+            ldsadd(sc + 2 * NB2 + idx, wf * double(v[k][2]));
+          }
         }
       }
     }
@@ -1805,7 +1856,7 @@ void launch_mass_stencil_build(const LevelDev& L, const double* eta, double* c64
   if (L.blend) hipLaunchKernelGGL((k_mass_stencil_build<true>), grid, dim3(256), 0, s, L, eta, c64, c32);
   else hipLaunchKernelGGL((k_mass_stencil_build<false>), grid, dim3(256), 0, s, L, eta, c64, c32);
 }
-size_t mass_stencil_lds_bytes(int nloc1, int real_bytes) { return (size_t)nloc1 * real_bytes; }
+size_t mass_stencil_lds_bytes(int nloc1, int real_bytes) { return ((size_t)nloc1 + 1) * real_bytes; }
 template <typename R>
 void launch_mass_stencil(const LevelDev& L, const R* p, R* y, R* slots, hipStream_t s) {
   hipLaunchKernelGGL((k_mass_stencil<R>), dim3((unsigned)L.nmacro), dim3(256),

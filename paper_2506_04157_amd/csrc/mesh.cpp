@@ -611,6 +611,18 @@ P1Stencil build_p1_stencil(int n) {
         if (dir_of(a, b, c) < 0) dirs.push_back({a, b, c});
       }
   if ((int)dirs.size() != NDIR1) throw std::runtime_error("unexpected lattice edge directions");
+  // order: the node itself, the 7 directions that are lexicographically
+  // positive, then their negatives in the same order (direction d + 7 = -d)
+  {
+    std::vector<std::array<int, 3>> pos;
+    for (size_t d = 1; d < dirs.size(); ++d)
+      if (dirs[d] > std::array<int, 3>{0, 0, 0}) pos.push_back(dirs[d]);
+    std::sort(pos.begin(), pos.end());
+    if (pos.size() != 7) throw std::runtime_error("lattice edge directions are not symmetric");
+    dirs.assign(1, {0, 0, 0});
+    for (auto& d : pos) dirs.push_back(d);
+    for (auto& d : pos) dirs.push_back({-d[0], -d[1], -d[2]});
+  }
   for (int d = 0; d < NDIR1; ++d)
     for (int k = 0; k < 3; ++k) st.dir[d][k] = dirs[d][k];
   const int64_t nloc = (int64_t)(n + 1) * (n + 2) * (n + 3) / 6;
@@ -622,7 +634,7 @@ P1Stencil build_p1_stencil(int n) {
         for (int d = 0; d < NDIR1; ++d) {
           const int a = I + dirs[d][0], b = J + dirs[d][1], c = K + dirs[d][2];
           const bool in = a >= 0 && b >= 0 && c >= 0 && a + b + c <= n;
-          st.nb[(size_t)d * nloc + t] = (int16_t)(in ? lattice_loc(a, b, c, n) : t);
+          st.nb[(size_t)d * nloc + t] = (int16_t)(in ? lattice_loc(a, b, c, n) : nloc);
         }
       }
   // slots: those of a one-strip sweep (exactly the macro-boundary nodes)

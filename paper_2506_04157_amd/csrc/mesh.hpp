@@ -102,11 +102,12 @@ void build_gather(const MacroMesh& mm, const Level& lv, const Sweep& sw, int whi
 
 // Lattice tables of the P1 mass stencil of one level (the same for every
 // macro): a P1 lattice node couples with itself and its 14 lattice
-// neighbours; direction 0 is the node itself.
+// neighbours; direction 0 is the node itself, 1..7 the lexicographically
+// positive lattice directions and 8..14 their negatives (d + 7 = -d).
 constexpr int NDIR1 = 15;
 struct P1Stencil {
   int dir[NDIR1][3];           // lattice offset of each direction
-  std::vector<int16_t> nb;     // [NDIR1][nloc1] neighbour local index, the node itself where absent
+  std::vector<int16_t> nb;     // [NDIR1][nloc1] neighbour local index, nloc1 where absent
   std::vector<int> dst;        // [nloc1] slot of macro-boundary nodes, -1 for macro-interior ones
   std::vector<int> inc_ptr;    // [nloc1 + 1] micro-tets containing each node
   std::vector<int> inc;        // pairs: packed type | px<<3 | py<<13 | pz<<23, and

@@ -946,7 +946,7 @@ void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const s
   for (int l = c.lmin(); l <= Lf; ++l) {
     LevelData& L = c.at(l);
     if (!L.d.ms.on) continue;
-    const size_t nc = (size_t)L.d.nmacro * NDIR1D * L.h.nloc1;
+    const size_t nc = (size_t)L.d.nmacro * NSTORE1 * (L.h.nloc1 + 1);
     L.ms_c64.alloc(nc);
     L.ms_c32.alloc(nc);
     L.d.ms.c64 = L.ms_c64.p;
