@@ -82,7 +82,17 @@ typedef struct {
   int use_Bbar;        /* 1: B + C in the Uzawa pressure update (eq. SymmetricUzawaStep1 remark) */
   int power_its;       /* power iterations for lambda_max(D^-1 A): 15 */
   double cheb_lo, cheb_hi; /* Chebyshev interval = [cheb_lo, cheb_hi] * lambda_max: 0.12, 1.2 */
+  int uzawa;           /* block preconditioner (Sec. 5.2.1): STK_UZAWA_SYMMETRIC (default),
+                          STK_UZAWA_INEXACT (eq. InexactUzawaStep1), STK_UZAWA_ADJOINT
+                          (eq. AdjointInexactUzawaStep1) */
+  int schur;           /* Schur approximation (Sec. 5.2.3): STK_SCHUR_VBFBT (eq. schurV,
+                          default), STK_SCHUR_MASS (eq. schurMass, M_{1/eta} CG to
+                          tol_invmass), STK_SCHUR_DIAG_BFBT (diag(A)-BFBT: the BFBT form
+                          with C = D = diag(A)) */
 } stk_solver_params;
+
+enum { STK_UZAWA_SYMMETRIC = 0, STK_UZAWA_INEXACT = 1, STK_UZAWA_ADJOINT = 2 };
+enum { STK_SCHUR_VBFBT = 0, STK_SCHUR_MASS = 1, STK_SCHUR_DIAG_BFBT = 2 };
 
 typedef struct {
   int iterations;          /* FGMRES iterations */
@@ -153,6 +163,14 @@ int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, void* rc);
 /* One V-cycle on the finest level, x = V(b); which = 0: A-block cycle
  * (m_A, deg_A), 1: BFBT cycle Ac (m_V, deg_V). */
 int stk_vcycle(stk_ctx* ctx, const stk_solver_params* params, int prec, const void* b, void* x, int which);
+
+/* One application of the block preconditioner chosen in params (uzawa,
+ * schur, precision) to the FP64 residual [ru; rp], started from zero, as
+ * FGMRES applies it (Sec. 5.2.4): device doubles ru, zu (3 n_p2), rp, zp
+ * (n_p1); outputs overwritten, zu projected, zp of arithmetic mean 0.
+ * transpose = 1: the preconditioner of K^T (B and B + C swap roles). */
+int stk_precondition(stk_ctx* ctx, const stk_solver_params* params, const double* ru, const double* rp, double* zu,
+                     double* zp, int transpose);
 
 /* Stokes solve (Sec. 5.2.4): f_u (3 n_p2), g_p (n_p1, nullable = 0),
  * u_dirichlet (3 n_p2, nullable = 0; read at Dirichlet nodes only); outputs

@@ -18,7 +18,9 @@ Plain linear algebra on the oracle's sparse matrices, in FP64:
 * ``pcg``             preconditioned CG stopped on a relative residual.
 * ``bfbt``            the BFBT-type Schur approximation, eq. (schurV), with
                       caller-supplied inner operators.
-* ``symmetric_uzawa`` one step of eq. (SymmetricUzawaStep1) from zero.
+* ``symmetric_uzawa``, ``inexact_uzawa``, ``adjoint_uzawa``  one step of
+                      eqs. (SymmetricUzawaStep1), (InexactUzawaStep1) and
+                      (AdjointInexactUzawaStep1) from zero (Sec. 5.2.1).
 * ``fgmres``          right-preconditioned flexible GMRES (Saad 1993).
 """
 import numpy as np
@@ -149,6 +151,22 @@ def symmetric_uzawa(ru, rp, A, Bt, Bbar, Ahat_inv, Shat_inv, sigma, omega):
     uh = sigma * Ahat_inv(ru)
     p = -omega * Shat_inv(rp - Bbar @ uh)
     u = uh + sigma * Ahat_inv(ru - A @ uh - Bt @ p)
+    return u, p
+
+
+def inexact_uzawa(ru, rp, Bbar, Ahat_inv, Shat_inv, sigma, omega):
+    """One step of eq. (InexactUzawaStep1) from (0, 0): velocity first, then
+    the pressure from the continuity residual of the new velocity."""
+    u = sigma * Ahat_inv(ru)
+    p = -omega * Shat_inv(rp - Bbar @ u)
+    return u, p
+
+
+def adjoint_uzawa(ru, rp, Bt, Ahat_inv, Shat_inv, sigma, omega):
+    """One step of eq. (AdjointInexactUzawaStep1) from (0, 0): pressure first,
+    then the velocity from the momentum residual of the new pressure."""
+    p = -omega * Shat_inv(rp)
+    u = sigma * Ahat_inv(ru - Bt @ p)
     return u, p
 
 

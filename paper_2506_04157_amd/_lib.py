@@ -8,6 +8,8 @@ LIB_PATH = os.path.join(HERE, "libstokes.so")
 STK_OK, STK_EINVAL, STK_ENOMEM, STK_EHIP, STK_ENOCONV, STK_ENOTREADY = 0, -1, -2, -3, -4, -5
 MESH_CUBE, MESH_SHELL = 0, 1
 BC_DIRICHLET, BC_FREESLIP = 1, 2
+UZAWA_SYMMETRIC, UZAWA_INEXACT, UZAWA_ADJOINT = 0, 1, 2
+SCHUR_VBFBT, SCHUR_MASS, SCHUR_DIAG_BFBT = 0, 1, 2
 
 
 class MeshDesc(ctypes.Structure):
@@ -23,7 +25,8 @@ class SolverParams(ctypes.Structure):
                 ("tol_invmass", ctypes.c_double), ("tol_coarse", ctypes.c_double), ("m_A", ctypes.c_int),
                 ("deg_A", ctypes.c_int), ("m_V", ctypes.c_int), ("deg_V", ctypes.c_int),
                 ("max_inner", ctypes.c_int), ("use_Bbar", ctypes.c_int), ("power_its", ctypes.c_int),
-                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double)]
+                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double), ("uzawa", ctypes.c_int),
+                ("schur", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -68,6 +71,7 @@ SIGNATURES = {
     "stk_prolong": [_CTX, _I, _I, _P, _P],
     "stk_restrict": [_CTX, _I, _I, _P, _P],
     "stk_vcycle": [_CTX, ctypes.POINTER(SolverParams), _I, _P, _P, _I],
+    "stk_precondition": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, _I],
     "stk_solve": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, _P, ctypes.POINTER(Report)],
     "stk_solve_adjoint": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, ctypes.POINTER(Report)],
     "stk_gradient": [_CTX, _P, _P, _D, _P, _P],

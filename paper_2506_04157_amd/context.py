@@ -182,6 +182,14 @@ class StokesContext:
             check(rc)
         return u, p, rep.as_dict()
 
+    def precondition(self, ru, rp, params=None, transpose=False):
+        """One application of the block preconditioner to the residual [ru; rp]."""
+        params = params or self.params or default_params()
+        zu, zp = self.zeros_u(), self.zeros_p()
+        check(self.lib.stk_precondition(self.h, ctypes.byref(params), _ptr(ru), _ptr(rp), _ptr(zu), _ptr(zp),
+                                        int(transpose)))
+        return zu, zp
+
     def solve_adjoint(self, ju, jp=None, params=None):
         params = params or self.params or default_params()
         jp = self.zeros_p() if jp is None else jp

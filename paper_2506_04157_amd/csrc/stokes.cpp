@@ -170,7 +170,7 @@ template <> float* LevelData::msl<float>() {
 
 // indices into the per-level velocity work pools
 enum { W_B = 0, W_X, W_R, W_D, W_T, W_CG_R, W_CG_Z, W_CG_P, W_CG_Q, W_U0, W_U1, W_U2, W_U3, W_U4, W_U5,
-       W_F0, W_F1, W_F2, W_F3, W_C_R, W_C_Z, W_C_P, W_C_Q, W_C_B, W_C_X };
+       W_F0, W_F1, W_F2, W_F3, W_C_R, W_C_Z, W_C_P, W_C_Q, W_C_B, W_C_X, W_PC0, W_PC1 };
 // pressure-size pools
 enum { Q_0 = 0, Q_1, Q_2, Q_3, Q_4, Q_5, Q_6, Q_7, Q_8, Q_9, Q_ONES, Q_MD, Q_U0, Q_U1, Q_F0, Q_F1, Q_F2, Q_F3 };
 
@@ -453,7 +453,23 @@ void solve_mass(Ctx& c, const R* b, R* x) {
   if (c.rep) c.rep->mass_its += its;
 }
 
-// S_C p = B Ac^-1 B^T p, with Ac one V-cycle (m_V, deg_V)
+// The BFBT inner operator C^-1 of the chosen Schur approximation: one V-cycle
+// Ac (m_V, deg_V) for the V-cycle BFBT (eq. schurV), diag(A)^-1 (projected)
+// for the diag(A)-BFBT (Sec. 5.2.3)
+template <class R>
+void bfbt_cinv(Ctx& c, const R* in, R* out) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  if (c.par.schur == STK_SCHUR_DIAG_BFBT) {
+    vmul<R>(L.dinvp<R>(), in, out, N, c.s);
+    project<R>(c, l, out);
+  } else {
+    vcycle<R>(c, l, in, out, c.par.m_V, c.par.deg_V);
+  }
+}
+
+// S_C p = B C^-1 B^T p
 template <class R>
 void apply_SC(Ctx& c, const R* p, R* y) {
   const int l = c.L();
@@ -462,7 +478,7 @@ void apply_SC(Ctx& c, const R* p, R* y) {
   R* t = L.pool<R>().get(W_U3, N, c.s);
   R* z = L.pool<R>().get(W_U4, N, c.s);
   applyBt<R>(c, l, p, t, false, BCM_OUT);
-  vcycle<R>(c, l, t, z, c.par.m_V, c.par.deg_V);
+  bfbt_cinv<R>(c, t, z);
   applyB<R>(c, l, z, y, false, BCM_IN);
   project_mean<R>(c, y);
 }
@@ -517,16 +533,32 @@ void schur_vbfbt(Ctx& c, const R* rp, R* out) {
   R* w = L.pool<R>().get(W_U5, N, c.s);
   solve_SC<R>(c, rp, y1);
   applyBt<R>(c, l, y1, t, false, BCM_OUT);
-  vcycle<R>(c, l, t, z, c.par.m_V, c.par.deg_V);
+  bfbt_cinv<R>(c, t, z);
   applyA<R>(c, l, z, w, BCM_IN | BCM_OUT);
-  vcycle<R>(c, l, w, z, c.par.m_V, c.par.deg_V);
+  bfbt_cinv<R>(c, w, z);
   applyB<R>(c, l, z, y2, false, BCM_IN);
   project_mean<R>(c, y2);
   solve_SC<R>(c, y2, out);
 }
 
-// Symmetric Uzawa step from zero, eq. (SymmetricUzawaStep1):
-//   uh = sigma A^-1 ru;  p = -omega S^-1 (rp - Bbar uh);  u = uh + sigma A^-1 (ru - A uh - B^T p)
+// S^-1 of the chosen approximation (Sec. 5.2.3) applied to a mean-zero rp
+template <class R>
+void schur_inv(Ctx& c, const R* rp, R* out) {
+  if (c.par.schur == STK_SCHUR_MASS) {
+    solve_mass<R>(c, rp, out);   // eq. schurMass
+    project_mean<R>(c, out);
+    if (c.rep) c.rep->s_solves++;
+  } else {
+    schur_vbfbt<R>(c, rp, out);   // eq. schurV, or the diag(A)-BFBT
+  }
+}
+
+// Uzawa-type block preconditioners (Sec. 5.2.1), one step from (u, p) = 0:
+//   symmetric (eq. SymmetricUzawaStep1):
+//     uh = sigma A^-1 ru;  p = -omega S^-1 (rp - Bbar uh);  u = uh + sigma A^-1 (ru - A uh - B^T p)
+//   inexact (eq. InexactUzawaStep1):   u = sigma A^-1 ru;  p = -omega S^-1 (rp - Bbar u)
+//   adjoint (eq. AdjointInexactUzawaStep1):  p = -omega S^-1 rp;  u = sigma A^-1 (ru - B^T p)
+// Bbar = B + C in the pressure update when use_Bbar (Sec. 5.2.1, last remark).
 // For the transposed system the roles of B and Bbar swap.
 template <class R>
 void uzawa(Ctx& c, const R* ru, const R* rp, R* u, R* p, bool transpose) {
@@ -540,15 +572,37 @@ void uzawa(Ctx& c, const R* ru, const R* rp, R* u, R* p, bool transpose) {
   R* qp = L.ppool<R>().get(Q_U1, n1, c.s);
   const bool withC = c.has_rho && !transpose && c.par.use_Bbar;
   const bool withCt = c.has_rho && transpose;
+  const int variant = c.par.uzawa;
+  // p = -omega S^-1 (rp - Bbar v), v = nullptr for v = 0
+  auto pressure = [&](const R* v) {
+    vcopy<R>(rp, tp, n1, c.s);
+    if (v) {
+      applyB<R>(c, l, v, qp, withC, BCM_IN);
+      vaxpy<R>(R(-1), qp, tp, n1, c.s);
+    }
+    project_mean<R>(c, tp);
+    schur_inv<R>(c, tp, p);
+    vscale<R>(R(-c.par.omega), p, n1, c.s);
+    project_mean<R>(c, p);
+  };
+  if (variant == STK_UZAWA_ADJOINT) {
+    pressure(nullptr);
+    // u = sigma A^-1 (ru - B^T p)
+    vcopy<R>(ru, w, N, c.s);
+    applyBt<R>(c, l, p, t, withCt, BCM_OUT);
+    vaxpy<R>(R(-1), t, w, N, c.s);
+    project<R>(c, l, w);
+    solve_A<R>(c, w, u);
+    if (c.par.sigma != 1.0) vscale<R>(R(c.par.sigma), u, N, c.s);
+    return;
+  }
   solve_A<R>(c, ru, uh);
   if (c.par.sigma != 1.0) vscale<R>(R(c.par.sigma), uh, N, c.s);
-  applyB<R>(c, l, uh, qp, withC, BCM_IN);
-  vcopy<R>(rp, tp, n1, c.s);
-  vaxpy<R>(R(-1), qp, tp, n1, c.s);
-  project_mean<R>(c, tp);
-  schur_vbfbt<R>(c, tp, p);
-  vscale<R>(R(-c.par.omega), p, n1, c.s);
-  project_mean<R>(c, p);
+  pressure(uh);
+  if (variant == STK_UZAWA_INEXACT) {
+    vcopy<R>(uh, u, N, c.s);
+    return;
+  }
   applyA<R>(c, l, uh, t, BCM_IN | BCM_OUT);
   vcopy<R>(ru, w, N, c.s);
   vaxpy<R>(R(-1), t, w, N, c.s);
@@ -557,6 +611,31 @@ void uzawa(Ctx& c, const R* ru, const R* rp, R* u, R* p, bool transpose) {
   project<R>(c, l, w);
   solve_A<R>(c, w, u);
   vaxpby<R>(R(1), uh, R(c.par.sigma), u, N, c.s);
+}
+
+// The preconditioner as FGMRES applies it: FP32 (mixed) or FP64 Uzawa step on
+// the FP64 residual [v; v + N], result re-projected in FP64
+void precondition(Ctx& c, const double* v, double* z, bool transpose) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2, n1 = L.h.n1;
+  if (c.par.precision == 32) {
+    float* vu = L.pool<float>().get(W_F0, N, c.s);
+    float* zu = L.pool<float>().get(W_F1, N, c.s);
+    float* vp = L.ppool<float>().get(Q_F0, n1, c.s);
+    float* zp = L.ppool<float>().get(Q_F1, n1, c.s);
+    vconvert<double, float>(v, vu, N, c.s);
+    vconvert<double, float>(v + N, vp, n1, c.s);
+    uzawa<float>(c, vu, vp, zu, zp, transpose);
+    vconvert<float, double>(zu, z, N, c.s);
+    vconvert<float, double>(zp, z + N, n1, c.s);
+  } else {
+    uzawa<double>(c, v, v + N, z, z + N, transpose);
+  }
+  // keep the Krylov space exactly in range(P): FP32 projections leave
+  // normal components of relative size ~1e-7 at free-slip nodes
+  project<double>(c, l, z);
+  project_mean<double>(c, z + N);
 }
 
 // ---- FGMRES (Saad 1993), right preconditioned, FP64 -----------------------------
@@ -582,26 +661,7 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
     applyK<double>(c, x, x + N, y, y + N, transpose, BCM_IN | BCM_OUT);
     project_mean<double>(c, y + N);
   };
-  const bool mixed = c.par.precision == 32;
-  auto precond = [&](const double* v, double* z) {
-    if (mixed) {
-      float* vu = L.pool<float>().get(W_F0, N, c.s);
-      float* zu = L.pool<float>().get(W_F1, N, c.s);
-      float* vp = L.ppool<float>().get(Q_F0, n1, c.s);
-      float* zp = L.ppool<float>().get(Q_F1, n1, c.s);
-      vconvert<double, float>(v, vu, N, c.s);
-      vconvert<double, float>(v + N, vp, n1, c.s);
-      uzawa<float>(c, vu, vp, zu, zp, transpose);
-      vconvert<float, double>(zu, z, N, c.s);
-      vconvert<float, double>(zp, z + N, n1, c.s);
-    } else {
-      uzawa<double>(c, v, v + N, z, z + N, transpose);
-    }
-    // keep the Krylov space exactly in range(P): FP32 projections leave
-    // normal components of relative size ~1e-7 at free-slip nodes
-    project<double>(c, l, z);
-    project_mean<double>(c, z + N);
-  };
+  auto precond = [&](const double* v, double* z) { precondition(c, v, z, transpose); };
   FgmresOut out;
   vfill<double>(xu, 0.0, N, c.s);
   vfill<double>(xp, 0.0, n1, c.s);
@@ -861,6 +921,8 @@ void check_params(const stk_solver_params* p) {
   REQUIRE(p->m_A >= 1 && p->deg_A >= 1 && p->m_V >= 1 && p->deg_V >= 1, "smoother steps/degree must be >= 1");
   REQUIRE(p->cheb_lo > 0 && p->cheb_hi > p->cheb_lo, "bad Chebyshev interval factors");
   REQUIRE(p->max_inner >= 1 && p->max_outer >= 1 && p->power_its >= 1, "iteration caps must be >= 1");
+  REQUIRE(p->uzawa >= STK_UZAWA_SYMMETRIC && p->uzawa <= STK_UZAWA_ADJOINT, "unknown Uzawa variant");
+  REQUIRE(p->schur >= STK_SCHUR_VBFBT && p->schur <= STK_SCHUR_DIAG_BFBT, "unknown Schur approximation");
 }
 
 // power iteration for lambda_max(D^-1 A) with projections, FP64
@@ -1307,6 +1369,27 @@ static int solve_common(stk_ctx* ctx, const stk_solver_params* params, const dou
   if (rc != STK_OK) return rc;
   if (status == STK_ENOCONV) g_err = "FGMRES reached max_outer before the tolerance";
   return status;
+}
+
+int stk_precondition(stk_ctx* ctx, const stk_solver_params* params, const double* ru, const double* rp, double* zu,
+                     double* zp, int transpose) {
+  return guard([&] {
+    need_ready(ctx);
+    check_params(params);
+    REQUIRE(ru && rp && zu && zp, "null vector");
+    ctx->par = *params;
+    LevelData& F = ctx->at(ctx->L());
+    const long long N = 3 * F.h.n2, n1 = F.h.n1;
+    double* v = F.pool<double>().get(W_PC0, N + n1, ctx->s);
+    double* z = F.pool<double>().get(W_PC1, N + n1, ctx->s);
+    vcopy<double>(ru, v, N, ctx->s);
+    vcopy<double>(rp, v + N, n1, ctx->s);
+    precondition(*ctx, v, z, transpose != 0);
+    vcopy<double>(z, zu, N, ctx->s);
+    vcopy<double>(z + N, zp, n1, ctx->s);
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    HIPCHK(hipGetLastError());
+  });
 }
 
 int stk_solve(stk_ctx* ctx, const stk_solver_params* params, const double* f_u, const double* g_p,

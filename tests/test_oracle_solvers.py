@@ -5,7 +5,7 @@ import scipy.sparse.linalg as spla
 
 from oracle.fem import assemble_A, assemble_B
 from oracle.mesh import RefinedMesh, cube_macros, shell_macros
-from oracle.solvers import (bfbt, chebyshev, chebyshev_error_polynomial, fgmres, pcg,
+from oracle.solvers import (adjoint_uzawa, inexact_uzawa, bfbt, chebyshev, chebyshev_error_polynomial, fgmres, pcg,
                             prolongation, symmetric_uzawa, vcycle, vector_prolongation)
 from oracle.system import solve_stokes, velocity_basis
 
@@ -123,6 +123,39 @@ def test_fgmres_with_exact_symmetric_uzawa_converges_in_one_step():
     # with an inexact preconditioner FGMRES still converges to the solution
     x, it, hist = fgmres(lambda v: K @ v, b, lambda v: v / 10.0, 1e-11, restart=40)
     assert np.linalg.norm(K @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_inexact_and_adjoint_uzawa_are_the_block_triangular_solves():
+    """With exact inner solves and S = Bbar A^-1 B^T, one inexact Uzawa step
+    from zero solves the lower block-triangular system [[A, 0], [Bbar, -S/omega]]
+    (scaled by sigma) and the adjoint step the upper one [[A, B^T], [0, -S/omega]];
+    FGMRES preconditioned by either converges in two iterations."""
+    rng = np.random.default_rng(7)
+    n, m = 14, 6
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    B = rng.standard_normal((m, n))
+    Bbar = B + 0.1 * rng.standard_normal((m, n))
+    S = Bbar @ np.linalg.solve(A, B.T)
+    K = np.block([[A, B.T], [Bbar, np.zeros((m, m))]])
+    Ainv = lambda r: np.linalg.solve(A, r)
+    Sinv = lambda r: np.linalg.solve(S, r)
+    ru, rp = rng.standard_normal(n), rng.standard_normal(m)
+    sigma, omega = 0.8, 0.3
+    u, p = inexact_uzawa(ru, rp, Bbar, Ainv, Sinv, sigma, omega)
+    lower = np.block([[A / sigma, np.zeros((n, m))], [Bbar, -S / omega]])
+    ref = np.linalg.solve(lower, np.concatenate([ru, rp]))
+    assert np.allclose(np.concatenate([u, p]), ref, rtol=1e-11, atol=1e-12)
+    u, p = adjoint_uzawa(ru, rp, B.T, Ainv, Sinv, sigma, omega)
+    upper = np.block([[A / sigma, B.T], [np.zeros((m, n)), -S / omega]])
+    ref = np.linalg.solve(upper, np.concatenate([ru, rp]))
+    assert np.allclose(np.concatenate([u, p]), ref, rtol=1e-11, atol=1e-12)
+    b = rng.standard_normal(n + m)
+    for step in (lambda v: inexact_uzawa(v[:n], v[n:], Bbar, Ainv, Sinv, 1.0, 1.0),
+                 lambda v: adjoint_uzawa(v[:n], v[n:], B.T, Ainv, Sinv, 1.0, 1.0)):
+        x, it, hist = fgmres(lambda v: K @ v, b, lambda v: np.concatenate(step(v)), 1e-12, restart=10)
+        assert it <= 2
+        assert np.allclose(K @ x, b, atol=1e-10)
 
 
 def test_pcg_and_direct_solve_agree():
