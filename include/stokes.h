@@ -154,7 +154,8 @@ int stk_diag_A(stk_ctx* ctx, int level, double* d);
 int stk_cheb_bounds(stk_ctx* ctx, int level, double* lo, double* hi);
 int stk_set_cheb_bounds(stk_ctx* ctx, int level, double lo, double hi);
 /* `steps` applications of the degree-`degree` Jacobi-Chebyshev polynomial to
- * A x = b on `level` with projections (Sec. 5.2.2); x updated in place. */
+ * A x = b on `level` with projections (Sec. 5.2.2); x updated in place.  b
+ * and x are expected admissible (projected); x leaves projected. */
 int stk_smooth(stk_ctx* ctx, int level, int prec, const void* b, void* x, int degree, int steps);
 /* Canonical P2 prolongation from `level`-1 to `level` (ef overwritten) and
  * its transpose (rc overwritten), with projections on the output. */

@@ -185,15 +185,21 @@ template <typename R> void vmul(const R* a, const R* x, R* y, long long n, hipSt
 template <typename A, typename B> void vconvert(const A* x, B* y, long long n, hipStream_t s);
 template <typename R> void vinvert(const R* d, R* y, long long n, hipStream_t s);          // y = 1/d (0 -> 1)
 void vexp(const double* x, double* y, long long n, hipStream_t s);
-// Chebyshev helpers (see solver): d = c1 * Dinv .* r  + c2 * d
-template <typename R> void vcheb_dir(const R* dinv, const R* r, R c1, R c2, R* d, long long n, hipStream_t s);
+// Chebyshev smoother updates; xin = false: x enters as zero and is not read.
 // r = b - t (t nullable: r = b); d = c1 dinv .* r
 template <typename R> void vcheb_start(const R* b, const R* t, const R* dinv, R c1, R* r, R* d, long long n, hipStream_t s);
+// one degree-1 step: x += c1 dinv .* (b - t) (t nullable)
+template <typename R> void vcheb_one(const R* b, const R* t, const R* dinv, R c1, R* x, bool xin, long long n, hipStream_t s);
 // r -= t; x += d; d = c1 dinv .* r + c2 d
-template <typename R> void vcheb_step(const R* t, const R* dinv, R c1, R c2, R* r, R* x, R* d, long long n, hipStream_t s);
+template <typename R> void vcheb_step(const R* t, const R* dinv, R c1, R c2, R* r, R* x, R* d, bool xin, long long n, hipStream_t s);
+// the last step of a degree: x += d + (c1 dinv .* (r - t) + c2 d)
+template <typename R> void vcheb_last(const R* t, const R* dinv, R c1, R c2, const R* r, const R* d, R* x, bool xin, long long n, hipStream_t s);
 template <typename R> void vsub(const R* b, const R* t, R* r, long long n, hipStream_t s);   // r = b - t
 // Deterministic two-stage dot product accumulated in FP64; result to device *out.
 template <typename R> void vdot(const R* x, const R* y, long long n, double* partial, double* out, hipStream_t s);
+// x += a p; r += b q; *out = |r|^2 (FP64, deterministic, same partial layout as vdot)
+template <typename R>
+void vaxpy2_nrm(R a, const R* p, R* x, R b, const R* q, R* r, long long n, double* partial, double* out, hipStream_t s);
 void vsum_partials(double* partial, int np, double* out, hipStream_t s);
 constexpr int DOT_BLOCKS = 1024;
 // device-resident Jacobi CG pieces (scalars in sc[], partial sums in part[],

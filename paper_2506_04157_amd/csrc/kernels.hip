@@ -74,6 +74,14 @@ __device__ __forceinline__ int lloc(int I, int J, int K, int m) {
 __device__ __forceinline__ int wmask(int I, int J, int K, int m) {
   return ((m - I - J - K) > 0) | ((I > 0) << 1) | ((J > 0) << 2) | ((K > 0) << 3);
 }
+// Global index of P2 lattice point (I,J,K) (side m, weight mask `mask`) of
+// macro `mac`; l2 is the macro's local-to-global table.  Macro-interior points
+// are numbered macro by macro in lattice order, so theirs is closed-form (the
+// mesh builder checks this) and needs no table load.
+__device__ __forceinline__ size_t p2_gidx(const uint32_t* l2, int mac, int I, int J, int K, int m, int mask) {
+  return mask == 15 ? (size_t)mac * (size_t)tetc(m - 4) + (size_t)lloc(I - 1, J - 1, K - 1, m - 4)
+                    : (size_t)l2[lloc(I, J, K, m)];
+}
 
 // reciprocal and reciprocal square root: hardware approximation refined by
 // Newton steps (two in FP64, giving full double accuracy)
@@ -1324,7 +1332,8 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
   const uint32_t* l2f = Lf.l2g2 + (size_t)mac * Lf.nloc2;
   const R* G = geo_of<R>(Lc) + (size_t)mac * 16;
   const uint8_t* bact = Lc.bact + (size_t)mac * 16;
-  const uint8_t* own = Lf.own + (size_t)mac * 16;
+  // the macro's 16 ownership bytes (16-byte aligned), held in registers
+  const uint4 ownw = *reinterpret_cast<const uint4*>(Lf.own + (size_t)mac * 16);
   const size_t Nc = (size_t)Lc.n2, Nf = (size_t)Lf.n2;
   {
     // coarse brick: staged values (prolongation) or zeroed accumulators
@@ -1335,7 +1344,8 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
       const int i = threadIdx.x + 256 * k;
       const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
       const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
-      g[k] = (PRO && i < NB2 && I + J + K <= mc2) ? (size_t)l2c[lloc(I, J, K, mc2)] : ~(size_t)0;
+      g[k] = (PRO && i < NB2 && I + J + K <= mc2) ? p2_gidx(l2c, mac, I, J, K, mc2, wmask(I, J, K, mc2))
+                                                   : ~(size_t)0;
     }
     R v[NS][3];
 #pragma unroll
@@ -1375,8 +1385,10 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
     for (int k = 0; k < NB; ++k) {
       const int JX = ta[k].x & 1023, JY = (ta[k].x >> 10) & 1023, JZ = (ta[k].x >> 20) & 1023;
       mask[k] = wmask(JX, JY, JZ, mf2);
-      ok[k] = ok[k] && own[mask[k]];
-      gf[k] = ok[k] ? (size_t)l2f[lloc(JX, JY, JZ, mf2)] : 0;
+      const int mk = mask[k];
+      const unsigned ow = mk < 4 ? ownw.x : (mk < 8 ? ownw.y : (mk < 12 ? ownw.z : ownw.w));
+      ok[k] = ok[k] && ((ow >> (8 * (mk & 3))) & 0xffu) != 0;
+      gf[k] = ok[k] ? p2_gidx(l2f, mac, JX, JY, JZ, mf2, mk) : 0;
     }
     R v[NB][3];
     if (!PRO || MODE == 2) {
@@ -1448,7 +1460,7 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
         if (act == ACT_DIR) continue;
         bc_project<R>(act, G, I, J, K, mc2, v0, v1, v2);
       }
-      const size_t g = l2c[lloc(I, J, K, mc2)];
+      const size_t g = p2_gidx(l2c, mac, I, J, K, mc2, mask);
       const bool excl = mask == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
       if (excl) {
         out[g] = v0;
@@ -1534,12 +1546,8 @@ template <typename R> __global__ void k_invert(const R* __restrict__ d, R* __res
 __global__ void k_exp(const double* __restrict__ x, double* __restrict__ y, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = exp(x[i]);
 }
-template <typename R>
-__global__ void k_cheb_dir(const R* __restrict__ dinv, const R* __restrict__ r, R c1, R c2, R* __restrict__ d, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    d[i] = (c2 == R(0)) ? c1 * dinv[i] * r[i] : c1 * dinv[i] * r[i] + c2 * d[i];
-}
-// Chebyshev smoother pieces (fused vector updates)
+// Chebyshev smoother pieces (fused vector updates).  xin = 0: x enters as zero
+// and is not read.
 template <typename R>
 __global__ void k_cheb_start(const R* __restrict__ b, const R* __restrict__ t, const R* __restrict__ dinv, R c1,
                              R* __restrict__ r, R* __restrict__ d, long long n) {
@@ -1550,14 +1558,33 @@ __global__ void k_cheb_start(const R* __restrict__ b, const R* __restrict__ t, c
   }
 }
 template <typename R>
+__global__ void k_cheb_one(const R* __restrict__ b, const R* __restrict__ t, const R* __restrict__ dinv, R c1,
+                           R* __restrict__ x, int xin, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R ri = t ? b[i] - t[i] : b[i];
+    const R di = c1 * dinv[i] * ri;
+    x[i] = xin ? x[i] + di : di;
+  }
+}
+template <typename R>
 __global__ void k_cheb_step(const R* __restrict__ t, const R* __restrict__ dinv, R c1, R c2, R* __restrict__ r,
-                            R* __restrict__ x, R* __restrict__ d, long long n) {
+                            R* __restrict__ x, R* __restrict__ d, int xin, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const R ri = r[i] - t[i];
     const R di = d[i];
     r[i] = ri;
-    x[i] += di;
+    x[i] = xin ? x[i] + di : di;
     d[i] = c1 * dinv[i] * ri + c2 * di;
+  }
+}
+template <typename R>
+__global__ void k_cheb_last(const R* __restrict__ t, const R* __restrict__ dinv, R c1, R c2, const R* __restrict__ r,
+                            const R* __restrict__ d, R* __restrict__ x, int xin, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R ri = r[i] - t[i];
+    const R di = d[i];
+    const R xi = xin ? x[i] + di : di;
+    x[i] = xi + (c1 * dinv[i] * ri + c2 * di);
   }
 }
 template <typename R>
@@ -1572,6 +1599,27 @@ __global__ __launch_bounds__(256) void k_dot(const R* __restrict__ x, const R* _
   double s = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     s += (double)x[i] * (double)y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+// x += a p; r += b q; partial[block] = sum of the new r_i^2 (FP64)
+template <typename R>
+__global__ __launch_bounds__(256) void k_axpy2_nrm(R a, const R* __restrict__ p, R* __restrict__ x, R b,
+                                                   const R* __restrict__ q, R* __restrict__ r, long long n,
+                                                   double* partial) {
+  __shared__ double red[256];
+  double s = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const R ri = r[i] + b * q[i];
+    r[i] = ri;
+    s += (double)ri * (double)ri;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -1942,14 +1990,17 @@ template <typename R> void vmul(const R* a, const R* x, R* y, long long n, hipSt
 template <typename A, typename B> void vconvert(const A* x, B* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_convert<A, B>), dim3(vgrid(n)), dim3(256), 0, s, x, y, n); }
 template <typename R> void vinvert(const R* d, R* y, long long n, hipStream_t s) { hipLaunchKernelGGL((k_invert<R>), dim3(vgrid(n)), dim3(256), 0, s, d, y, n); }
 void vexp(const double* x, double* y, long long n, hipStream_t s) { hipLaunchKernelGGL(k_exp, dim3(vgrid(n)), dim3(256), 0, s, x, y, n); }
-template <typename R> void vcheb_dir(const R* dinv, const R* r, R c1, R c2, R* d, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cheb_dir<R>), dim3(vgrid(n)), dim3(256), 0, s, dinv, r, c1, c2, d, n);
-}
 template <typename R> void vcheb_start(const R* b, const R* t, const R* dinv, R c1, R* r, R* d, long long n, hipStream_t s) {
   hipLaunchKernelGGL((k_cheb_start<R>), dim3(vgrid(n)), dim3(256), 0, s, b, t, dinv, c1, r, d, n);
 }
-template <typename R> void vcheb_step(const R* t, const R* dinv, R c1, R c2, R* r, R* x, R* d, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cheb_step<R>), dim3(vgrid(n)), dim3(256), 0, s, t, dinv, c1, c2, r, x, d, n);
+template <typename R> void vcheb_one(const R* b, const R* t, const R* dinv, R c1, R* x, bool xin, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_one<R>), dim3(vgrid(n)), dim3(256), 0, s, b, t, dinv, c1, x, (int)xin, n);
+}
+template <typename R> void vcheb_step(const R* t, const R* dinv, R c1, R c2, R* r, R* x, R* d, bool xin, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_step<R>), dim3(vgrid(n)), dim3(256), 0, s, t, dinv, c1, c2, r, x, d, (int)xin, n);
+}
+template <typename R> void vcheb_last(const R* t, const R* dinv, R c1, R c2, const R* r, const R* d, R* x, bool xin, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_last<R>), dim3(vgrid(n)), dim3(256), 0, s, t, dinv, c1, c2, r, d, x, (int)xin, n);
 }
 template <typename R> void vsub(const R* b, const R* t, R* r, long long n, hipStream_t s) {
   hipLaunchKernelGGL((k_sub<R>), dim3(vgrid(n)), dim3(256), 0, s, b, t, r, n);
@@ -1958,6 +2009,13 @@ template <typename R> void vdot(const R* x, const R* y, long long n, double* par
   long long g = (n + 255) / 256;
   int nb = (int)(g < DOT_BLOCKS ? (g < 1 ? 1 : g) : DOT_BLOCKS);
   hipLaunchKernelGGL((k_dot<R>), dim3(nb), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, nb, out);
+}
+template <typename R>
+void vaxpy2_nrm(R a, const R* p, R* x, R b, const R* q, R* r, long long n, double* partial, double* out, hipStream_t s) {
+  long long g = (n + 255) / 256;
+  int nb = (int)(g < DOT_BLOCKS ? (g < 1 ? 1 : g) : DOT_BLOCKS);
+  hipLaunchKernelGGL((k_axpy2_nrm<R>), dim3(nb), dim3(256), 0, s, a, p, x, b, q, r, n, partial);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, nb, out);
 }
 void vsum_partials(double* partial, int np, double* out, hipStream_t s) {
@@ -1972,10 +2030,12 @@ void vsum_partials(double* partial, int np, double* out, hipStream_t s) {
   template void vscale<R>(R, R*, long long, hipStream_t);                          \
   template void vmul<R>(const R*, const R*, R*, long long, hipStream_t);           \
   template void vinvert<R>(const R*, R*, long long, hipStream_t);                  \
-  template void vcheb_dir<R>(const R*, const R*, R, R, R*, long long, hipStream_t); \
   template void vdot<R>(const R*, const R*, long long, double*, double*, hipStream_t);         \
+  template void vaxpy2_nrm<R>(R, const R*, R*, R, const R*, R*, long long, double*, double*, hipStream_t); \
   template void vcheb_start<R>(const R*, const R*, const R*, R, R*, R*, long long, hipStream_t); \
-  template void vcheb_step<R>(const R*, const R*, R, R, R*, R*, R*, long long, hipStream_t);    \
+  template void vcheb_one<R>(const R*, const R*, const R*, R, R*, bool, long long, hipStream_t); \
+  template void vcheb_step<R>(const R*, const R*, R, R, R*, R*, R*, bool, long long, hipStream_t); \
+  template void vcheb_last<R>(const R*, const R*, R, R, const R*, const R*, R*, bool, long long, hipStream_t); \
   template void vsub<R>(const R*, const R*, R*, long long, hipStream_t);
 INST_V(double)
 INST_V(float)

@@ -2,6 +2,7 @@
 #include "mesh.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <stdexcept>
@@ -324,7 +325,13 @@ Level build_level(const MacroMesh& mm, const Topology& top, int L) {
           for (int I = 0; I <= m - J - K; ++I, ++l) {
             int w[4] = {m - I - J - K, I, J, K};
             for (int k = 0; k < 4; ++k) loc_w[4 * l + k] = w[k];
-            if (w[0] > 0 && I > 0 && J > 0 && K > 0) loc_int[l] = (int)ni++;
+            if (w[0] > 0 && I > 0 && J > 0 && K > 0) {
+              // the kernels compute a macro-interior index in closed form as
+              // the lattice index of (I-1, J-1, K-1) in the side m-4 lattice
+              if (lattice_loc(I - 1, J - 1, K - 1, m - 4) != ni)
+                throw std::runtime_error("interior numbering is not the shifted lattice order");
+              loc_int[l] = (int)ni++;
+            }
           }
     }
     for (int mc = 0; mc < nm; ++mc) {
@@ -695,8 +702,13 @@ TransferTable build_transfer_table(const Level& coarse) {
       for (int c = 0; c < 3; ++c) tinv[t][r][c] = (int)std::lround(Mi[r][c]);
   }
   const int ntiles = (int)coarse.tiles.size() / 3;
+  // Entry order within a tile: fine points inside the macro first (a
+  // wavefront of them loads no index table), then those on its boundary;
+  // lattice order within each group (rows of consecutive fine nodes)
+  std::vector<std::pair<int64_t, std::array<int, 8>>> ent;
   for (int ti = 0; ti < ntiles; ++ti) {
     tt.off.push_back((int)(tt.tab.size() / 8));
+    ent.clear();
     const int ox = coarse.tiles[3 * ti], oy = coarse.tiles[3 * ti + 1], oz = coarse.tiles[3 * ti + 2];
     const int lox = ox > 0, loy = oy > 0, loz = oz > 0;
     for (int az = loz; az < BFh; ++az)
@@ -745,11 +757,17 @@ TransferTable build_transfer_table(const Level& coarse) {
               packed[nnz++] = idx[a] | ((w[a] + 1) << 10);
             }
           for (int a = nnz; a < 10; ++a) packed[a] = 0;
-          tt.tab.push_back(JX | (JY << 10) | (JZ << 20));
-          tt.tab.push_back(nnz);
-          for (int k = 0; k < 5; ++k) tt.tab.push_back(packed[2 * k] | (packed[2 * k + 1] << 16));
-          tt.tab.push_back(0);
+          const bool interior = JX > 0 && JY > 0 && JZ > 0 && JX + JY + JZ < mf2;
+          std::array<int, 8> e;
+          e[0] = JX | (JY << 10) | (JZ << 20);
+          e[1] = nnz;
+          for (int k = 0; k < 5; ++k) e[2 + k] = packed[2 * k] | (packed[2 * k + 1] << 16);
+          e[7] = 0;
+          ent.emplace_back(interior ? 0 : 1, e);
         }
+    std::stable_sort(ent.begin(), ent.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (const auto& e : ent) tt.tab.insert(tt.tab.end(), e.second.begin(), e.second.end());
   }
   tt.off.push_back((int)(tt.tab.size() / 8));
   return tt;

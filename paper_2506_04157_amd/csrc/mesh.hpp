@@ -125,6 +125,9 @@ P1Stencil build_p1_stencil(int n);
 // index, 10 bits | (8 * weight + 1) << 10), in the coarse micro-tet's node
 // order; padding.
 struct TransferTable {
+  // per tile: the fine points of its coarse cubes, those inside the macro
+  // first (their global index is closed-form), each as 8 ints: packed
+  // position, weight count, 5 words of two (brick index | (8 w + 1) << 10)
   std::vector<int> tab;
   std::vector<int> off;   // per tile: first entry (ntiles + 1)
 };

@@ -222,6 +222,14 @@ double dot(Ctx& c, const R* x, const R* y, long long n) {
 }
 template <class R>
 double nrm2(Ctx& c, const R* x, long long n) { return std::sqrt(dot<R>(c, x, x, n)); }
+// CG update x += alpha p, r -= alpha q; returns |r| of the updated r
+template <class R>
+double cg_step_nrm(Ctx& c, double alpha, const R* p, R* x, const R* q, R* r, long long n) {
+  vaxpy2_nrm<R>(R(alpha), p, x, R(-alpha), q, r, n, c.dotbuf.p, c.dotbuf.p + 2 * DOT_BLOCKS, c.s);
+  HIPCHK(hipMemcpyAsync(c.hpin, c.dotbuf.p + 2 * DOT_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  HIPCHK(hipStreamSynchronize(c.s));
+  return std::sqrt(*c.hpin);
+}
 
 template <class R>
 void project(Ctx& c, int l, R* v) {
@@ -292,24 +300,31 @@ void chebyshev(Ctx& c, int l, const R* b, R* x, int steps, int deg, bool xzero) 
   R* t = L.pool<R>().get(W_T, N, c.s);
   const R* dinv = L.dinvp<R>();
   for (int st = 0; st < steps; ++st) {
-    // r = P (b - A x): b is projected and A's output too, so no extra projection
-    if (xzero && st == 0) {
-      vcheb_start<R>(b, nullptr, dinv, R(1.0 / theta), r, d, N, c.s);
+    // r = b - A x (b and A's output are projected).  The directions d stay
+    // unprojected: A projects its input, and since the projection is linear
+    // and x enters projected, projecting x after the step leaves exactly the
+    // sum of the projected directions.
+    const bool x0 = xzero && st == 0;   // x enters as zero
+    if (!x0) applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
+    if (deg == 1) {
+      vcheb_one<R>(b, x0 ? nullptr : t, dinv, R(1.0 / theta), x, !x0, N, c.s);
     } else {
-      applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
-      vcheb_start<R>(b, t, dinv, R(1.0 / theta), r, d, N, c.s);
+      vcheb_start<R>(b, x0 ? nullptr : t, dinv, R(1.0 / theta), r, d, N, c.s);
+      double rho_old = 1.0 / sigma;
+      for (int k = 1; k < deg; ++k) {
+        // x += d; r -= A d; d = 2 rho/delta D^-1 r + rho rho_old d (the last
+        // direction goes into x at once)
+        applyA<R>(c, l, d, t, BCM_IN | BCM_OUT);
+        const double rho = 1.0 / (2.0 * sigma - rho_old);
+        const bool xin = !(x0 && k == 1);
+        if (k + 1 < deg)
+          vcheb_step<R>(t, dinv, R(2.0 * rho / delta), R(rho * rho_old), r, x, d, xin, N, c.s);
+        else
+          vcheb_last<R>(t, dinv, R(2.0 * rho / delta), R(rho * rho_old), r, d, x, xin, N, c.s);
+        rho_old = rho;
+      }
     }
-    project<R>(c, l, d);
-    double rho_old = 1.0 / sigma;
-    for (int k = 1; k < deg; ++k) {
-      // x += d; r -= A d; d = 2 rho/delta D^-1 r + rho rho_old d
-      applyA<R>(c, l, d, t, BCM_IN | BCM_OUT);
-      const double rho = 1.0 / (2.0 * sigma - rho_old);
-      vcheb_step<R>(t, dinv, R(2.0 * rho / delta), R(rho * rho_old), r, x, d, N, c.s);
-      project<R>(c, l, d);
-      rho_old = rho;
-    }
-    vaxpy<R>(R(1), d, x, N, c.s);
+    project<R>(c, l, x);
   }
 }
 
@@ -387,8 +402,7 @@ void vcycle(Ctx& c, int l, const R* b, R* x, int steps, int deg) {
   LevelData& L = c.at(l);
   LevelData& C = c.at(l - 1);
   const long long N = 3 * L.h.n2, Nc = 3 * C.h.n2;
-  vfill<R>(x, R(0), N, c.s);
-  chebyshev<R>(c, l, b, x, steps, deg, true);
+  chebyshev<R>(c, l, b, x, steps, deg, true);   // writes x without reading it
   R* t = L.pool<R>().get(W_T, N, c.s);
   applyA<R>(c, l, x, t, BCM_IN | BCM_OUT);
   R* bc = C.pool<R>().get(W_B, Nc, c.s);
@@ -425,9 +439,7 @@ void solve_A(Ctx& c, const R* b, R* x) {
     if (c.rep) c.rep->a_cg_its++;
     applyA<R>(c, l, p, q, BCM_IN | BCM_OUT);
     const double alpha = rz / dot<R>(c, p, q, N);
-    vaxpy<R>(R(alpha), p, x, N, c.s);
-    vaxpy<R>(R(-alpha), q, r, N, c.s);
-    if (nrm2<R>(c, r, N) <= c.par.tol_A * nb) break;
+    if (cg_step_nrm<R>(c, alpha, p, x, q, r, N) <= c.par.tol_A * nb) break;
     vcycle<R>(c, l, r, z, c.par.m_A, c.par.deg_A);
     const double rz2 = dot<R>(c, r, z, N);
     vaxpby<R>(R(1), z, R(rz2 / rz), p, N, c.s);
@@ -508,9 +520,7 @@ void solve_SC(Ctx& c, const R* b, R* x) {
     if (c.rep) c.rep->s_cg_its++;
     apply_SC<R>(c, p, q);
     const double alpha = rz / dot<R>(c, p, q, n1);
-    vaxpy<R>(R(alpha), p, x, n1, c.s);
-    vaxpy<R>(R(-alpha), q, r, n1, c.s);
-    if (nrm2<R>(c, r, n1) <= c.par.tol_vbfbt * nb) break;
+    if (cg_step_nrm<R>(c, alpha, p, x, q, r, n1) <= c.par.tol_vbfbt * nb) break;
     solve_mass<R>(c, r, z);
     project_mean<R>(c, z);
     const double rz2 = dot<R>(c, r, z, n1);
