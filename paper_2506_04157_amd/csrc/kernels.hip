@@ -1837,10 +1837,13 @@ static void stokes_dispatch(const LevelDev& L, const R* u, const R* p, const R* 
   }
   dim3 grid((unsigned)(L.sw.nstrips * L.nmacro));
   const size_t lds = sweep_lds_bytes(FL, L.sw.cap2, L.sw.cap1, sizeof(R));
+  // a layer of a macro holds about n^2 micro-tets: smaller workgroups on the
+  // coarser levels keep the threads busy and let more macros run per CU
+  const unsigned bsz = L.n <= 4 ? 64 : (L.n <= 8 ? 128 : 256);
   if (L.blend)
-    hipLaunchKernelGGL((k_sweep<R, true, FL>), grid, dim3(256), lds, s, L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode);
+    hipLaunchKernelGGL((k_sweep<R, true, FL>), grid, dim3(bsz), lds, s, L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode);
   else
-    hipLaunchKernelGGL((k_sweep<R, false, FL>), grid, dim3(256), lds, s, L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode);
+    hipLaunchKernelGGL((k_sweep<R, false, FL>), grid, dim3(bsz), lds, s, L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode);
 }
 
 template <typename R>
