@@ -119,3 +119,19 @@ def smooth_vector_field(seed, xyz, k=3):
         a = rng.uniform(-1, 1, 3)
         out += np.sin(xyz @ w + ph)[:, None] * a[None, :]
     return out
+
+
+def plate_velocity(seed, xyz, n_plates=6, scale=0.5):
+    """Synthetic tangential surface velocity: the sphere split into
+    ``n_plates`` Voronoi plates around seeded centres, each rotating rigidly
+    about its own seeded Euler pole, u = scale * omega_k x X.  Stands in for a
+    plate reconstruction (the factor 1/2 as in the paper's model setup)."""
+    rng = np.random.default_rng(seed)
+    xyz = np.asarray(xyz, dtype=np.float64)
+    centres = rng.normal(size=(n_plates, 3))
+    centres /= np.linalg.norm(centres, axis=1)[:, None]
+    poles = rng.normal(0.0, 1.0, size=(n_plates, 3))
+    r = np.linalg.norm(xyz, axis=1)
+    unit = xyz / np.where(r > 0, r, 1.0)[:, None]
+    plate = np.argmax(unit @ centres.T, axis=1)
+    return scale * np.cross(poles[plate], xyz)

@@ -215,4 +215,31 @@ void cg_update(const R* p, const R* q, const R* dinv, R* x, R* r, R* z, long lon
 template <typename R>
 void cg_pupdate(const R* z, R* p, long long n, double* part, double* sc, int parity, hipStream_t s);
 
+// Coarsest-level operator held as element matrices, and the node-based data of
+// its CG (FP64).  Vectors are component-major (3 * nn).
+struct CoarseDev {
+  int ne;                  // micro-tets of the level
+  int nn;                  // P2 nodes
+  const uint32_t* enode;   // 10 global P2 nodes per element (local node order of the element kernels)
+  const double* emat;      // 900 per element: A_e column-major, local DoF index c * 10 + a
+  const float* ematf;      // the same rounded to FP32 (coarse solves of the FP32 preconditioner)
+  const int* iptr;         // per node: its incidences (element, local node) are slots iptr[i] .. iptr[i+1]-1
+  const int* epos;         // per element and local node (e * 10 + a): its incidence slot
+  const uint8_t* act;      // per node: ACT_NONE, ACT_DIR or ACT_FS
+  const double* nrm;       // 3 per node: free-slip normal (0 elsewhere)
+  const double* dinv;      // inverse diagonal of A, 3 * nn
+};
+constexpr int CCG_ELEMS = 8;   // elements per workgroup of the element kernel (30 threads each)
+// A_e of every micro-tet of level L (eta: P1 nodal, FP64), in FP64 and FP32
+void launch_elem_matrix(const LevelDev& L, const double* eta, double* emat, float* ematf, hipStream_t s);
+// CG on the coarsest level: x = 0, r = P b, z = P D^-1 r, partials and scalars
+void ccg_init(const CoarseDev& cd, const double* b, double* x, double* r, double* z, double tol, double* part,
+              double* sc, hipStream_t s);
+// iteration `it` (0-based): p = z + beta p (p = z at it 0), q = P A p (as
+// P A z + beta q), x += alpha p, r -= alpha q, z = P D^-1 r; Y: 30 doubles per
+// element, stored by incidence slot (component c at slot + c * 10 ne); fp32:
+// products with the FP32 element matrices (FP64 accumulation)
+void ccg_iter(const CoarseDev& cd, bool fp32, double* x, double* r, double* z, double* p, double* q, double* Y,
+              double* part, double* sc, int it, hipStream_t s);
+
 }  // namespace stk

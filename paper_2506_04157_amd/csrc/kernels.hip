@@ -1683,6 +1683,10 @@ __device__ __forceinline__ void block_partials(double a, double b, double* pa, d
 }
 __device__ __forceinline__ double* cg_rr(double* part, int parity) { return part + DOT_BLOCKS + 2 * DOT_BLOCKS * parity; }
 __device__ __forceinline__ double* cg_rz(double* part, int parity) { return cg_rr(part, parity) + DOT_BLOCKS; }
+__device__ __forceinline__ const double* cg_rr(const double* part, int parity) {
+  return part + DOT_BLOCKS + 2 * DOT_BLOCKS * parity;
+}
+__device__ __forceinline__ const double* cg_rz(const double* part, int parity) { return cg_rr(part, parity) + DOT_BLOCKS; }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_cg_init(const R* __restrict__ r, const R* __restrict__ dinv,
@@ -1775,6 +1779,307 @@ __global__ __launch_bounds__(256) void k_cg_p(double* sc, const R* __restrict__ 
   const R beta = R(rz / rzo);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
+}
+
+// ---- coarsest level: CG on stored element matrices -----------------------------
+// The coarse solve (Sec. 5.2.2) runs many short iterations on a small level,
+// where the element kernel is one long FP64 latency chain per thread.  The
+// level's element matrices are therefore formed once per viscosity field, and
+// an iteration is three kernels: element products A_e z_e, a node pass that
+// sums them over the incident elements, projects, and forms p = z + beta p and
+// q = A p = A z + beta q, and a node pass for the x, r, z updates.  Node
+// passes hold the three components of a node, so the projections need no
+// kernel of their own.
+
+// column j of A_e of every micro-tet e (one thread per (e, j)): the element
+// operator applied to the j-th unit vector, no boundary projection
+template <bool BLEND>
+__global__ __launch_bounds__(256) void k_elem_matrix(LevelDev L, const double* __restrict__ eta,
+                                                     double* __restrict__ emat, float* __restrict__ ematf) {
+  using E = StokesElem<double, BLEND, F_A>;
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int n = L.n;
+  const int ne = n * n * n;
+  if (gid >= (long long)ne * L.nmacro * 30) return;
+  const long long e = gid / 30;
+  const int j = (int)(gid - e * 30);
+  const int mac = (int)(e / ne);
+  const int pk = L.eall[e - (long long)mac * ne];
+  const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const double* G = L.geo + (size_t)mac * 16;
+  size_t g1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    g1[v] = l1[lloc(px + c_toff[type][v][0], py + c_toff[type][v][1], pz + c_toff[type][v][2], n)];
+  double xv[4][3];
+  if (BLEND) elem_vertices<double>(G, type, px, py, pz, n, xv);
+  E el;
+  el.load(
+      L.tinv + ((size_t)mac * 6 + type) * 10, [&](int v, int k) { return xv[v][k]; },
+      [&](int c, int a) { return c * 10 + a == j ? 1.0 : 0.0; },
+      [&](int v, double& ev, double&, double&) { ev = eta[g1[v]]; });
+  el.template qp<0>(G);
+  el.template qp<1>(G);
+  el.template qp<2>(G);
+  el.template qp<3>(G);
+  double* col = emat + (size_t)e * 900 + (size_t)j * 30;
+  float* colf = ematf + (size_t)e * 900 + (size_t)j * 30;
+  el.store(
+      [&](int c, int a, double v) {
+        col[c * 10 + a] = v;
+        colf[c * 10 + a] = (float)v;
+      },
+      [](int, double) {});
+}
+
+__device__ __forceinline__ void node_project(int act, const double* __restrict__ nrm, double v[3]) {
+  if (act == ACT_DIR) {
+    v[0] = v[1] = v[2] = 0.0;
+  } else if (act == ACT_FS) {
+    const double dn = v[0] * nrm[0] + v[1] * nrm[1] + v[2] * nrm[2];
+    v[0] -= dn * nrm[0];
+    v[1] -= dn * nrm[1];
+    v[2] -= dn * nrm[2];
+  }
+}
+
+// Sums of up to three partial arrays in one pass (same order in every block).
+__device__ __forceinline__ void block_sum3(const double* a, const double* b, const double* c, int np,
+                                           double (*red)[256], double out[3]) {
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+    s0 += a[i];
+    if (b) s1 += b[i];
+    if (c) s2 += c[i];
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      red[2][threadIdx.x] += red[2][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  out[0] = red[0][0];
+  out[1] = red[1][0];
+  out[2] = red[2][0];
+  __syncthreads();
+}
+
+// x = 0; r = P b; z = P D^-1 r; partials of r.r and r.z as the "previous" parity
+__global__ __launch_bounds__(256) void k_ccg_init(CoarseDev cd, const double* __restrict__ b, double* __restrict__ x,
+                                                  double* __restrict__ r, double* __restrict__ z, double* part) {
+  __shared__ double red[2][256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nn = (size_t)cd.nn;
+  double a = 0, bb = 0;
+  if (i < cd.nn) {
+    double rv[3], zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rv[c] = b[i + c * nn];
+    node_project(cd.act[i], cd.nrm + 3 * (size_t)i, rv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) zv[c] = cd.dinv[i + c * nn] * rv[c];
+    node_project(cd.act[i], cd.nrm + 3 * (size_t)i, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[i + c * nn] = 0.0;
+      r[i + c * nn] = rv[c];
+      z[i + c * nn] = zv[c];
+      a += rv[c] * rv[c];
+      bb += rv[c] * zv[c];
+    }
+  }
+  block_partials(a, bb, cg_rr(part, 1), cg_rz(part, 1), red);
+}
+
+// The iteration kernels are short dependent chains of memory accesses, so
+// each issues every load that does not depend on the iteration's scalars
+// before it waits for any, and only then tests the convergence flag (a
+// finished solve stores nothing).
+
+// (A_e z_e)_j: the search direction's product follows by linearity,
+// A p = A z + beta A p_prev, so this kernel needs no scalar of the iteration.
+// Results go to the incidence slot of (e, local node) in node order, so that
+// the node pass reads each node's contributions contiguously.  CCG_ELEMS
+// elements of 30 threads per 256-thread workgroup.
+template <typename M>
+__global__ __launch_bounds__(256) void k_ccg_elem(CoarseDev cd, const M* __restrict__ emat, const double* sc,
+                                                  const double* __restrict__ z, double* __restrict__ Y) {
+  __shared__ double ze[CCG_ELEMS][30];
+  const int le = threadIdx.x / 30, j = threadIdx.x - 30 * le;
+  const long long e = (long long)blockIdx.x * CCG_ELEMS + le;
+  const bool on = le < CCG_ELEMS && e < cd.ne;
+  const double done = sc[CG_DONE];
+  double a[30];
+  double zv = 0.0;
+  size_t slot = 0;
+  if (on) {
+    const M* A = emat + (size_t)e * 900 + j;
+#pragma unroll
+    for (int k = 0; k < 30; ++k) a[k] = A[30 * k];
+    zv = z[(size_t)cd.enode[e * 10 + j % 10] + (size_t)(j / 10) * cd.nn];
+    slot = (size_t)cd.epos[e * 10 + j % 10] + (size_t)(j / 10) * ((size_t)cd.ne * 10);
+  }
+  if (done != 0.0) return;
+  if (on) ze[le][j] = zv;
+  __syncthreads();
+  if (on) {
+    double y = 0.0;
+#pragma unroll
+    for (int k = 0; k < 30; ++k) y = fma(a[k], ze[le][k], y);
+    Y[slot] = y;
+  }
+}
+
+// convergence test on |r|^2 of the previous iteration; beta = r.z / previous
+// r.z; p = z + beta p; q = P A p = P (sum of the incident element rows of A z)
+// + beta q; partials of p.q
+__global__ __launch_bounds__(256) void k_ccg_node1(CoarseDev cd, double* sc, double* part, int np,
+                                                   const double* __restrict__ z, double* __restrict__ p,
+                                                   double* __restrict__ q, const double* __restrict__ Y, int parity,
+                                                   int first) {
+  __shared__ double red[3][256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nn = (size_t)cd.nn;
+  const bool on = i < cd.nn;
+  const double done = sc[CG_DONE], thr = sc[CG_THR];
+  double zv[3] = {0, 0, 0}, po[3] = {0, 0, 0}, qo[3] = {0, 0, 0}, qv[3] = {0, 0, 0}, nr[3] = {0, 0, 0};
+  int act = ACT_NONE;
+  if (on) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t g = i + c * nn;
+      zv[c] = z[g];
+      po[c] = p[g];
+      qo[c] = q[g];
+      nr[c] = cd.nrm[3 * (size_t)i + c];
+    }
+    act = cd.act[i];
+    const int k0 = cd.iptr[i], k1 = cd.iptr[i + 1];
+    const size_t ninc = (size_t)cd.ne * 10;
+    for (int kb = k0; kb < k1; kb += 8) {
+      // branch-free batch: every load of the batch is in flight at once
+      // (slots past the node's list read slot k0 and are weighted 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = kb + u < k1 ? kb + u : k0;
+        const double w = kb + u < k1 ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) qv[c] = fma(w, Y[k + c * ninc], qv[c]);
+      }
+    }
+  }
+  double sums[3] = {0, 0, 0};   // |r|^2, r.z, previous r.z
+  if (!first) block_sum3(cg_rr(part, parity ^ 1), cg_rz(part, parity ^ 1), cg_rz(part, parity), np, red, sums);
+  if (done != 0.0) return;
+  if (!first && sums[0] <= thr) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[CG_DONE] = 1.0;
+    return;
+  }
+  const double beta = first ? 0.0 : sums[1] / sums[2];
+  double s = 0;
+  if (on) {
+    node_project(act, nr, qv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t g = i + c * nn;
+      const double pv = first ? zv[c] : fma(beta, po[c], zv[c]);
+      const double qc = first ? qv[c] : fma(beta, qo[c], qv[c]);
+      p[g] = pv;
+      q[g] = qc;
+      s += pv * qc;
+    }
+  }
+  red[0][threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0][0];
+}
+
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = P D^-1 r; partials of
+// r.r and r.z of this parity; iteration count
+__global__ __launch_bounds__(256) void k_ccg_node2(CoarseDev cd, double* sc, double* part, int np,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z, int parity) {
+  __shared__ double red[3][256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nn = (size_t)cd.nn;
+  const bool on = i < cd.nn;
+  const double done = sc[CG_DONE];
+  double pv[3] = {0, 0, 0}, qv[3] = {0, 0, 0}, xv[3] = {0, 0, 0}, rv[3] = {0, 0, 0}, dv[3] = {0, 0, 0},
+         nr[3] = {0, 0, 0};
+  int act = ACT_NONE;
+  if (on) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t g = i + c * nn;
+      pv[c] = p[g];
+      qv[c] = q[g];
+      xv[c] = x[g];
+      rv[c] = r[g];
+      dv[c] = cd.dinv[g];
+      nr[c] = cd.nrm[3 * (size_t)i + c];
+    }
+    act = cd.act[i];
+  }
+  double sums[3];   // p.q, previous r.z
+  block_sum3(part, cg_rz(part, parity ^ 1), nullptr, np, red, sums);
+  if (done != 0.0) return;
+  const double alpha = sums[1] / sums[0];
+  double a = 0, b = 0;
+  if (on) {
+    double zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xv[c] += alpha * pv[c];
+      rv[c] -= alpha * qv[c];
+      zv[c] = dv[c] * rv[c];
+    }
+    node_project(act, nr, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t g = i + c * nn;
+      x[g] = xv[c];
+      r[g] = rv[c];
+      z[g] = zv[c];
+      a += rv[c] * rv[c];
+      b += rv[c] * zv[c];
+    }
+  }
+  block_partials(a, b, cg_rr(part, parity), cg_rz(part, parity), reinterpret_cast<double (*)[256]>(red));
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[CG_IT] += 1.0;
+}
+
+void launch_elem_matrix(const LevelDev& L, const double* eta, double* emat, float* ematf, hipStream_t s) {
+  const long long tot = (long long)L.n * L.n * L.n * L.nmacro * 30;
+  dim3 grid((unsigned)((tot + 255) / 256));
+  if (L.blend) hipLaunchKernelGGL(k_elem_matrix<true>, grid, dim3(256), 0, s, L, eta, emat, ematf);
+  else hipLaunchKernelGGL(k_elem_matrix<false>, grid, dim3(256), 0, s, L, eta, emat, ematf);
+}
+void ccg_init(const CoarseDev& cd, const double* b, double* x, double* r, double* z, double tol, double* part,
+              double* sc, hipStream_t s) {
+  const int nb = (cd.nn + 255) / 256;
+  hipLaunchKernelGGL(k_ccg_init, dim3(nb), dim3(256), 0, s, cd, b, x, r, z, part);
+  hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, part, nb, tol * tol, sc);
+}
+void ccg_iter(const CoarseDev& cd, bool fp32, double* x, double* r, double* z, double* p, double* q, double* Y,
+              double* part, double* sc, int it, hipStream_t s) {
+  const int nb = (cd.nn + 255) / 256, parity = it & 1, first = it == 0;
+  const dim3 ge((cd.ne + CCG_ELEMS - 1) / CCG_ELEMS);
+  if (fp32) hipLaunchKernelGGL(k_ccg_elem<float>, ge, dim3(256), 0, s, cd, cd.ematf, sc, z, Y);
+  else hipLaunchKernelGGL(k_ccg_elem<double>, ge, dim3(256), 0, s, cd, cd.emat, sc, z, Y);
+  hipLaunchKernelGGL(k_ccg_node1, dim3(nb), dim3(256), 0, s, cd, sc, part, nb, z, p, q, Y, parity, first);
+  hipLaunchKernelGGL(k_ccg_node2, dim3(nb), dim3(256), 0, s, cd, sc, part, nb, p, q, x, r, z, parity);
 }
 
 static inline int redgrid(long long n) {

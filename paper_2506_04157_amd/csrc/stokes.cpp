@@ -133,6 +133,14 @@ struct LevelData {
   template <class R> const R* dinvp() const;
   template <class R> R* sl2();
   template <class R> R* sl1();
+  // coarsest level: element matrices and node data of its CG
+  bool ccg = false;
+  CoarseDev cd{};
+  DBuf<uint32_t> c_enode;
+  DBuf<double> c_emat, c_nrm;
+  DBuf<float> c_ematf;
+  DBuf<int> c_iptr, c_pos;
+  DBuf<uint8_t> c_act;
 };
 template <> Pool<double>& LevelData::pool<double>() { return p64; }
 template <> Pool<float>& LevelData::pool<float>() { return p32; }
@@ -170,7 +178,7 @@ template <> float* LevelData::msl<float>() {
 
 // indices into the per-level velocity work pools
 enum { W_B = 0, W_X, W_R, W_D, W_T, W_CG_R, W_CG_Z, W_CG_P, W_CG_Q, W_U0, W_U1, W_U2, W_U3, W_U4, W_U5,
-       W_F0, W_F1, W_F2, W_F3, W_C_R, W_C_Z, W_C_P, W_C_Q, W_C_B, W_C_X, W_PC0, W_PC1 };
+       W_F0, W_F1, W_F2, W_F3, W_C_R, W_C_Z, W_C_P, W_C_Q, W_C_B, W_C_X, W_PC0, W_PC1, W_C_Y };
 // pressure-size pools
 enum { Q_0 = 0, Q_1, Q_2, Q_3, Q_4, Q_5, Q_6, Q_7, Q_8, Q_9, Q_ONES, Q_MD, Q_U0, Q_U1, Q_F0, Q_F1, Q_F2, Q_F3 };
 
@@ -189,6 +197,8 @@ struct stk_ctx {
   DBuf<double> cgbuf;      // device CG scalars
   DBuf<double> cgpart;     // device CG partial sums
   double* hpin = nullptr;
+  double* hcg = nullptr;         // two pinned copies of the device CG scalars
+  hipEvent_t cgev[2] = {nullptr, nullptr};
   bool ready = false;
   bool has_rho = false;
   DBuf<double> lnrho;
@@ -329,10 +339,36 @@ void chebyshev(Ctx& c, int l, const R* b, R* x, int steps, int deg, bool xzero) 
 }
 
 // ---- coarse grid: Jacobi-preconditioned CG in FP64 (Sec. 5.2.2, tol_coarse) ---
+// Drives a device-resident CG: step(it) enqueues iteration it; chunks of
+// `chunk` iterations are enqueued one ahead of the host's look at the device
+// scalars (convergence flag, iteration count) of the chunk before, so the
+// GPU never waits for the host.  Kernels of a finished solve return at once,
+// so the chunk in flight when the flag is seen costs only its launches.
+// Returns the device's iteration count.
+template <class Step>
+int run_chunks(Ctx& c, const double* sc, int chunk, int maxit, Step step) {
+  int it = 0, k = 0;
+  for (;;) {
+    for (int i = 0; i < chunk && it < maxit; ++i, ++it) step(it);
+    const int cur = k & 1;
+    HIPCHK(hipMemcpyAsync(c.hcg + cur * CGS_N, sc, CGS_N * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipEventRecord(c.cgev[cur], c.s));
+    ++k;
+    if (k >= 2) {
+      const double* h = c.hcg + (cur ^ 1) * CGS_N;
+      HIPCHK(hipEventSynchronize(c.cgev[cur ^ 1]));
+      if (h[CGS_DONE] != 0.0) return (int)h[CGS_IT];
+    }
+    if (it >= maxit) break;
+  }
+  HIPCHK(hipEventSynchronize(c.cgev[(k - 1) & 1]));
+  return (int)c.hcg[((k - 1) & 1) * CGS_N + CGS_IT];
+}
+
 // Jacobi-preconditioned CG with device-resident scalars (no host round trip
-// per iteration); the host looks at the convergence flag every CG_CHUNK
-// iterations.  apply(p, q) computes q = A p; proj(v) projects in place (it
-// must be an orthogonal projection commuting with the residual's range).
+// per iteration; see run_chunks).  apply(p, q) computes q = A p; proj(v)
+// projects in place (it must be an orthogonal projection commuting with the
+// residual's range).
 template <class R, class Apply, class Proj>
 int dev_pcg(Ctx& c, long long N, Apply apply, Proj proj, const R* dinv, const R* b, R* x, R* r, R* z, R* p, R* q,
             double tol, int maxit, int chunk) {
@@ -344,24 +380,19 @@ int dev_pcg(Ctx& c, long long N, Apply apply, Proj proj, const R* dinv, const R*
   cg_init<R>(r, dinv, z, N, tol, part, sc, c.s);
   proj(z);
   vcopy<R>(z, p, N, c.s);
-  int it = 0;
-  for (;;) {
-    for (int k = 0; k < chunk; ++k) {
-      const int parity = (it + k) & 1;
-      apply(p, q);
-      cg_dot<R>(p, q, N, part, sc, c.s);
-      cg_update<R>(p, q, dinv, x, r, z, N, part, sc, parity, c.s);
-      proj(z);
-      cg_pupdate<R>(z, p, N, part, sc, parity, c.s);
-    }
-    it += chunk;
-    HIPCHK(hipMemcpyAsync(c.hpin, sc, CGS_N * sizeof(double), hipMemcpyDeviceToHost, c.s));
-    HIPCHK(hipStreamSynchronize(c.s));
-    if (c.hpin[CGS_DONE] != 0.0 || it >= maxit) return (int)c.hpin[CGS_IT];
-  }
+  return run_chunks(c, sc, chunk, maxit, [&](int it) {
+    const int parity = it & 1;
+    apply(p, q);
+    cg_dot<R>(p, q, N, part, sc, c.s);
+    cg_update<R>(p, q, dinv, x, r, z, N, part, sc, parity, c.s);
+    proj(z);
+    cg_pupdate<R>(z, p, N, part, sc, parity, c.s);
+  });
 }
 
-void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit) {
+// fp32: the FP32 preconditioner's coarse solve (element matrices rounded to
+// FP32; vectors, scalars and accumulation stay FP64)
+void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit, bool fp32) {
   const int l = c.lmin();
   LevelData& L = c.at(l);
   const long long N = 3 * L.h.n2;
@@ -370,6 +401,16 @@ void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit) {
   double* z = P.get(W_C_Z, N, c.s);
   double* p = P.get(W_C_P, N, c.s);
   double* q = P.get(W_C_Q, N, c.s);
+  if (L.ccg) {
+    double* Y = P.get(W_C_Y, (size_t)L.cd.ne * 30, c.s);
+    double* part = c.cgpart.p;
+    double* sc = c.cgbuf.p;
+    ccg_init(L.cd, b, x, r, z, tol, part, sc, c.s);
+    const int its = run_chunks(c, sc, 4, maxit,
+                               [&](int it) { ccg_iter(L.cd, fp32, x, r, z, p, q, Y, part, sc, it, c.s); });
+    if (c.rep) c.rep->coarse_its += its;
+    return;
+  }
   const int its = dev_pcg<double>(
       c, N, [&](const double* pp, double* qq) { applyA<double>(c, l, pp, qq, BCM_IN | BCM_OUT); },
       [&](double* v) { project<double>(c, l, v); }, L.dinv.p, b, x, r, z, p, q, tol, maxit, 8);
@@ -382,12 +423,12 @@ void coarse_solve(Ctx& c, const R* b, R* x) {
   LevelData& L = c.at(l);
   const long long N = 3 * L.h.n2;
   if (std::is_same<R, double>::value) {
-    coarse_cg64(c, (const double*)b, (double*)x, c.par.tol_coarse, c.par.max_inner * 10);
+    coarse_cg64(c, (const double*)b, (double*)x, c.par.tol_coarse, c.par.max_inner * 10, false);
   } else {
     double* b64 = L.pool<double>().get(W_C_B, N, c.s);
     double* x64 = L.pool<double>().get(W_C_X, N, c.s);
     vconvert<float, double>((const float*)b, b64, N, c.s);
-    coarse_cg64(c, b64, x64, c.par.tol_coarse, c.par.max_inner * 10);
+    coarse_cg64(c, b64, x64, c.par.tol_coarse, c.par.max_inner * 10, true);
     vconvert<double, float>(x64, (float*)x, N, c.s);
   }
 }
@@ -759,6 +800,60 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
 }
 
 // ---- setup --------------------------------------------------------------------------
+// Coarsest level: the element node table, the node-to-element incidence slots and
+// the per-node boundary data of the element-matrix CG.  The element order is
+// that of the level's element list (macro-major), as in the element kernels.
+void setup_coarse(Ctx& c, LevelData& L, const std::vector<int>& ea) {
+  const Level& h = L.h;
+  const int n = h.n, m2 = 2 * n, nm = c.mm.nm();
+  const long long ne = (long long)ea.size() * nm;
+  const long long nn = h.n2;
+  if (nn > 256LL * DOT_BLOCKS || ne * 900 * 8 > (4LL << 30)) return;   // stays on the element-kernel CG
+  std::vector<uint32_t> en((size_t)ne * 10);
+  for (int mac = 0; mac < nm; ++mac)
+    for (size_t k = 0; k < ea.size(); ++k) {
+      const int pk = ea[k];
+      const int t = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
+      int P[10][3];
+      for (int v = 0; v < 4; ++v)
+        for (int d = 0; d < 3; ++d) P[v][d] = 2 * ((d == 0 ? px : d == 1 ? py : pz) + TYPE_OFF[t][v][d]);
+      for (int e = 0; e < 6; ++e)
+        for (int d = 0; d < 3; ++d) P[4 + e][d] = (P[EDGE_V[e][0]][d] + P[EDGE_V[e][1]][d]) / 2;
+      uint32_t* out = en.data() + ((size_t)mac * ea.size() + k) * 10;
+      for (int a = 0; a < 10; ++a)
+        out[a] = h.l2g2[(size_t)mac * h.nloc2 + lattice_loc(P[a][0], P[a][1], P[a][2], m2)];
+    }
+  std::vector<int> ptr(nn + 1, 0), pos((size_t)ne * 10);
+  for (size_t i = 0; i < en.size(); ++i) ptr[en[i] + 1]++;
+  for (long long i = 0; i < nn; ++i) ptr[i + 1] += ptr[i];
+  {
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t i = 0; i < en.size(); ++i) pos[i] = fill[en[i]]++;
+  }
+  std::vector<uint8_t> act(nn, ACT_NONE);
+  std::vector<double> nrm(3 * nn, 0.0);
+  for (size_t i = 0; i < h.bnode.size(); ++i) {
+    const int bc = h.bkind[i] == 1 ? c.desc.bc_inner : c.desc.bc_outer;
+    const uint32_t g = h.bnode[i];
+    if (bc == STK_BC_DIRICHLET) {
+      act[g] = ACT_DIR;
+    } else if (bc == STK_BC_FREESLIP) {
+      act[g] = ACT_FS;
+      for (int k = 0; k < 3; ++k) nrm[3 * (size_t)g + k] = h.bnormal[3 * i + k];
+    }
+  }
+  L.c_enode.upload(en);
+  L.c_iptr.upload(ptr);
+  L.c_pos.upload(pos);
+  L.c_act.upload(act);
+  L.c_nrm.upload(nrm);
+  L.c_emat.alloc((size_t)ne * 900);
+  L.c_ematf.alloc((size_t)ne * 900);
+  L.cd = CoarseDev{(int)ne, (int)nn, L.c_enode.p, L.c_emat.p, L.c_ematf.p, L.c_iptr.p, L.c_pos.p, L.c_act.p,
+                   L.c_nrm.p, nullptr};
+  L.ccg = true;
+}
+
 void upload_level(Ctx& c, int l) {
   LevelData& L = c.at(l);
   const Level& h = L.h;
@@ -803,6 +898,7 @@ void upload_level(Ctx& c, int l) {
     L.eall.upload(ea);
     d.eall = L.eall.p;
     d.elemwise = h.n <= 2;
+    if (l == c.lmin()) setup_coarse(c, L, ea);
   }
   L.sw_strip.upload(L.sw.strip);
   L.sw_plist2.upload(L.sw.plist2);
@@ -1006,6 +1102,13 @@ void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const s
     vinvert<double>(L.dinv.p, L.dinv.p, N, c.s);
     vconvert<double, float>(L.dinv.p, L.dinvf.p, N, c.s);
   }
+  {
+    LevelData& C = c.at(c.lmin());
+    if (C.ccg) {
+      C.cd.dinv = C.dinv.p;
+      launch_elem_matrix(C.d, C.eta.p, C.c_emat.p, C.c_ematf.p, c.s);
+    }
+  }
   for (int l = c.lmin() + 1; l <= Lf; ++l) {
     LevelData& L = c.at(l);
     if (!L.bounds_set) {
@@ -1121,6 +1224,8 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
     c->cgbuf.alloc(16);
     c->cgpart.alloc(5 * DOT_BLOCKS);
     HIPCHK(hipHostMalloc((void**)&c->hpin, 64, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hcg, 2 * CGS_N * sizeof(double), hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreateWithFlags(&c->cgev[k], hipEventDisableTiming));
     HIPCHK(hipDeviceSynchronize());
     *out = c.release();
   });
@@ -1131,6 +1236,9 @@ int stk_destroy(stk_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->s);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+    if (ctx->hcg) (void)hipHostFree(ctx->hcg);
+    for (int k = 0; k < 2; ++k)
+      if (ctx->cgev[k]) (void)hipEventDestroy(ctx->cgev[k]);
     delete ctx;
   });
 }

@@ -183,6 +183,43 @@ def test_solve_shell_freeslip_compressible(precision):
     assert abs(pg.mean()) < 1e-12 * np.abs(pg).max()
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_solve_shell_plate_velocity_and_freeslip_cmb(precision):
+    """The boundary arrangement of the paper's model (Sec. 2): prescribed
+    tangential (plate) velocity at the surface r = 1, free slip at the
+    core-mantle boundary r = 0.55; compressible, viscosity contrast 1e4."""
+    print(f"\n[solve shell plates prec {precision}]", flush=True)
+    P = Pair("shell", 2, min_level=0, n_tan=1, n_rad=1, bc_inner=2, bc_outer=1)
+    m = P.meshes[2]
+    field = inputs.SHField(2)
+    eta = inputs.viscosity_contrast(field.temperature(m.X1), 1e4)
+    lnrho = inputs.ln_density(m.X1)
+    f = rhs_buoyancy(m, field.temperature(m.X2))
+    uS = inputs.plate_velocity(13, m.X2)
+    assert np.abs(np.einsum("ij,ij->i", uS, m.X2)).max() < 1e-13   # tangential
+    uD = np.where(m.flag2 == 2, uS.T, 0.0).ravel()   # the data lives on the surface nodes
+    (uo, po, _), (A, B, Bb, Q) = _oracle_solution(P, eta, lnrho, f, uD)
+    params = default_params(tol_rel=1e-10, precision=precision)
+    P.ctx.set_fields(P.p_to_lib(eta), P.p_to_lib(lnrho), params=params)
+    u, p, rep = P.ctx.solve(P.u_to_lib(f), u_dirichlet=P.u_to_lib(uD), params=params)
+    print(rep["iterations"], rep["rel_residual"], rep["seconds"])
+    ug, pg = P.u_to_or(u), P.p_to_or(p)
+    assert rep["rel_residual"] <= 1e-10
+    Pm = Q @ Q.T
+    ru = Pm @ (f - A @ ug - B.T @ pg)
+    rp = Bb @ ug
+    rp = rp - rp.mean()
+    scale = np.hypot(np.linalg.norm(Pm @ (f - A @ uD)), np.linalg.norm(Bb @ uD))
+    assert np.hypot(np.linalg.norm(ru), np.linalg.norm(rp)) <= 2e-10 * scale
+    assert relerr(ug, uo) < 1e-5 and relerr(pg, po) < 1e-5
+    # surface nodes carry the plate velocity; core-mantle boundary nodes have u.n = 0
+    U = ug.reshape(3, -1).T
+    surf, cmb = m.flag2 == 2, m.flag2 == 1
+    assert np.abs(U[surf] - uS[surf]).max() <= 1e-14 * np.abs(uS).max()
+    nrm = m.X2[cmb] / np.linalg.norm(m.X2[cmb], axis=1)[:, None]
+    assert np.abs(np.einsum("ij,ij->i", U[cmb], nrm)).max() <= 1e-12 * np.abs(U).max()
+
+
 def test_adjoint_solve_and_gradient():
     print("\n[adjoint]", flush=True)
     P = Pair("shell", 2, min_level=0)
