@@ -135,3 +135,13 @@ def plate_velocity(seed, xyz, n_plates=6, scale=0.5):
     unit = xyz / np.where(r > 0, r, 1.0)[:, None]
     plate = np.argmax(unit @ centres.T, axis=1)
     return scale * np.cross(poles[plate], xyz)
+
+
+def base_viscosity_profile(n=65, r_in=R_IN, r_out=R_OUT):
+    """Synthetic radial base viscosity eta_base on a uniform grid of n radii:
+    log-linear through a stiff lower mantle, a weak asthenosphere and a stiff
+    lithosphere.  Stands in for the profile the paper shows only as a figure."""
+    r = np.linspace(r_in, r_out, n)
+    knots = np.array([r_in, 0.85, 0.88, 0.95, 0.97, r_out])
+    log10 = np.array([1.5, 1.0, -1.0, -1.0, 2.0, 2.0])
+    return 10.0 ** np.interp(r, knots, log10)

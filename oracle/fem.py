@@ -10,7 +10,9 @@ Definitions (Sec. 5.1, "Linear algebraic formulation"; stress tensor of Sec. 2):
 * M_{1/eta, ij} = int psi_i psi_j / eta dx      (Sec. 5.2.3, Schur approximation)
 * f_i = int T r_hat . phi_i dx                  (buoyancy with unit scaling)
 
-eta, ln rho are P1 interpolants of nodal values, T is a P2 interpolant.
+eta, ln rho are P1 interpolants of nodal values, T is a P2 interpolant; on
+the coarse levels up to l_eta the viscosity is instead evaluated at the
+quadrature points from T (Sec. 5.2.2, ``assemble_A_qp``).
 Integrals on a blended element K = B(F(K^)) are pulled back to the reference
 tetrahedron with the Jacobian J = J_B(F(xi)) J_F and the weight
 |det J_B| |det J_F| (Sec. 4.1).  Velocity DoFs are stored component-major:
@@ -146,6 +148,44 @@ def assemble_A(mesh, eta1, rule=None):
         W, G2, G1, X, N2, N1 = geometry(mesh, sel, rule)
         eta_q = np.einsum("qk,ek->eq", N1, eta1[mesh.e1[sel]])
         Ae = element_A(W, G2, eta_q)
+        d = _vec_dofs(mesh, sel)
+        rows.append(np.repeat(d, 30, axis=1).ravel())
+        cols.append(np.tile(d, (1, 30)).ravel())
+        vals.append(Ae.ravel())
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n)).tocsr()
+
+
+def viscosity_model(x, T, eta_base, E_A, V_A, r_in, r_out):
+    """Frank-Kamenetskii viscosity of the geodynamic model (Sec. 6, eq.
+    ViscosityDef): eta(x, T) = eta_base(|x|) exp(-E_A T + V_A (r_out - |x|)).
+
+    The radial base profile is known only from a figure; the reading here
+    takes it as ``len(eta_base)`` samples on a uniform grid of [r_in, r_out],
+    linear in between and constant outside."""
+    r = np.linalg.norm(np.asarray(x), axis=-1)
+    grid = np.linspace(r_in, r_out, len(eta_base))
+    return np.interp(r, grid, eta_base) * np.exp(-E_A * np.asarray(T) + V_A * (r_out - r))
+
+
+def vertex_p2_nodes(mesh):
+    """P2 node of every P1 vertex (the element's first four P2 nodes are its
+    vertices, in the order of its P1 nodes)."""
+    v2 = np.empty(mesh.n1, dtype=np.int64)
+    v2[mesh.e1.ravel()] = mesh.e2[:, :4].ravel()
+    return v2
+
+
+def assemble_A_qp(mesh, eta_fn, T2, rule=None):
+    """A with the viscosity evaluated at the quadrature points from a P2
+    temperature (Sec. 5.2.2, levels up to l_eta): eta_q = eta_fn(x_q, T_h(x_q)),
+    x_q the physical quadrature point and T_h the P2 interpolant of T2."""
+    n = 3 * mesh.n2
+    rows, cols, vals = [], [], []
+    for sel in _chunks(mesh.ne):
+        W, G2, G1, X, N2, N1 = geometry(mesh, sel, rule)
+        Tq = np.einsum("qa,ea->eq", N2, T2[mesh.e2[sel]])
+        Ae = element_A(W, G2, eta_fn(X, Tq))
         d = _vec_dofs(mesh, sel)
         rows.append(np.repeat(d, 30, axis=1).ravel())
         cols.append(np.tile(d, (1, 30)).ravel())

@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 import sympy as sy
 
-from oracle.fem import (assemble_A, assemble_B, assemble_M_inv_eta, element_A, geometry,
-                        rhs_buoyancy, strain_and_div)
+from oracle.fem import (assemble_A, assemble_A_qp, assemble_B, assemble_M_inv_eta, element_A, geometry,
+                        rhs_buoyancy, strain_and_div, vertex_p2_nodes, viscosity_model)
 from oracle.mesh import RefinedMesh, cube_macros, shell_macros
 from oracle.quadrature import rule_q4, rule_stroud
 
@@ -190,3 +190,42 @@ def test_mass_and_buoyancy():
         f = rhs_buoyancy(ms, np.ones(ms.n2))
         errs.append(abs(f @ ms.X2.T.ravel() - exact))
     assert errs[2] < errs[1] < errs[0] and errs[1] / errs[2] > 3.5
+
+
+def test_quadrature_point_viscosity_assembly():
+    """A with eta evaluated at the quadrature points (Sec. 5.2.2): on affine
+    (cube) elements an affine eta(x) is its own P1 interpolant, so the
+    assembly equals the P1-eta one; a quadratic T is its own P2 interpolant,
+    so eta = T_h(x_q) equals eta = T(x_q); on the blended shell a constant
+    eta reproduces the constant-eta operator."""
+    m = RefinedMesh(cube_macros(), 2)
+    k, c0 = np.array([0.3, -0.2, 0.5]), 1.7
+    A1 = assemble_A(m, c0 + m.x1 @ k)
+    Aq = assemble_A_qp(m, lambda X, Tq: c0 + X @ k, np.zeros(m.n2))
+    assert abs(Aq - A1).max() <= 1e-13 * abs(A1).max()
+    quad = lambda X: 2.0 + X[..., 0] * X[..., 1] - 0.5 * X[..., 2] ** 2 + X[..., 1]
+    AT = assemble_A_qp(m, lambda X, Tq: Tq, quad(m.x2))
+    AX = assemble_A_qp(m, lambda X, Tq: quad(X), np.zeros(m.n2))
+    assert abs(AT - AX).max() <= 1e-13 * abs(AX).max()
+    # the dropped-interpolation mistake is visible: P1 interpolation of the
+    # quadratic differs from its quadrature-point values
+    assert abs(assemble_A(m, quad(m.x1)) - AX).max() > 1e-3 * abs(AX).max()
+    ms = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 1)
+    Ac = assemble_A_qp(ms, lambda X, Tq: np.full(Tq.shape, 3.0), np.zeros(ms.n2))
+    assert abs(Ac - assemble_A(ms, np.full(ms.n1, 3.0))).max() <= 1e-13 * abs(Ac).max()
+
+
+def test_viscosity_model_and_vertex_nodes():
+    """eq. ViscosityDef: eta_base interpolated linearly on its radial grid,
+    exp(-E_A T) in temperature, exp(V_A (r_out - r)) in depth; P1 vertices
+    map onto P2 nodes at the same place."""
+    base = np.array([1.0, 3.0, 2.0])
+    x = np.array([[0.55, 0.0, 0.0], [0.0, 0.6625, 0.0], [0.0, 0.0, 1.0], [0.3, 0.4, 0.0]])
+    T = np.array([0.0, 0.5, 1.0, 0.2])
+    eta = viscosity_model(x, T, base, 4.61, 2.996, 0.55, 1.0)
+    b = np.array([1.0, 2.0, 2.0, 1.0])       # r = 0.55, 0.6625 (halfway to 0.775), 1, 0.5 (clamped)
+    r = np.array([0.55, 0.6625, 1.0, 0.5])
+    assert np.allclose(eta, b * np.exp(-4.61 * T + 2.996 * (1.0 - r)), rtol=1e-15)
+    ms = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 2)
+    v2 = vertex_p2_nodes(ms)
+    assert np.abs(ms.X2[v2] - ms.X1).max() < 1e-15
