@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the A-apply timings (for counter collection)")
+    ap.add_argument("--l-eta-study", action="store_true",
+                    help="only the coarse-viscosity study: A-block CG iterations and time of 10 FGMRES "
+                         "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not "
@@ -265,6 +268,28 @@ def main():
         del a, b
         result["a_apply"] = a_apply()
         print(json.dumps(result["a_apply"]), flush=True)
+        return
+
+    if args.l_eta_study:
+        # Fig. AIterations setting: the first 10 FGMRES iterations of a solve,
+        # A-block CG iterations and their time, per choice of l_eta (-1: P1
+        # viscosity on every level)
+        base = inputs.base_viscosity_profile()
+        f = None
+        study = {}
+        for l_eta in (-1, 0, 1):
+            prm = default_params(precision=32, tol_rel=1e-12, max_outer=10)
+            sc.set_temperature_viscosity(T2, base, l_eta=l_eta, lnrho=lnrho, params=prm)
+            if f is None:
+                f = sc.rhs_buoyancy(T2)
+            u, p, rep = sc.solve(f, params=prm, allow_noconv=True)
+            torch.cuda.synchronize()
+            study[str(l_eta)] = {k: rep[k] for k in ("iterations", "rel_residual", "a_solves", "a_cg_its",
+                                                    "vcycles", "coarse_its", "seconds")}
+            log(f"l_eta {l_eta}: {rep['iterations']} FGMRES its, rel res {rep['rel_residual']:.2e}, "
+                f"A-block CG its {rep['a_cg_its']}, {rep['seconds']:.1f}s")
+        print(json.dumps({"l_eta_study": study, "E_A": 4.610, "V_A": 2.996,
+                          "eta_base": "inputs.base_viscosity_profile()", "level": args.level}), flush=True)
         return
 
     def step():

@@ -130,6 +130,21 @@ int stk_coords(const stk_ctx* ctx, int level, int which, double* xyz, uint8_t* f
 int stk_set_fields(stk_ctx* ctx, const double* eta_p1, const double* lnrho_p1, const stk_solver_params* params);
 /* Same with eta = exp(m) computed on the device from nodal log-viscosity m. */
 int stk_set_log_viscosity(stk_ctx* ctx, const double* m_p1, const double* lnrho_p1, const stk_solver_params* params);
+/* The viscosity of the geodynamic model (eq. ViscosityDef) from a P2
+ * temperature, with quadrature-point evaluation on the coarse levels
+ * (Sec. 5.2.2): eta(x, T) = eta_base(|x|) exp(-E_A T + V_A (r_out - |x|)),
+ * eta_base linear between n_base >= 2 samples on a uniform grid of
+ * [r_in, r_out] (host array, > 0) and constant outside.  Levels l_eta+1 ..
+ * level take the P1 interpolant with vertex values eta(x_V, T(x_V)) (the
+ * coarse ones by injection, as in stk_set_fields); levels min_level .. l_eta
+ * evaluate eta at the quadrature points from the P2 temperature injected to
+ * that level, and apply A with the element-parallel kernel (l_eta <
+ * min_level: none).  T_p2: device, n_p2 doubles of the finest level;
+ * lnrho_p1 and params as in stk_set_fields.  Errors: STK_EINVAL for a cube
+ * mesh, l_eta >= level, a bad eta_base, or non-finite T, E_A, V_A.  A later
+ * stk_set_fields / stk_set_log_viscosity returns every level to P1. */
+int stk_set_temperature_viscosity(stk_ctx* ctx, const double* T_p2, const double* lnrho_p1, const double* eta_base,
+                                  int n_base, double E_A, double V_A, int l_eta, const stk_solver_params* params);
 
 /* Buoyancy right-hand side f_i = int scale T_h r_hat . phi_i (Sec. 5.1,
  * eq. for f with g = -r_hat, unit material factors); T: n_p2 device doubles,

@@ -58,6 +58,7 @@ SIGNATURES = {
     "stk_coords": [_CTX, _I, _I, _P, _P],
     "stk_set_fields": [_CTX, _P, _P, ctypes.POINTER(SolverParams)],
     "stk_set_log_viscosity": [_CTX, _P, _P, ctypes.POINTER(SolverParams)],
+    "stk_set_temperature_viscosity": [_CTX, _P, _P, _P, _I, _D, _D, _I, ctypes.POINTER(SolverParams)],
     "stk_rhs_buoyancy": [_CTX, _P, _D, _P],
     "stk_apply_A": [_CTX, _I, _I, _P, _P, _I],
     "stk_apply_B": [_CTX, _I, _I, _P, _P, _I, _I],

@@ -100,6 +100,15 @@ class StokesContext:
         self.params = params or default_params()
         check(self.lib.stk_set_log_viscosity(self.h, _ptr(m), _ptr(lnrho), ctypes.byref(self.params)))
 
+    def set_temperature_viscosity(self, T, eta_base, E_A=4.610, V_A=2.996, l_eta=-1, lnrho=None, params=None):
+        """eta(x, T) of the geodynamic model from the P2 temperature T (device,
+        FP64); quadrature-point evaluation on levels min_level .. l_eta."""
+        self.params = params or default_params()
+        base = np.ascontiguousarray(eta_base, dtype=np.float64)
+        check(self.lib.stk_set_temperature_viscosity(
+            self.h, _ptr(T), _ptr(lnrho), base.ctypes.data_as(ctypes.c_void_p), len(base), float(E_A), float(V_A),
+            int(l_eta), ctypes.byref(self.params)))
+
     def rhs_buoyancy(self, T, scale=1.0, out=None):
         out = self.zeros_u() if out is None else out
         check(self.lib.stk_rhs_buoyancy(self.h, _ptr(T), float(scale), _ptr(out)))

@@ -62,6 +62,15 @@ struct StencilDev {
   GatherDev g;
 };
 
+// Viscosity model of the geodynamic setup (eq. ViscosityDef):
+// eta(x, T) = eta_base(r) exp(-EA T + VA (rout - r)), r = |x|, eta_base linear
+// between nbase samples on a uniform grid of [rin, rout], constant outside.
+struct ViscDev {
+  const double* base;
+  int nbase;
+  double EA, VA, rin, rout;
+};
+
 struct LevelDev {
   int n;                  // P1 lattice side 2^L (P2 side 2n)
   int nloc2, nloc1;       // lattice points per macro
@@ -84,6 +93,10 @@ struct LevelDev {
   StencilDev ms;          // P1 mass stencil
   const int4* xtab;       // grid-transfer table with this level as the coarse one (2 int4 per entry)
   const int* xoff;        // per tile: first entry
+  int qpv;                // 1: A takes eta at the quadrature points from T2 (element-parallel kernels only)
+  const double* T2;       // P2 temperature of this level (qpv)
+  const float* T2f;
+  ViscDev vm;
 };
 
 // Boundary node lists of a level (for vector projections).
@@ -172,6 +185,13 @@ void launch_restrict_diff(const LevelDev& Lc, const LevelDev& Lf, const R* bf, c
                           hipStream_t s);
 template <typename R>
 void launch_inject(const LevelDev& Lc, const LevelDev& Lf, const R* vf, R* vc, hipStream_t s);
+// P2 nodal values of the next coarser level (coarse node = fine node)
+template <typename R>
+void launch_inject_p2(const LevelDev& Lc, const LevelDev& Lf, const R* vf, R* vc, hipStream_t s);
+// P1 viscosity eta(x_V, T(x_V)) at the vertices of level L from its P2 temperature L.T2
+void launch_eta_vertices(const LevelDev& L, double* eta1, hipStream_t s);
+// diag(A) (no projection) summed from the element matrices' diagonals; d zeroed by the caller
+void launch_elem_diag(const LevelDev& L, const double* eta, double* d, hipStream_t s);
 template <typename R>
 void launch_project(const BcDev& bc, long long n2, R* v, hipStream_t s);
 

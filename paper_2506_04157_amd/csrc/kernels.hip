@@ -173,6 +173,55 @@ struct QGeo {
   __device__ __forceinline__ void JinvT(R v[3]) const { rowJinv(v); }
 };
 
+// ---- viscosity at the quadrature points (Sec. 5.2.2, levels up to l_eta) ----
+template <typename R> __device__ __forceinline__ const R* t2_of(const LevelDev& L);
+template <> __device__ __forceinline__ const double* t2_of<double>(const LevelDev& L) { return L.T2; }
+template <> __device__ __forceinline__ const float* t2_of<float>(const LevelDev& L) { return L.T2f; }
+
+// eq. ViscosityDef at radius r and temperature T
+template <typename R>
+__device__ __forceinline__ R visc_model(const ViscDev& vm, R r, R T) {
+  const int nb = vm.nbase;
+  R t = (r - R(vm.rin)) / R(vm.rout - vm.rin) * R(nb - 1);
+  t = t < R(0) ? R(0) : (t > R(nb - 1) ? R(nb - 1) : t);
+  int i = (int)t;
+  if (i > nb - 2) i = nb - 2;
+  const R w = t - R(i);
+  const R b = (R(1) - w) * R(vm.base[i]) + w * R(vm.base[i + 1]);
+  return b * exp(-R(vm.EA) * T + R(vm.VA) * (R(vm.rout) - r));
+}
+
+// Viscosity at the element's 4 quadrature points from its 10 P2 temperatures,
+// returned as the nodal values whose P1 interpolant takes exactly those values
+// at the points (the element kernels evaluate eta only there): with Q_q the
+// point values and S their sum, v_q = (Q_q - QB S) / (QA - QB), since the
+// interpolant at point q is QB sum(v) + (QA - QB) v_q and QA + 3 QB = 1.
+// xv: reference vertex positions; the radius of the blended point is s(x).
+template <typename R>
+__device__ __forceinline__ void qp_viscosity(const ViscDev& vm, const R* G, const R xv[4][3], const R T10[10],
+                                             R et[4]) {
+  R xs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xs[k] = xv[0][k] + xv[1][k] + xv[2][k] + xv[3][k];
+  const R tv = T10[0] + T10[1] + T10[2] + T10[3];
+  const R te = T10[4] + T10[5] + T10[6] + T10[7] + T10[8] + T10[9];
+  const R tq_e[4] = {T10[4] + T10[5] + T10[6], T10[4] + T10[7] + T10[8], T10[5] + T10[7] + T10[9],
+                     T10[6] + T10[8] + T10[9]};
+  R eq[4], se = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    R xq[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xq[k] = R(QB) * xs[k] + R(QA - QB) * xv[q][k];
+    const R r = G[12] * xq[0] + G[13] * xq[1] + G[14] * xq[2] + G[15];
+    const R Tq = R(NV_OTH) * tv + R(NV_OWN - NV_OTH) * T10[q] + R(NE_OTH) * te + R(NE_OWN - NE_OTH) * tq_e[q];
+    eq[q] = visc_model<R>(vm, r, Tq);
+    se += eq[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) et[q] = (eq[q] - R(QB) * se) * R(1.0 / (QA - QB));
+}
+
 // Element context: lattice positions and LDS indices of the 10 P2 / 4 P1 nodes.
 struct ElemIdx {
   int n2i[10], n1i[4];
@@ -765,6 +814,16 @@ __device__ __forceinline__ void elemwise_one(const LevelDev& L, long long gid, c
   for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
   R xv[4][3];
   if (BLEND) elem_vertices<R>(G, type, px, py, pz, n, xv);
+  // quadrature-point viscosity from the P2 temperature (blended shell only)
+  R etq[4] = {0, 0, 0, 0};
+  const bool qpv = BLEND && E::NE && L.qpv;
+  if (qpv) {
+    const R* T2 = t2_of<R>(L);
+    R T10[10];
+#pragma unroll
+    for (int a = 0; a < 10; ++a) T10[a] = T2[g2[a]];
+    qp_viscosity<R>(L.vm, G, xv, T10, etq);
+  }
   // velocity at the 10 nodes, projected once per node (macro-interior nodes need none)
   R uv[10][3];
   if (E::NU) {
@@ -781,7 +840,7 @@ __device__ __forceinline__ void elemwise_one(const LevelDev& L, long long gid, c
       tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10, [&](int v, int k) { return xv[v][k]; },
       [&](int c, int a) { return uv[a][c]; },
       [&](int v, R& ev, R& pv, R& rv) {
-        if (E::NE) ev = eta[g1[v]];
+        if (E::NE) ev = qpv ? etq[v] : eta[g1[v]];
         if (E::NP) pv = p[g1[v]];
         if (E::NR) rv = lnrho[g1[v]];
       });
@@ -1792,13 +1851,15 @@ __global__ __launch_bounds__(256) void k_cg_p(double* sc, const R* __restrict__ 
 // kernel of their own.
 
 // column j of A_e of every micro-tet e (one thread per (e, j)): the element
-// operator applied to the j-th unit vector, no boundary projection
-template <bool BLEND>
-__global__ __launch_bounds__(256) void k_elem_matrix(LevelDev L, const double* __restrict__ eta,
-                                                     double* __restrict__ emat, float* __restrict__ ematf) {
+// operator applied to the j-th unit vector, no boundary projection.  DIAG:
+// only the diagonal entry, summed into d at its global DoF.
+template <bool BLEND, bool DIAG>
+__global__ __launch_bounds__(256) void k_elem_cols(LevelDev L, const double* __restrict__ eta,
+                                                   double* __restrict__ emat, float* __restrict__ ematf,
+                                                   double* __restrict__ d) {
   using E = StokesElem<double, BLEND, F_A>;
   const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int n = L.n;
+  const int n = L.n, m2 = 2 * n;
   const int ne = n * n * n;
   if (gid >= (long long)ne * L.nmacro * 30) return;
   const long long e = gid / 30;
@@ -1807,30 +1868,105 @@ __global__ __launch_bounds__(256) void k_elem_matrix(LevelDev L, const double* _
   const int pk = L.eall[e - (long long)mac * ne];
   const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
   const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
   const double* G = L.geo + (size_t)mac * 16;
-  size_t g1[4];
+  size_t g1[4], g2[10];
+  int I2[10], J2[10], K2[10];
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
-    g1[v] = l1[lloc(px + c_toff[type][v][0], py + c_toff[type][v][1], pz + c_toff[type][v][2], n)];
+  for (int v = 0; v < 4; ++v) {
+    const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], K = pz + c_toff[type][v][2];
+    g1[v] = l1[lloc(I, J, K, n)];
+    I2[v] = 2 * I;
+    J2[v] = 2 * J;
+    K2[v] = 2 * K;
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    I2[4 + ed] = (I2[EV0(ed)] + I2[EV1(ed)]) >> 1;
+    J2[4 + ed] = (J2[EV0(ed)] + J2[EV1(ed)]) >> 1;
+    K2[4 + ed] = (K2[EV0(ed)] + K2[EV1(ed)]) >> 1;
+  }
+  const bool qpv = BLEND && L.qpv;
+  if (DIAG || qpv) {
+#pragma unroll
+    for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+  }
   double xv[4][3];
   if (BLEND) elem_vertices<double>(G, type, px, py, pz, n, xv);
+  double etq[4] = {0, 0, 0, 0};
+  if (qpv) {
+    double T10[10];
+#pragma unroll
+    for (int a = 0; a < 10; ++a) T10[a] = L.T2[g2[a]];
+    qp_viscosity<double>(L.vm, G, xv, T10, etq);
+  }
   E el;
   el.load(
       L.tinv + ((size_t)mac * 6 + type) * 10, [&](int v, int k) { return xv[v][k]; },
       [&](int c, int a) { return c * 10 + a == j ? 1.0 : 0.0; },
-      [&](int v, double& ev, double&, double&) { ev = eta[g1[v]]; });
+      [&](int v, double& ev, double&, double&) { ev = qpv ? etq[v] : eta[g1[v]]; });
   el.template qp<0>(G);
   el.template qp<1>(G);
   el.template qp<2>(G);
   el.template qp<3>(G);
-  double* col = emat + (size_t)e * 900 + (size_t)j * 30;
-  float* colf = ematf + (size_t)e * 900 + (size_t)j * 30;
-  el.store(
-      [&](int c, int a, double v) {
-        col[c * 10 + a] = v;
-        colf[c * 10 + a] = (float)v;
-      },
-      [](int, double) {});
+  if (DIAG) {
+    el.store(
+        [&](int c, int a, double v) {
+          if (c * 10 + a == j) gadd(d + g2[a] + (size_t)c * L.n2, v);
+        },
+        [](int, double) {});
+  } else {
+    double* col = emat + (size_t)e * 900 + (size_t)j * 30;
+    float* colf = ematf + (size_t)e * 900 + (size_t)j * 30;
+    el.store(
+        [&](int c, int a, double v) {
+          col[c * 10 + a] = v;
+          colf[c * 10 + a] = (float)v;
+        },
+        [](int, double) {});
+  }
+}
+
+// P2 nodal values of the next coarser level: coarse lattice point (I,J,K) is
+// fine point (2I,2J,2K) of the same macro
+template <typename R>
+__global__ void k_inject_p2(LevelDev Lc, LevelDev Lf, const R* __restrict__ vf, R* __restrict__ vc) {
+  const int mac = blockIdx.y;
+  const int m = 2 * Lc.n;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < Lc.nloc2; l += gridDim.x * blockDim.x) {
+    int K = 0;
+    while (tetc(m) - tetc(m - K - 1) <= l) ++K;
+    int r = l - (int)(tetc(m) - tetc(m - K));
+    const int s = m - K;
+    int J = 0;
+    while (r >= s - J + 1) { r -= s - J + 1; ++J; }
+    const int I = r;
+    const size_t gc = Lc.l2g2[(size_t)mac * Lc.nloc2 + l];
+    const size_t gf = Lf.l2g2[(size_t)mac * Lf.nloc2 + lloc(2 * I, 2 * J, 2 * K, 2 * m)];
+    vc[gc] = vf[gf];   // shared nodes get the same value from every macro
+  }
+}
+
+// eta(x_V, T(x_V)) at the P1 vertices of a blended level (vertex (I,J,K) is
+// P2 point (2I,2J,2K); its radius is s at the reference point)
+__global__ void k_eta_vertices(LevelDev L, double* __restrict__ eta1) {
+  const int mac = blockIdx.y;
+  const int n = L.n;
+  const double* G = L.geo + (size_t)mac * 16;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < L.nloc1; l += gridDim.x * blockDim.x) {
+    int K = 0;
+    while (tetc(n) - tetc(n - K - 1) <= l) ++K;
+    int r = l - (int)(tetc(n) - tetc(n - K));
+    const int s = n - K;
+    int J = 0;
+    while (r >= s - J + 1) { r -= s - J + 1; ++J; }
+    const int I = r;
+    double x[3];
+    lattice_x<double>(G, I, J, K, n, x);
+    const double rad = G[12] * x[0] + G[13] * x[1] + G[14] * x[2] + G[15];
+    const double T = L.T2[L.l2g2[(size_t)mac * L.nloc2 + lloc(2 * I, 2 * J, 2 * K, 2 * n)]];
+    eta1[L.l2g1[(size_t)mac * L.nloc1 + l]] = visc_model<double>(L.vm, rad, T);
+  }
 }
 
 __device__ __forceinline__ void node_project(int act, const double* __restrict__ nrm, double v[3]) {
@@ -2063,9 +2199,25 @@ __global__ __launch_bounds__(256) void k_ccg_node2(CoarseDev cd, double* sc, dou
 void launch_elem_matrix(const LevelDev& L, const double* eta, double* emat, float* ematf, hipStream_t s) {
   const long long tot = (long long)L.n * L.n * L.n * L.nmacro * 30;
   dim3 grid((unsigned)((tot + 255) / 256));
-  if (L.blend) hipLaunchKernelGGL(k_elem_matrix<true>, grid, dim3(256), 0, s, L, eta, emat, ematf);
-  else hipLaunchKernelGGL(k_elem_matrix<false>, grid, dim3(256), 0, s, L, eta, emat, ematf);
+  if (L.blend) hipLaunchKernelGGL((k_elem_cols<true, false>), grid, dim3(256), 0, s, L, eta, emat, ematf, nullptr);
+  else hipLaunchKernelGGL((k_elem_cols<false, false>), grid, dim3(256), 0, s, L, eta, emat, ematf, nullptr);
 }
+void launch_elem_diag(const LevelDev& L, const double* eta, double* d, hipStream_t s) {
+  const long long tot = (long long)L.n * L.n * L.n * L.nmacro * 30;
+  dim3 grid((unsigned)((tot + 255) / 256));
+  if (L.blend) hipLaunchKernelGGL((k_elem_cols<true, true>), grid, dim3(256), 0, s, L, eta, nullptr, nullptr, d);
+  else hipLaunchKernelGGL((k_elem_cols<false, true>), grid, dim3(256), 0, s, L, eta, nullptr, nullptr, d);
+}
+void launch_eta_vertices(const LevelDev& L, double* eta1, hipStream_t s) {
+  dim3 grid((unsigned)((L.nloc1 + 255) / 256), (unsigned)L.nmacro);
+  hipLaunchKernelGGL(k_eta_vertices, grid, dim3(256), 0, s, L, eta1);
+}
+template <typename R>
+void launch_inject_p2(const LevelDev& Lc, const LevelDev& Lf, const R* vf, R* vc, hipStream_t s) {
+  dim3 grid((unsigned)((Lc.nloc2 + 255) / 256), (unsigned)Lc.nmacro);
+  hipLaunchKernelGGL((k_inject_p2<R>), grid, dim3(256), 0, s, Lc, Lf, vf, vc);
+}
+template void launch_inject_p2<double>(const LevelDev&, const LevelDev&, const double*, double*, hipStream_t);
 void ccg_init(const CoarseDev& cd, const double* b, double* x, double* r, double* z, double tol, double* part,
               double* sc, hipStream_t s) {
   const int nb = (cd.nn + 255) / 256;

@@ -133,6 +133,9 @@ struct LevelData {
   template <class R> const R* dinvp() const;
   template <class R> R* sl2();
   template <class R> R* sl1();
+  // P2 temperature of the level (quadrature-point viscosity)
+  DBuf<double> T2;
+  DBuf<float> T2f;
   // coarsest level: element matrices and node data of its CG
   bool ccg = false;
   CoarseDev cd{};
@@ -203,6 +206,7 @@ struct stk_ctx {
   bool has_rho = false;
   DBuf<double> lnrho;
   DBuf<float> lnrhof;
+  DBuf<double> vbase;      // radial base viscosity samples (quadrature-point viscosity)
   stk_solver_params par{};
   stk_report* rep = nullptr;
   // FGMRES storage
@@ -1098,7 +1102,8 @@ void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const s
     L.dinv.alloc(N);
     L.dinvf.alloc(N);
     vfill<double>(L.dinv.p, 0.0, N, c.s);
-    launch_diag<double>(L.d, L.eta.p, L.dinv.p, c.s);
+    if (L.d.qpv) launch_elem_diag(L.d, L.eta.p, L.dinv.p, c.s);
+    else launch_diag<double>(L.d, L.eta.p, L.dinv.p, c.s);
     vinvert<double>(L.dinv.p, L.dinv.p, N, c.s);
     vconvert<double, float>(L.dinv.p, L.dinvf.p, N, c.s);
   }
@@ -1140,6 +1145,53 @@ void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const s
   HIPCHK(hipStreamSynchronize(c.s));
   HIPCHK(hipGetLastError());
   c.ready = true;
+}
+
+// Levels min_level .. l_eta take the quadrature-point viscosity and the
+// element-parallel kernel; the others the P1 viscosity and the plane sweep on
+// levels with n > 2.
+void configure_viscosity_levels(Ctx& c, int l_eta) {
+  for (int l = c.lmin(); l <= c.L(); ++l) {
+    LevelDev& d = c.at(l).d;
+    d.qpv = l <= l_eta ? 1 : 0;
+    d.elemwise = (c.at(l).h.n <= 2 || l <= l_eta) ? 1 : 0;
+  }
+}
+
+void set_temperature_viscosity_internal(Ctx& c, const double* T2, const double* lnrho, const double* base, int nbase,
+                                        double EA, double VA, int l_eta, const stk_solver_params* par) {
+  REQUIRE(c.desc.kind == STK_MESH_SHELL, "quadrature-point viscosity needs the blended shell");
+  REQUIRE(l_eta < c.L(), "l_eta must be below the finest level");
+  REQUIRE(nbase >= 2, "eta_base needs at least two samples");
+  for (int i = 0; i < nbase; ++i) REQUIRE(std::isfinite(base[i]) && base[i] > 0.0, "eta_base must be positive");
+  REQUIRE(std::isfinite(EA) && std::isfinite(VA), "E_A and V_A must be finite");
+  check_params(par);
+  const int Lf = c.L();
+  LevelData& F = c.at(Lf);
+  const long long n2 = F.h.n2;
+  {
+    std::vector<double> h(n2);
+    HIPCHK(hipMemcpyAsync(h.data(), T2, n2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    for (long long i = 0; i < n2; ++i) REQUIRE(std::isfinite(h[i]), "temperature must be finite");
+  }
+  c.vbase.upload(std::vector<double>(base, base + nbase));
+  const ViscDev vm{c.vbase.p, nbase, EA, VA, c.desc.r_in, c.desc.r_out};
+  for (int l = c.lmin(); l <= Lf; ++l) {
+    LevelData& L = c.at(l);
+    L.T2.alloc(L.h.n2);
+    L.T2f.alloc(L.h.n2);
+    L.d.T2 = L.T2.p;
+    L.d.T2f = L.T2f.p;
+    L.d.vm = vm;
+  }
+  vcopy<double>(T2, F.T2.p, n2, c.s);
+  for (int l = Lf; l > c.lmin(); --l) launch_inject_p2<double>(c.at(l - 1).d, c.at(l).d, c.at(l).T2.p, c.at(l - 1).T2.p, c.s);
+  for (int l = c.lmin(); l <= Lf; ++l) vconvert<double, float>(c.at(l).T2.p, c.at(l).T2f.p, c.at(l).h.n2, c.s);
+  configure_viscosity_levels(c, l_eta);
+  F.eta.alloc(F.h.n1);
+  launch_eta_vertices(F.d, F.eta.p, c.s);
+  set_fields_internal(c, F.eta.p, lnrho, par);
 }
 
 void need_ready(Ctx* c) {
@@ -1262,6 +1314,7 @@ int stk_coords(const stk_ctx* ctx, int level, int which, double* xyz, uint8_t* f
 int stk_set_fields(stk_ctx* ctx, const double* eta_p1, const double* lnrho_p1, const stk_solver_params* params) {
   return guard([&] {
     REQUIRE(ctx && eta_p1, "null argument");
+    configure_viscosity_levels(*ctx, -1);
     set_fields_internal(*ctx, eta_p1, lnrho_p1, params);
   });
 }
@@ -1269,10 +1322,19 @@ int stk_set_fields(stk_ctx* ctx, const double* eta_p1, const double* lnrho_p1, c
 int stk_set_log_viscosity(stk_ctx* ctx, const double* m_p1, const double* lnrho_p1, const stk_solver_params* params) {
   return guard([&] {
     REQUIRE(ctx && m_p1, "null argument");
+    configure_viscosity_levels(*ctx, -1);
     LevelData& F = ctx->at(ctx->L());
     F.eta.alloc(F.h.n1);
     vexp(m_p1, F.eta.p, F.h.n1, ctx->s);
     set_fields_internal(*ctx, F.eta.p, lnrho_p1, params);
+  });
+}
+
+int stk_set_temperature_viscosity(stk_ctx* ctx, const double* T_p2, const double* lnrho_p1, const double* eta_base,
+                                  int n_base, double E_A, double V_A, int l_eta, const stk_solver_params* params) {
+  return guard([&] {
+    REQUIRE(ctx && T_p2 && eta_base, "null argument");
+    set_temperature_viscosity_internal(*ctx, T_p2, lnrho_p1, eta_base, n_base, E_A, V_A, l_eta, params);
   });
 }
 
@@ -1355,7 +1417,8 @@ int stk_diag_A(stk_ctx* ctx, int level, double* d) {
     REQUIRE(d, "null vector");
     LevelData& L = ctx->at(level);
     vfill<double>(d, 0.0, 3 * L.h.n2, ctx->s);
-    launch_diag<double>(L.d, L.eta.p, d, ctx->s);
+    if (L.d.qpv) launch_elem_diag(L.d, L.eta.p, d, ctx->s);
+    else launch_diag<double>(L.d, L.eta.p, d, ctx->s);
     HIPCHK(hipGetLastError());
   });
 }
