@@ -559,7 +559,26 @@ void build_gather(const MacroMesh& mm, const Level& lv, const Sweep& sw, int whi
       const uint32_t g = l2g[(size_t)mc * nloc + e.first];
       slot[pos[g]++] = (int)((int64_t)mc * nsh + e.second);
     }
-  // pos[g] now points past the node's range; slots are in (macro, slot) order
+  // pos[g] now points past the node's range; a node's slots are in macro
+  // order.  Order the nodes by their first slot, so that neighbouring threads
+  // of the gather read neighbouring slots (the slots of one macro face are
+  // contiguous in both of its macros).
+  const size_t nn = node.size();
+  std::vector<int> order(nn);
+  for (size_t i = 0; i < nn; ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return slot[ptr[a]] < slot[ptr[b]]; });
+  std::vector<uint32_t> node2(nn);
+  std::vector<int> ptr2(1, 0), slot2;
+  slot2.reserve(slot.size());
+  for (size_t i = 0; i < nn; ++i) {
+    const int a = order[i];
+    node2[i] = node[a];
+    for (int k = ptr[a]; k < ptr[a + 1]; ++k) slot2.push_back(slot[k]);
+    ptr2.push_back((int)slot2.size());
+  }
+  node.swap(node2);
+  ptr.swap(ptr2);
+  slot.swap(slot2);
 }
 
 void level_coords(const MacroMesh& mm, const Topology& top, const Level& lv, int which, double* X,
