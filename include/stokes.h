@@ -110,7 +110,9 @@ typedef struct {
 } stk_report;
 
 /* Sec. 4.1: build the macro mesh, refine to `level`, number the nodes and
- * upload the tables.  `hip_stream` is a hipStream_t (NULL = default). */
+ * upload the tables.  `hip_stream` is a hipStream_t (NULL = default).
+ * STK_EINVAL also when the coarsest level (min_level) has more than 262144
+ * P2 nodes or 596523 micro-tets: its CG keeps the element matrices. */
 int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out);
 int stk_destroy(stk_ctx* ctx);
 void stk_default_params(stk_solver_params* p);

@@ -137,7 +137,7 @@ struct LevelData {
   DBuf<double> T2;
   DBuf<float> T2f;
   // coarsest level: element matrices and node data of its CG
-  bool ccg = false;
+  bool ccg = false;   // set on the coarsest level
   CoarseDev cd{};
   DBuf<uint32_t> c_enode;
   DBuf<double> c_emat, c_nrm;
@@ -405,19 +405,12 @@ void coarse_cg64(Ctx& c, const double* b, double* x, double tol, int maxit, bool
   double* z = P.get(W_C_Z, N, c.s);
   double* p = P.get(W_C_P, N, c.s);
   double* q = P.get(W_C_Q, N, c.s);
-  if (L.ccg) {
-    double* Y = P.get(W_C_Y, (size_t)L.cd.ne * 30, c.s);
-    double* part = c.cgpart.p;
-    double* sc = c.cgbuf.p;
-    ccg_init(L.cd, b, x, r, z, tol, part, sc, c.s);
-    const int its = run_chunks(c, sc, 4, maxit,
-                               [&](int it) { ccg_iter(L.cd, fp32, x, r, z, p, q, Y, part, sc, it, c.s); });
-    if (c.rep) c.rep->coarse_its += its;
-    return;
-  }
-  const int its = dev_pcg<double>(
-      c, N, [&](const double* pp, double* qq) { applyA<double>(c, l, pp, qq, BCM_IN | BCM_OUT); },
-      [&](double* v) { project<double>(c, l, v); }, L.dinv.p, b, x, r, z, p, q, tol, maxit, 8);
+  double* Y = P.get(W_C_Y, (size_t)L.cd.ne * 30, c.s);
+  double* part = c.cgpart.p;
+  double* sc = c.cgbuf.p;
+  ccg_init(L.cd, b, x, r, z, tol, part, sc, c.s);
+  const int its = run_chunks(c, sc, 4, maxit,
+                             [&](int it) { ccg_iter(L.cd, fp32, x, r, z, p, q, Y, part, sc, it, c.s); });
   if (c.rep) c.rep->coarse_its += its;
 }
 
@@ -812,7 +805,8 @@ void setup_coarse(Ctx& c, LevelData& L, const std::vector<int>& ea) {
   const int n = h.n, m2 = 2 * n, nm = c.mm.nm();
   const long long ne = (long long)ea.size() * nm;
   const long long nn = h.n2;
-  if (nn > 256LL * DOT_BLOCKS || ne * 900 * 8 > (4LL << 30)) return;   // stays on the element-kernel CG
+  REQUIRE(nn <= 256LL * DOT_BLOCKS && ne * 900 * 8 <= (4LL << 30),
+          "min_level too fine: the coarsest level must have at most 262144 P2 nodes and 596523 micro-tets");
   std::vector<uint32_t> en((size_t)ne * 10);
   for (int mac = 0; mac < nm; ++mac)
     for (size_t k = 0; k < ea.size(); ++k) {
