@@ -1,0 +1,38 @@
+"""The seeded synthetic input generators (CPU): determinism and the properties
+the workloads rely on."""
+import numpy as np
+
+import inputs
+
+
+def test_plate_velocity_is_tangential_piecewise_rigid_and_seeded():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2000, 3))
+    x /= np.linalg.norm(x, axis=1)[:, None]
+    u = inputs.plate_velocity(13, x)
+    assert np.abs(np.einsum("ij,ij->i", u, x)).max() < 1e-14          # u . n = 0 on the sphere
+    assert np.array_equal(u, inputs.plate_velocity(13, x))              # seeded
+    assert not np.allclose(u, inputs.plate_velocity(14, x))
+    # rigid rotation per plate: u = omega_k x X for one of n_plates poles
+    centres = np.random.default_rng(13).normal(size=(6, 3))
+    centres /= np.linalg.norm(centres, axis=1)[:, None]
+    plate = np.argmax(x @ centres.T, axis=1)
+    for k in range(6):
+        sel = plate == k
+        if sel.sum() < 3:
+            continue
+        # one rotation vector om with u = om x X fits every point of the plate
+        P = x[sel]
+        C = np.zeros((len(P), 3, 3))                 # C @ om = X x om = -(om x X)
+        C[:, 0, 1], C[:, 0, 2] = -P[:, 2], P[:, 1]
+        C[:, 1, 0], C[:, 1, 2] = P[:, 2], -P[:, 0]
+        C[:, 2, 0], C[:, 2, 1] = -P[:, 1], P[:, 0]
+        om = np.linalg.lstsq(C.reshape(-1, 3), -u[sel].ravel(), rcond=None)[0]
+        assert np.abs(np.cross(om, P) - u[sel]).max() < 1e-12
+
+
+def test_base_viscosity_profile_is_positive_and_layered():
+    b = inputs.base_viscosity_profile(65)
+    r = np.linspace(inputs.R_IN, inputs.R_OUT, 65)
+    assert (b > 0).all() and b.max() / b.min() > 1e2
+    assert b[r >= 0.97].min() > b[(r > 0.88) & (r < 0.95)].max()         # stiff lithosphere over a weak layer
