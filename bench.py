@@ -34,8 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # counted FP32 VALU arithmetic per micro-tet of the A-apply sweep kernel
-# (fma/fmac/fmamk = 2 flops, mul/add/sub = 1, rsq/rcp = 1), taken from the
-# kernel's gfx950 assembly; see the design doc for the count and how it was made
+# (fma/fmac/fmamk = 2 flops, mul/add/sub = 1, rsq/rcp = 1): the VALU
+# instructions of the element-loop body in the kernel's gfx950 assembly (917
+# instructions, one micro-tet per lane and iteration)
 A_FLOPS_PER_TET_FP32 = 1194
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flops x 2.4 GHz
