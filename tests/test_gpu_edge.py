@@ -1,0 +1,78 @@
+"""Degenerate and invalid inputs through the C ABI (GPU): a zero right-hand
+side, a one-level hierarchy (the V-cycle is the coarse solve alone), and the
+errors the ABI promises."""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from oracle.fem import assemble_A, assemble_B
+from oracle.system import solve_stokes
+from paper_2506_04157_amd import StokesContext, default_params
+from paper_2506_04157_amd._lib import STK_EINVAL, STK_ENOTREADY, StokesError
+from tests._util import Pair, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def test_zero_right_hand_side_gives_zero_solution():
+    sc = StokesContext("shell", level=2, min_level=0)
+    n2, n1 = sc.sizes()
+    sc.set_fields(torch.ones(n1, dtype=torch.float64, device="cuda"))
+    for prec in (64, 32):
+        u, p, rep = sc.solve(torch.zeros(3 * n2, dtype=torch.float64, device="cuda"),
+                             params=default_params(precision=prec))
+        assert rep["iterations"] == 0 and rep["initial_residual"] == 0.0
+        assert torch.count_nonzero(u).item() == 0 and torch.count_nonzero(p).item() == 0
+    sc.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_one_level_hierarchy(precision):
+    print(f"\n[one level cube prec {precision}]", flush=True)
+    P = Pair("cube", 2, min_level=2)
+    m = P.meshes[2]
+    eta = np.exp(inputs.uniform(3, m.n1, -1.0, 1.0))
+    f = inputs.uniform(4, 3 * m.n2)
+    A, B = assemble_A(m, eta), assemble_B(m)
+    _, Q = P.projector()
+    uo, po, _ = solve_stokes(A, B, f, np.zeros(m.n1), Q, Bt=B.T)
+    params = default_params(tol_rel=1e-10, precision=precision)
+    P.ctx.set_fields(P.p_to_lib(eta), params=params)
+    u, p, rep = P.ctx.solve(P.u_to_lib(f), params=params)
+    assert rep["rel_residual"] <= 1e-10
+    assert relerr(P.u_to_or(u), uo) < 1e-7 and relerr(P.p_to_or(p), po) < 1e-6
+
+
+def test_invalid_inputs_are_refused():
+    sc = StokesContext("shell", level=1, min_level=0)
+    n2, n1 = sc.sizes()
+    with pytest.raises(StokesError) as e:
+        sc.solve(torch.zeros(3 * n2, dtype=torch.float64, device="cuda"))
+    assert e.value.code == STK_ENOTREADY
+    for bad in (0.0, -1.0, float("nan")):
+        eta = torch.ones(n1, dtype=torch.float64, device="cuda")
+        eta[n1 // 2] = bad
+        with pytest.raises(StokesError) as e:
+            sc.set_fields(eta)
+        assert e.value.code == STK_EINVAL
+    sc.set_fields(torch.ones(n1, dtype=torch.float64, device="cuda"))
+    x = torch.zeros(3 * n2, dtype=torch.float64, device="cuda")
+    with pytest.raises(StokesError) as e:
+        sc.apply_A(x, level=5)
+    assert e.value.code == STK_EINVAL
+    T = torch.zeros(n2, dtype=torch.float64, device="cuda")
+    with pytest.raises(StokesError) as e:   # l_eta must be below the finest level
+        sc.set_temperature_viscosity(T, inputs.base_viscosity_profile(), l_eta=1)
+    assert e.value.code == STK_EINVAL
+    with pytest.raises(StokesError) as e:   # a base profile needs two positive samples
+        sc.set_temperature_viscosity(T, [1.0], l_eta=0)
+    assert e.value.code == STK_EINVAL
+    sc.close()
+    cube = StokesContext("cube", level=1, min_level=0)
+    c2, c1 = cube.sizes()
+    with pytest.raises(StokesError) as e:   # quadrature-point viscosity needs the blended shell
+        cube.set_temperature_viscosity(torch.zeros(c2, dtype=torch.float64, device="cuda"),
+                                       inputs.base_viscosity_profile(), l_eta=0)
+    assert e.value.code == STK_EINVAL
+    cube.close()
