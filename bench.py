@@ -189,7 +189,29 @@ def summarize_traffic(dfetch, dwrite, n_u, out, cmd):
     print("\n".join(lines))
 
 
+def summarize_counters(d, out, cmd, match):
+    """Per-kernel averages of every counter of a rocprofv3 --pmc run over the
+    dispatches whose kernel name contains `match`, grouped by grid size."""
+    acc = {}
+    for r in _rows(os.path.join(d, "run_counter_collection.csv")):
+        if match not in r["Kernel_Name"]:
+            continue
+        key = (r["Kernel_Name"][:90], int(r["Grid_Size"]), r["Counter_Name"])
+        acc.setdefault(key, []).append(float(r["Counter_Value"]))
+    lines = ["# rocprofv3 counter summary (average per dispatch)", f"# command: {cmd}", ""]
+    for (k, g, c) in sorted(acc, key=lambda t: (t[0], -t[1], t[2])):
+        v = acc[(k, g, c)]
+        lines.append(f"{k}  grid {g:>10d}  {c:<16s} {sum(v) / len(v):14.4f}  ({len(v)} dispatches)")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        # bench.py --summarize-counters DIR OUT "COMMAND" KERNEL_SUBSTRING
+        summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
         # bench.py --summarize-profile DIR OUT "COMMAND"
         summarize_profile(sys.argv[2], sys.argv[3], sys.argv[4])
@@ -209,6 +231,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the A-apply timings (for counter collection)")
+    ap.add_argument("--transfer-only", action="store_true",
+                    help="only the finest-level FP32 restriction and prolongation (for counter collection)")
     ap.add_argument("--l-eta-study", action="store_true",
                     help="only the coarse-viscosity study: A-block CG iterations and time of 10 FGMRES "
                          "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
@@ -269,6 +293,27 @@ def main():
         del a, b
         result["a_apply"] = a_apply()
         print(json.dumps(result["a_apply"]), flush=True)
+        return
+
+    if args.transfer_only:
+        # five FP32 restrictions to and prolongations from the next coarser
+        # level; each call zero-fills its output and returns synchronised
+        sc.set_log_viscosity(mlog, lnrho, mixed)
+        lf = args.level
+        nc = 3 * sc.sizes(lf - 1)[0]
+        rf = torch.tensor(inputs.uniform(1, Nu), dtype=torch.float32, device=dev)
+        ec = torch.tensor(inputs.uniform(2, nc), dtype=torch.float32, device=dev)
+        out = {}
+        for name, fn in (("restrict", lambda: sc.restrict(rf, lf)), ("prolong", lambda: sc.prolong(ec, lf))):
+            fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            out[name] = {"ms_per_call": (time.perf_counter() - t1) / 5 * 1e3}
+            log(f"{name} level {lf}: {out[name]['ms_per_call']:.3f} ms per call")
+        print(json.dumps(out), flush=True)
         return
 
     if args.l_eta_study:
