@@ -229,3 +229,86 @@ def test_viscosity_model_and_vertex_nodes():
     ms = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 2)
     v2 = vertex_p2_nodes(ms)
     assert np.abs(ms.X2[v2] - ms.X1).max() < 1e-15
+
+
+def _p1_quadrature_points(ev):
+    """Barycentric weights, reference points and weights (|K| / 4) of the
+    symmetric 4-point rule on each reference element, computed from the
+    element's vertices alone: point q has weight a on vertex q and b on the
+    others, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20."""
+    a, b = (5.0 + 3.0 * 5 ** 0.5) / 20.0, (5.0 - 5 ** 0.5) / 20.0
+    lam = np.full((4, 4), b) + (a - b) * np.eye(4)
+    vol = np.abs(np.linalg.det(ev[:, 1:] - ev[:, :1])) / 6.0
+    xq = np.einsum("qi,eid->eqd", lam, ev)
+    return lam, xq, vol / 4.0
+
+
+def test_mass_weight_is_reciprocal_viscosity_at_the_points():
+    """M_{1/eta} (Sec. 5.2.3, eq. schurMass; reading: consistent mass with
+    weight 1/eta_h(x_q)).  On affine (cube) elements an affine eta is its own
+    P1 interpolant, so every entry must equal the 4-point quadrature of
+    psi_i psi_j / eta(x_q) with eta evaluated analytically at the physical
+    points; interpolating 1/eta instead (the other plausible reading) differs."""
+    m = RefinedMesh(cube_macros(), 2)
+    k, c0 = np.array([2.0, -1.5, 3.0]), 2.0
+    eta_fn = lambda X: c0 + X @ k                      # in [0.5, 7] on the unit cube
+    M = assemble_M_inv_eta(m, eta_fn(m.x1)).toarray()
+    lam, xq, wq = _p1_quadrature_points(m.ev)
+    ref = np.zeros((m.n1, m.n1))
+    Me = np.einsum("e,eq,qi,qj->eij", wq, 1.0 / eta_fn(xq), lam, lam)
+    for i in range(4):
+        for j in range(4):
+            np.add.at(ref, (m.e1[:, i], m.e1[:, j]), Me[:, i, j])
+    assert np.abs(M - ref).max() <= 1e-14 * np.abs(ref).max()
+    # negative control: the P1 interpolant of 1/eta at the points
+    inv_h = np.einsum("qk,ek->eq", lam, 1.0 / eta_fn(m.x1)[m.e1])
+    Mi = np.einsum("e,eq,qi,qj->eij", wq, inv_h, lam, lam)
+    alt = np.zeros_like(ref)
+    for i in range(4):
+        for j in range(4):
+            np.add.at(alt, (m.e1[:, i], m.e1[:, j]), Mi[:, i, j])
+    assert np.abs(alt - ref).max() > 1e-4 * np.abs(ref).max()
+
+
+def test_buoyancy_uses_the_p2_temperature_at_the_points():
+    """f_i = int T_h r_hat . phi_i (Sec. 5.1 right-hand side, unit scaling):
+    T_h is the P2 interpolant on the reference (unblended) mesh, so for T
+    quadratic in the reference coordinate x~ it is exact at every quadrature
+    point.  The reference is built without the oracle's geometry code: points
+    from the element vertices, the blended weight |det J_F| |det J_B| with
+    det J_B from central differences of the blending map, r_hat = x~/|x~|
+    (the map is radial), and the P2 basis from its barycentric formulas.
+    A P1 interpolation of T (a plausible mistake) differs."""
+    m = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 1)
+    Tfn = lambda x: 0.4 + 0.3 * x[..., 0] * x[..., 2] - 0.2 * x[..., 1] ** 2 + 0.5 * x[..., 2]
+    f = rhs_buoyancy(m, Tfn(m.x2))
+    lam, xq, wq = _p1_quadrature_points(m.ev)
+    g, s0 = m.blend_g[m.emacro], m.blend_s0[m.emacro]
+
+    def blend(x):
+        s = np.einsum("ed,eqd->eq", g, x) + s0[:, None]
+        return x * (s / np.linalg.norm(x, axis=-1))[..., None]
+
+    h = 1e-6
+    J = np.empty(xq.shape + (3,))
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = h
+        J[..., d] = (blend(xq + e) - blend(xq - e)) / (2 * h)
+    detB = np.linalg.det(J)
+    rhat = xq / np.linalg.norm(xq, axis=-1, keepdims=True)
+    edges = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+    N = np.concatenate([lam * (2 * lam - 1), np.stack([4 * lam[:, i] * lam[:, j] for i, j in edges], 1)], 1)
+
+    def assemble(Tq):
+        fe = np.einsum("eq,eq,eq,eqc,qa->eca", wq[:, None] * np.ones((1, 4)), detB, Tq, rhat, N)
+        ref = np.zeros(3 * m.n2)
+        for c in range(3):
+            np.add.at(ref, c * m.n2 + m.e2, fe[:, c, :])
+        return ref
+
+    ref = assemble(Tfn(xq))
+    assert np.abs(f - ref).max() <= 1e-8 * np.abs(ref).max()
+    # negative control: T from its vertex values only (P1 interpolation)
+    Tp1 = np.einsum("qk,ek->eq", lam, Tfn(m.x2)[m.e2[:, :4]])
+    assert np.abs(assemble(Tp1) - ref).max() > 1e-4 * np.abs(ref).max()
