@@ -8,41 +8,53 @@ eta = exp(ln(1e4) (0.5 - T)) from a seeded degree-8 spherical-harmonic
 temperature T, density rho = exp(0.5 (1 - r)), buoyancy f = int T r_hat . phi,
 no-slip inner and free-slip outer boundary.  All inputs are synthetic.
 
-One step is one forward + backward pass of the differentiable solve:
-  set_log_viscosity  (eta on every level, diag(A), FP64 Chebyshev bounds)
-  rhs_buoyancy       (f from T)
-  solve              (FP64 FGMRES to 1e-8 relative residual, symmetric Uzawa
-                      with V-cycle BFBT, FP32 multigrid / Schur inner solves)
-  solve_adjoint      (the same solver on the transposed system, J = |u|^2 / 2)
-  gradient           (dJ/d ln eta and dJ/dT)
-value = (N_u + N_p) / seconds per step, in MDoF/s.
+One timed step is one finest-level FP64 A-apply y = P A P x (the plane-sweep
+kernel, the gather of shared nodes and the boundary projection) on a resident
+seeded vector: value = N_u / seconds per step in GDoF/s.  The sweep kernel of
+every timed step is bracketed by HIP events on the library's stream
+(stk_kernel_timer); its average duration gives the roofline position.
 
-Outside the timed steps the bench also reports: the A-apply throughput at the
-finest level in FP32 and FP64 (N_u / time per apply), the all-FP64 forward
-solve with its time and the mixed solve's difference from it, the roofline
-position of the dominant kernel (the FP32 A-apply sweep) and the CPU oracle
-timed on a small shell sample.
+After the timed steps, each once, within a wall-clock budget (STK_BENCH_BUDGET_S,
+default 420 s from the start; legs that would not fit are listed as skipped):
+  the FP32 A-apply (events, 20 applies);
+  the CPU oracle: scipy FP64 SpMV of the assembled A on the 10x2 shell at
+    level 1 (1 core, median of 20), and the oracle's direct solve pipeline on
+    a 3x1 level-1 shell;
+  the mixed-precision forward solve to 1e-8 (FP32 multigrid / Schur inner
+    solves inside FP64 FGMRES) and the all-FP64 forward solve, with times,
+    iterations, residuals and their difference;
+  the mixed adjoint solve (J = |u|^2 / 2) and the gradient kernel.
+The JSON line is printed once at the end, also when a leg fails or the
+process receives SIGTERM.
 """
 import argparse
 import hashlib
 import json
 import os
+import signal
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# counted FP32 VALU arithmetic per micro-tet of the A-apply sweep kernel
-# (fma/fmac/fmamk = 2 flops, mul/add/sub = 1, rsq/rcp = 1): the VALU
-# instructions of the element-loop body in the kernel's gfx950 assembly (917
-# instructions, one micro-tet per lane and iteration)
-A_FLOPS_PER_TET_FP32 = 1194
-PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
+# Algorithmic arithmetic of the blended A-apply per micro-tet (4 quadrature
+# points): the FP32 sweep's element loop counted from its gfx950 assembly
+# (fma/fmac/fmamk = 2 flops, mul/add/sub = 1, rsq/rcp = 1).  The FP64 kernel
+# executes about 100 more per micro-tet, the Newton steps of its rsq/rcp; they
+# are not counted as algorithmic work.
+A_FLOPS_PER_TET = 1194
+PEAK_FP64_TFLOPS = 78.6           # MI355X published FP64 vector peak
+PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak (packed)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flops x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_A_fp32_shell10x2_L4.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILES = {64: os.path.join(PROFILES, "traffic_k_sweep_A_fp64_shell10x2_L4.txt"),
+                 32: os.path.join(PROFILES, "traffic_k_sweep_A_fp32_shell10x2_L4.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_04157_amd", "csrc", "kernels.hip")
+ROOF_KERNELS = {64: "k_sweep<double, true, 1>", 32: "k_sweep<float, true, 1>"}
+METRIC = "A-apply GDoF/s + time-to-1e-8 Stokes solve, FP32-MG vs FP64, 1 MI355X"
 
 
 def log(*a):
@@ -54,13 +66,14 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(prec=64):
     """HBM bytes per launch of the roofline kernel from the committed counter
     summary, or None when absent or taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[prec]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -73,9 +86,23 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(nt=3, nr=1, level=1):
-    """The FP64 oracle (assembly + constrained direct solve, adjoint solve and
-    assembled gradient) on a small shell of the same family, one thread."""
+def host_cpu():
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "lscpu_model": model}
+
+
+def cpu_baseline(nt=10, nr=2, level=1, solve_nt=3, solve_nr=1, solve_level=1):
+    """The FP64 oracle timed on the host: scipy SpMV of the assembled A (1
+    thread, median of 20) on the 10x2 shell at level 1, in GDoF/s; and, as a
+    secondary figure, the oracle's direct-solve pipeline (assembly,
+    constrained forward and adjoint direct solves, gradient) on a small shell."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -85,29 +112,49 @@ def cpu_baseline(nt=3, nr=1, level=1):
     from oracle.mesh import RefinedMesh, shell_macros
     from oracle.system import solve_stokes, velocity_basis
 
+    field = inputs.SHField(2)
     with threadpool_limits(1):
         t0 = time.perf_counter()
         m = RefinedMesh(shell_macros(nt, nr, 0.55, 1.0), level)
-        field = inputs.SHField(2)
-        T2, T1 = field.temperature(m.X2), field.temperature(m.X1)
-        eta = inputs.viscosity_contrast(T1, 1e4)
-        lnrho = inputs.ln_density(m.X1)
+        eta = inputs.viscosity_contrast(field.temperature(m.X1), 1e4)
         A = assemble_A(m, eta)
-        B = assemble_B(m)
-        Bbar = B + assemble_B(m, lnrho, only_C=True)
-        f = rhs_buoyancy(m, T2)
-        Q, _, _ = velocity_basis(m, {1}, {2})
-        u, p, _ = solve_stokes(A, Bbar, f, np.zeros(m.n1), Q, Bt=B.T)
-        lam, _, _ = solve_stokes(A, B, u, np.zeros(m.n1), Q, Bt=Bbar.T)
-        grad_log_eta(m, eta, u, lam)
-        grad_temperature(m, lam)
-        dt = time.perf_counter() - t0
-    ndof = 3 * m.n2 + m.n1
-    return {"value": ndof / dt / 1e6, "unit": "MDoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"shell {nt}x{nr} ({60 * nt * nt * nr} macro-tets) level {level}, N_u={3 * m.n2}, "
-                       f"N_p={m.n1}, same fields and BCs; mesh + assembly + direct forward and adjoint "
-                       f"solves + gradient in FP64, {dt:.1f} s on 1 thread"),
-            "seconds": dt}
+        t_asm = time.perf_counter() - t0
+        x = inputs.uniform(0, A.shape[0])
+        ts = []
+        for _ in range(20):
+            s = time.perf_counter()
+            y = A @ x
+            ts.append(time.perf_counter() - s)
+        t_spmv = float(np.median(ts))
+        nu = A.shape[0]
+        del A, y
+        # secondary: the direct-solve pipeline on a small shell
+        t1 = time.perf_counter()
+        ms = RefinedMesh(shell_macros(solve_nt, solve_nr, 0.55, 1.0), solve_level)
+        T2, T1 = field.temperature(ms.X2), field.temperature(ms.X1)
+        eta_s = inputs.viscosity_contrast(T1, 1e4)
+        lnrho = inputs.ln_density(ms.X1)
+        As = assemble_A(ms, eta_s)
+        B = assemble_B(ms)
+        Bbar = B + assemble_B(ms, lnrho, only_C=True)
+        f = rhs_buoyancy(ms, T2)
+        Q, _, _ = velocity_basis(ms, {1}, {2})
+        u, p, _ = solve_stokes(As, Bbar, f, np.zeros(ms.n1), Q, Bt=B.T)
+        lam, _, _ = solve_stokes(As, B, u, np.zeros(ms.n1), Q, Bt=Bbar.T)
+        grad_log_eta(ms, eta_s, u, lam)
+        grad_temperature(ms, lam)
+        t_pipe = time.perf_counter() - t1
+    ndof_s = 3 * ms.n2 + ms.n1
+    return {"value": nu / t_spmv / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"assembled FP64 A of the oracle (scipy CSR SpMV, 1 thread, median of 20) on the "
+                       f"{nt}x{nr} shell ({60 * nt * nt * nr} macro-tets) at level {level}: N_u={nu}; "
+                       f"{t_spmv * 1e3:.1f} ms per SpMV; mesh + assembly {t_asm:.1f} s"),
+            "spmv_ms": t_spmv * 1e3, "assembly_s": t_asm,
+            "direct_solve_pipeline": {
+                "sample": (f"{solve_nt}x{solve_nr} shell level {solve_level} (N_u={3 * ms.n2}, N_p={ms.n1}): "
+                           "mesh, assembly, constrained direct forward and adjoint solves, gradient, FP64, 1 thread"),
+                "seconds": t_pipe, "mdof_s": ndof_s / t_pipe / 1e6},
+            "host": host_cpu()}
 
 
 def _rows(path):
@@ -116,10 +163,10 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
-ROOF_KERNEL = "k_sweep<float, true, 1>"
+ROOF_KERNEL = ROOF_KERNELS[64]
 
 
-def summarize_profile(d, out, cmd):
+def summarize_profile(d, out, cmd, kernel=ROOF_KERNEL):
     """Text summary of a rocprofv3 --kernel-trace --stats run: the kernels by
     total time and, from the trace, the roofline kernel's launches grouped by
     grid size (the finest level has the largest grid)."""
@@ -137,13 +184,13 @@ def summarize_profile(d, out, cmd):
         groups = {}
         with open(tr) as fh:
             for r in csv.DictReader(fh):
-                if ROOF_KERNEL not in r["Kernel_Name"]:
+                if kernel not in r["Kernel_Name"]:
                     continue
                 g = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
                 dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
                 s_, c_ = groups.get(g, (0, 0))
                 groups[g] = (s_ + dt, c_ + 1)
-        lines += ["", f"{ROOF_KERNEL} launches by grid size (work-items):"]
+        lines += ["", f"{kernel} launches by grid size (work-items):"]
         for g in sorted(groups, reverse=True):
             s_, c_ = groups[g]
             lines.append(f"  grid {g:>10d}: {c_:6d} launches, average {s_ / c_ / 1e3:10.1f} us")
@@ -152,7 +199,7 @@ def summarize_profile(d, out, cmd):
     print("\n".join(lines))
 
 
-def summarize_traffic(dfetch, dwrite, n_u, out, cmd):
+def summarize_traffic(dfetch, dwrite, n_u, out, cmd, kernel=ROOF_KERNEL):
     """HBM bytes per launch of the roofline kernel at the finest level from
     FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by the ratio of
     known bytes to the counter's reading on the plain copy of n_u floats that
@@ -173,12 +220,12 @@ def summarize_traffic(dfetch, dwrite, n_u, out, cmd):
         return max(cands)[0]
     kf, kw = known / (copy_kib(f) * 1024.0), known / (copy_kib(w) * 1024.0)
     def roof(acc):
-        cands = [(k[1], sum(v) / len(v)) for k, v in acc.items() if ROOF_KERNEL in k[0]]
+        cands = [(k[1], sum(v) / len(v)) for k, v in acc.items() if kernel in k[0]]
         return max(cands)[1]
     fb, wb = roof(f) * 1024.0 * kf, roof(w) * 1024.0 * kw
     lines = ["# HBM traffic of the roofline kernel (finest level, largest grid)",
              f"# fetch command: {cmd[0]}", f"# write command: {cmd[1]}",
-             f"kernel: {ROOF_KERNEL}",
+             f"kernel: {kernel}",
              f"kernel_source_sha256_16: {kernel_sha()}",
              f"copy_bytes_known: {known:.0f}",
              f"fetch_scale: {kf:.4f}", f"write_scale: {kw:.4f}",
@@ -207,26 +254,55 @@ def summarize_counters(d, out, cmd, match):
     print("\n".join(lines))
 
 
+def _roofline(prec, n_tets, nu, np_, ms_kernel, traffic):
+    """Roofline position of the A-apply sweep kernel from its average event
+    time: algorithmic flops (A_FLOPS_PER_TET per micro-tet) against the VALU
+    peak of its precision, and algorithmic bytes (x, y and eta once) against
+    HBM."""
+    peak = PEAK_FP64_TFLOPS if prec == 64 else PEAK_FP32_TFLOPS
+    wb = 8 if prec == 64 else 4
+    flops = A_FLOPS_PER_TET * n_tets
+    achieved = flops / (ms_kernel * 1e-3) / 1e12
+    algo_bytes = (2 * nu + np_) * wb
+    r = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+         "traffic": traffic,
+         "kernel": f"{ROOF_KERNELS[prec]} (A-apply plane sweep, finest level)",
+         "ms_per_launch": ms_kernel, "flops_per_launch": flops, "flops_per_micro_tet": A_FLOPS_PER_TET,
+         "hbm_gbs_algorithmic": algo_bytes / (ms_kernel * 1e-3) / 1e9,
+         "hbm_frac_algorithmic": algo_bytes / (ms_kernel * 1e-3) / 1e9 / PEAK_HBM_GBS,
+         "algorithmic_bytes_per_launch": algo_bytes}
+    if prec == 32:
+        r["frac_of_nonpacked_fp32_peak"] = achieved / PEAK_FP32_NONPACKED_TFLOPS
+    if traffic:
+        r["traffic_over_algorithmic"] = traffic / algo_bytes
+    return r
+
+
 def main():
+    t_begin = time.perf_counter()
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         # bench.py --summarize-counters DIR OUT "COMMAND" KERNEL_SUBSTRING
         summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
-        # bench.py --summarize-profile DIR OUT "COMMAND"
-        summarize_profile(sys.argv[2], sys.argv[3], sys.argv[4])
+        # bench.py --summarize-profile DIR OUT "COMMAND" [KERNEL]
+        summarize_profile(sys.argv[2], sys.argv[3], sys.argv[4], *sys.argv[5:6])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
-        # bench.py --summarize-traffic FETCH_DIR WRITE_DIR N_U OUT "FETCH_CMD" "WRITE_CMD"
-        summarize_traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], (sys.argv[6], sys.argv[7]))
+        # bench.py --summarize-traffic FETCH_DIR WRITE_DIR N_U OUT "FETCH_CMD" "WRITE_CMD" [KERNEL]
+        summarize_traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], (sys.argv[6], sys.argv[7]),
+                          *sys.argv[8:9])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--level", type=int, default=4)
     ap.add_argument("--n-tan", type=int, default=10)
     ap.add_argument("--n-rad", type=int, default=2)
+    ap.add_argument("--budget", type=float, default=float(os.environ.get("STK_BENCH_BUDGET_S", 420)),
+                    help="wall seconds from the start after which no further once-only leg is started")
+    ap.add_argument("--no-solves", action="store_true", help="skip the solve legs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--apply-only", action="store_true",
@@ -241,202 +317,277 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not "
               "part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.apply_only or args.transfer_only or args.l_eta_study:
+        return studies(args)
 
-    os.environ.setdefault("STK_VERBOSE", "1")   # solver progress on stderr
+    n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
+    workload = (f"blended spherical shell [0.55,1], icosahedral {args.n_tan}x{args.n_rad} macro mesh "
+                f"({60 * args.n_tan ** 2 * args.n_rad} macro-tets), level {args.level}, P2-P1; viscosity "
+                "contrast 1e4 from a seeded SH temperature, rho=exp(0.5(1-r)), no-slip inner / free-slip outer")
+    line = {
+        "metric": METRIC, "value": None, "unit": "GDoF/s",
+        "value_definition": "N_u / seconds per step; step = one finest-level FP64 A-apply y = P A P x "
+                            "(plane sweep + shared-node gather + projection), input resident in HBM",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload, "N_u": None, "N_p": None, "micro_tets": n_tets,
+                   "parallelism": "single GPU"},
+        "roofline": None, "cpu_baseline": None, "skipped": [], "errors": [],
+    }
+    printed = []
+
+    def emit(*_):
+        if printed:
+            return
+        printed.append(True)
+        line["wall_s"] = time.perf_counter() - t_begin
+        print(json.dumps(line), flush=True)
+
+    def on_term(signum, frame):
+        line["errors"].append(f"terminated by signal {signum}")
+        emit()
+        os._exit(128 + signum)
+
+    signal.signal(signal.SIGTERM, on_term)
+
+    def fits(name, seconds):
+        left = args.budget - (time.perf_counter() - t_begin)
+        if seconds > left:
+            line["skipped"].append({"leg": name, "estimated_s": seconds, "budget_left_s": round(left, 1)})
+            log(f"skip {name}: needs ~{seconds:.0f} s, {left:.0f} s left of the budget")
+            return False
+        return True
+
+    try:
+        run_bench(args, line, fits, n_tets)
+    except Exception as e:   # a late leg must not erase what was measured
+        import traceback
+        traceback.print_exc()
+        line["errors"].append(f"{type(e).__name__}: {e}")
+    finally:
+        emit()
+
+
+def run_bench(args, line, fits, n_tets):
     import numpy as np
     import torch
 
     import inputs
     from paper_2506_04157_amd import StokesContext, default_params
 
+    os.environ.setdefault("STK_VERBOSE", "1")   # solver progress lines on stderr
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    sc = StokesContext("shell", level=args.level, min_level=0, n_tan=args.n_tan, n_rad=args.n_rad, device=dev)
-    n2, n1 = sc.sizes()
-    Nu, Np = 3 * n2, n1
-    log(f"context {time.perf_counter() - t0:.1f}s  N_u={Nu} N_p={Np}")
-    X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
-    X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
-    field = inputs.SHField(2)
-    T2 = field.temperature_torch(X2).contiguous()
-    T1 = field.temperature_torch(X1)
-    mlog = (float(np.log(1e4)) * (0.5 - T1)).contiguous()
-    lnrho = (0.5 * (1.0 - torch.linalg.norm(X1, dim=1))).contiguous()
-    del X2, X1, T1
-    mixed = default_params(precision=32, tol_rel=1e-8)
-    full = default_params(precision=64, tol_rel=1e-8)
-    n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
-    result = {}
-
-    def a_apply():
-        out = {}
-        for dt_, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
-            x = torch.tensor(inputs.uniform(0, Nu), dtype=dt_, device=dev)
-            y = torch.empty_like(x)
-            sc.time_apply_A(x, y, reps=2)
-            ms, mk = sc.time_apply_A(x, y, reps=20)
-            out[name] = {"gdof_s": Nu / ms / 1e6, "ms_per_apply": ms, "ms_sweep_kernel": mk}
-            log(f"A-apply {name}: {ms:.3f} ms/apply ({Nu / ms / 1e6:.1f} GDoF/s), sweep kernel {mk:.3f} ms")
-            del x, y
-        return out
-
-    if args.apply_only:
-        # A-apply timings, preceded by plain device copies of known size that
-        # calibrate the HBM byte counters (FETCH_SIZE / WRITE_SIZE)
+    with StokesContext("shell", level=args.level, min_level=0, n_tan=args.n_tan, n_rad=args.n_rad,
+                       device=dev) as sc:
+        n2, n1 = sc.sizes()
+        Nu, Np = 3 * n2, n1
+        line["config"]["N_u"], line["config"]["N_p"] = Nu, Np
+        line["setup_s"] = {"context": time.perf_counter() - t0}
+        log(f"context {time.perf_counter() - t0:.1f}s  N_u={Nu} N_p={Np}")
+        X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
+        X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
+        field = inputs.SHField(2)
+        T2 = field.temperature_torch(X2).contiguous()
+        T1 = field.temperature_torch(X1)
+        mlog = (float(np.log(1e4)) * (0.5 - T1)).contiguous()
+        lnrho = (0.5 * (1.0 - torch.linalg.norm(X1, dim=1))).contiguous()
+        del X2, X1, T1
+        mixed = default_params(precision=32, tol_rel=1e-8)
+        full = default_params(precision=64, tol_rel=1e-8)
+        s = time.perf_counter()
         sc.set_log_viscosity(mlog, lnrho, mixed)
-        a = torch.ones(Nu, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
         torch.cuda.synchronize()
-        log(f"copy calibration: {3} copies of {4 * Nu} bytes")
-        del a, b
-        result["a_apply"] = a_apply()
-        print(json.dumps(result["a_apply"]), flush=True)
-        return
+        line["setup_s"]["fields"] = time.perf_counter() - s
 
-    if args.transfer_only:
-        # five FP32 restrictions to and prolongations from the next coarser
-        # level; each call zero-fills its output and returns synchronised
-        sc.set_log_viscosity(mlog, lnrho, mixed)
-        lf = args.level
-        nc = 3 * sc.sizes(lf - 1)[0]
-        rf = torch.tensor(inputs.uniform(1, Nu), dtype=torch.float32, device=dev)
-        ec = torch.tensor(inputs.uniform(2, nc), dtype=torch.float32, device=dev)
-        out = {}
-        for name, fn in (("restrict", lambda: sc.restrict(rf, lf)), ("prolong", lambda: sc.prolong(ec, lf))):
-            fn()
+        # ---- timed steps: one finest-level FP64 A-apply each ---------------------
+        x = torch.tensor(inputs.uniform(0, Nu), device=dev)
+        y = torch.empty_like(x)
+        for i in range(args.warmup):
+            sc.apply_A(x, out=y, bc=3)
+        torch.cuda.synchronize()
+        log(f"warmup {args.warmup} applies done; timing {args.steps}")
+        sc.kernel_timer(True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for i in range(args.steps):
+            sc.apply_A(x, out=y, bc=3)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        ms_k, nk = sc.kernel_timer(False)
+        ms_step = (te - ts) / args.steps * 1e3
+        line["ms_per_step"] = ms_step
+        line["value"] = Nu / (ms_step * 1e-3) / 1e9
+        line["step_timing"] = {"host_clock_ms_per_step": ms_step, "sweep_kernel_ms_per_launch": ms_k / max(nk, 1),
+                               "sweep_kernel_launches_timed": nk,
+                               "sweep_share_of_step": (ms_k / max(nk, 1)) / ms_step}
+        line["roofline"] = _roofline(64, n_tets, Nu, Np, ms_k / max(nk, 1),
+                                     read_traffic(64) if (args.level, args.n_tan, args.n_rad) == (4, 10, 2) else None)
+        log(f"FP64 A-apply: {ms_step:.3f} ms/step ({line['value']:.1f} GDoF/s), sweep kernel "
+            f"{ms_k / max(nk, 1):.3f} ms ({line['roofline']['frac'] * 100:.1f} % of FP64 peak)")
+        ynorm = torch.linalg.norm(y).item()
+        line["step_output_finite"] = bool(np.isfinite(ynorm))
+        del x, y
+
+        # ---- FP32 A-apply --------------------------------------------------------------
+        x32 = torch.tensor(inputs.uniform(0, Nu), dtype=torch.float32, device=dev)
+        y32 = torch.empty_like(x32)
+        sc.time_apply_A(x32, y32, reps=2)
+        ms32, mk32 = sc.time_apply_A(x32, y32, reps=20)
+        line["a_apply_fp32"] = {"gdof_s": Nu / (ms32 * 1e-3) / 1e9, "ms_per_apply": ms32, "ms_sweep_kernel": mk32,
+                                "roofline": _roofline(32, n_tets, Nu, Np, mk32,
+                                                      read_traffic(32) if (args.level, args.n_tan, args.n_rad)
+                                                      == (4, 10, 2) else None)}
+        log(f"FP32 A-apply: {ms32:.3f} ms ({Nu / ms32 / 1e6:.1f} GDoF/s), sweep kernel {mk32:.3f} ms")
+        del x32, y32
+
+        # ---- CPU oracle -------------------------------------------------------------------
+        if not args.no_cpu and fits("cpu_baseline", 60):
+            log("CPU oracle baseline")
+            cpu = cpu_baseline()
+            line["cpu_baseline"] = {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")}
+            line["cpu_baseline_detail"] = {k: cpu[k] for k in ("spmv_ms", "assembly_s", "direct_solve_pipeline",
+                                                               "host")}
+            log(f"oracle: {cpu['sample']}")
+
+        if args.no_solves:
+            return
+        # ---- solves -----------------------------------------------------------------------------
+        f = sc.rhs_buoyancy(T2)
+        solves = {}
+        line["solves"] = solves
+        u = p = None
+        if fits("mixed_forward_solve", 90):
+            log("mixed-precision forward solve")
+            u, p, rep = sc.solve(f, params=mixed)
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(5):
+            solves["mixed"] = _rep(rep)
+            log(f"mixed solve {rep['seconds']:.2f}s ({rep['iterations']} its, rel {rep['rel_residual']:.2e})")
+        if not args.no_fp64 and fits("fp64_forward_solve", 130):
+            log("all-FP64 forward solve")
+            u64, p64, r64 = sc.solve(f, params=full)
+            torch.cuda.synchronize()
+            solves["fp64"] = _rep(r64)
+            log(f"FP64 solve {r64['seconds']:.2f}s ({r64['iterations']} its)")
+            if u is not None:
+                du = (torch.linalg.norm(u - u64) / torch.linalg.norm(u64)).item()
+                dp = (torch.linalg.norm(p - p64) / torch.linalg.norm(p64)).item()
+                solves["mixed_vs_fp64"] = {
+                    "speedup": r64["seconds"] / solves["mixed"]["seconds"],
+                    "u_rel_diff": du, "p_rel_diff": dp}
+                log(f"mixed vs FP64: speed-up {solves['mixed_vs_fp64']['speedup']:.2f}, |du| {du:.2e}, |dp| {dp:.2e}")
+            del u64, p64
+        if u is not None and fits("adjoint_solve_and_gradient", 90):
+            log("mixed adjoint solve + gradient")
+            lu, lp, ra = sc.solve_adjoint(u, None, mixed)
+            torch.cuda.synchronize()
+            s = time.perf_counter()
+            gm, gT = sc.gradient(u, lu)
+            torch.cuda.synchronize()
+            solves["adjoint"] = _rep(ra)
+            solves["adjoint"]["gradient_s"] = time.perf_counter() - s
+            solves["adjoint"]["gradient_finite"] = bool(torch.isfinite(gm).all().item()
+                                                        and torch.isfinite(gT).all().item())
+            log(f"adjoint {ra['seconds']:.2f}s ({ra['iterations']} its)")
+
+
+def _rep(rep):
+    keys = ("seconds", "iterations", "rel_residual", "a_solves", "a_cg_its", "s_solves", "s_cg_its", "vcycles",
+            "coarse_its", "mass_its")
+    return {k: rep[k] for k in keys}
+
+
+def studies(args):
+    """Single-purpose runs for counter collection and the coarse-viscosity study."""
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2506_04157_amd import StokesContext, default_params
+
+    os.environ.setdefault("STK_VERBOSE", "1")
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    with StokesContext("shell", level=args.level, min_level=0, n_tan=args.n_tan, n_rad=args.n_rad,
+                       device=dev) as sc:
+        n2, n1 = sc.sizes()
+        Nu, Np = 3 * n2, n1
+        log(f"context {time.perf_counter() - t0:.1f}s  N_u={Nu} N_p={Np}")
+        X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
+        X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
+        field = inputs.SHField(2)
+        T2 = field.temperature_torch(X2).contiguous()
+        T1 = field.temperature_torch(X1)
+        mlog = (float(np.log(1e4)) * (0.5 - T1)).contiguous()
+        lnrho = (0.5 * (1.0 - torch.linalg.norm(X1, dim=1))).contiguous()
+        del X2, X1, T1
+        mixed = default_params(precision=32, tol_rel=1e-8)
+
+        if args.apply_only:
+            # A-apply timings, preceded by plain device copies of known size that
+            # calibrate the HBM byte counters (FETCH_SIZE / WRITE_SIZE)
+            sc.set_log_viscosity(mlog, lnrho, mixed)
+            a = torch.ones(Nu, dtype=torch.float32, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            log(f"copy calibration: 3 copies of {4 * Nu} bytes")
+            del a, b
+            out = {}
+            for dt_, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+                x = torch.tensor(inputs.uniform(0, Nu), dtype=dt_, device=dev)
+                y = torch.empty_like(x)
+                sc.time_apply_A(x, y, reps=2)
+                ms, mk = sc.time_apply_A(x, y, reps=20)
+                out[name] = {"gdof_s": Nu / ms / 1e6, "ms_per_apply": ms, "ms_sweep_kernel": mk}
+                log(f"A-apply {name}: {ms:.3f} ms/apply ({Nu / ms / 1e6:.1f} GDoF/s), sweep kernel {mk:.3f} ms")
+                del x, y
+            print(json.dumps(out), flush=True)
+            return
+
+        if args.transfer_only:
+            # five FP32 restrictions to and prolongations from the next coarser
+            # level; each call zero-fills its output and returns synchronised
+            sc.set_log_viscosity(mlog, lnrho, mixed)
+            lf = args.level
+            nc = 3 * sc.sizes(lf - 1)[0]
+            rf = torch.tensor(inputs.uniform(1, Nu), dtype=torch.float32, device=dev)
+            ec = torch.tensor(inputs.uniform(2, nc), dtype=torch.float32, device=dev)
+            out = {}
+            for name, fn in (("restrict", lambda: sc.restrict(rf, lf)), ("prolong", lambda: sc.prolong(ec, lf))):
                 fn()
-            torch.cuda.synchronize()
-            out[name] = {"ms_per_call": (time.perf_counter() - t1) / 5 * 1e3}
-            log(f"{name} level {lf}: {out[name]['ms_per_call']:.3f} ms per call")
-        print(json.dumps(out), flush=True)
-        return
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(5):
+                    fn()
+                torch.cuda.synchronize()
+                out[name] = {"ms_per_call": (time.perf_counter() - t1) / 5 * 1e3}
+                log(f"{name} level {lf}: {out[name]['ms_per_call']:.3f} ms per call")
+            print(json.dumps(out), flush=True)
+            return
 
-    if args.l_eta_study:
-        # Fig. AIterations setting: the first 10 FGMRES iterations of a solve,
-        # A-block CG iterations and their time, per choice of l_eta (-1: P1
-        # viscosity on every level)
-        base = inputs.base_viscosity_profile()
-        f = None
-        study = {}
-        for l_eta in (-1, 0, 1):
-            prm = default_params(precision=32, tol_rel=1e-12, max_outer=10)
-            sc.set_temperature_viscosity(T2, base, l_eta=l_eta, lnrho=lnrho, params=prm)
-            if f is None:
-                f = sc.rhs_buoyancy(T2)
-            u, p, rep = sc.solve(f, params=prm, allow_noconv=True)
-            torch.cuda.synchronize()
-            study[str(l_eta)] = {k: rep[k] for k in ("iterations", "rel_residual", "a_solves", "a_cg_its",
-                                                    "vcycles", "coarse_its", "seconds")}
-            log(f"l_eta {l_eta}: {rep['iterations']} FGMRES its, rel res {rep['rel_residual']:.2e}, "
-                f"A-block CG its {rep['a_cg_its']}, {rep['seconds']:.1f}s")
-        print(json.dumps({"l_eta_study": study, "E_A": 4.610, "V_A": 2.996,
-                          "eta_base": "inputs.base_viscosity_profile()", "level": args.level}), flush=True)
-        return
-
-    def step():
-        tt = {}
-        s = time.perf_counter()
-        sc.set_log_viscosity(mlog, lnrho, mixed)
-        f = sc.rhs_buoyancy(T2)
-        torch.cuda.synchronize()
-        tt["setup_s"] = time.perf_counter() - s
-        u, p, rep = sc.solve(f, params=mixed)
-        torch.cuda.synchronize()
-        tt["forward"] = rep
-        lu, lp, rep2 = sc.solve_adjoint(u, None, mixed)
-        torch.cuda.synchronize()
-        tt["adjoint"] = rep2
-        s = time.perf_counter()
-        gm, gT = sc.gradient(u, lu)
-        torch.cuda.synchronize()
-        tt["gradient_s"] = time.perf_counter() - s
-        return u, p, gm, gT, tt
-
-    for i in range(args.warmup):
-        log(f"warmup step {i + 1}/{args.warmup}")
-        step()
-    torch.cuda.synchronize()
-    log(f"timed steps: {args.steps}")
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        u, p, gm, gT, tt = step()
-        log(f"step {i + 1}: forward {tt['forward']['seconds']:.2f}s ({tt['forward']['iterations']} its), "
-            f"adjoint {tt['adjoint']['seconds']:.2f}s ({tt['adjoint']['iterations']} its)")
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t_start) / args.steps
-    fw, ad = tt["forward"], tt["adjoint"]
-    result["step_breakdown"] = {
-        "setup_s": tt["setup_s"], "forward_solve_s": fw["seconds"], "adjoint_solve_s": ad["seconds"],
-        "gradient_s": tt["gradient_s"], "forward_iterations": fw["iterations"],
-        "forward_rel_residual": fw["rel_residual"], "adjoint_iterations": ad["iterations"],
-        "adjoint_rel_residual": ad["rel_residual"],
-        "forward_counts": {k: fw[k] for k in ("a_solves", "a_cg_its", "s_solves", "s_cg_its", "vcycles",
-                                              "coarse_its", "mass_its")},
-        "grad_finite": bool(torch.isfinite(gm).all().item() and torch.isfinite(gT).all().item()),
-    }
-
-    result["a_apply"] = a_apply()
-
-    if not args.no_fp64:
-        log("all-FP64 forward solve")
-        sc.set_log_viscosity(mlog, lnrho, full)
-        f = sc.rhs_buoyancy(T2)
-        u64, p64, r64 = sc.solve(f, params=full)
-        torch.cuda.synchronize()
-        du = (torch.linalg.norm(u - u64) / torch.linalg.norm(u64)).item()
-        dp = (torch.linalg.norm(p - p64) / torch.linalg.norm(p64)).item()
-        result["solve_fp32mg_vs_fp64"] = {
-            "mixed_s": fw["seconds"], "fp64_s": r64["seconds"], "speedup": r64["seconds"] / fw["seconds"],
-            "mixed_iterations": fw["iterations"], "fp64_iterations": r64["iterations"],
-            "mixed_rel_residual": fw["rel_residual"], "fp64_rel_residual": r64["rel_residual"],
-            "u_rel_diff_vs_fp64": du, "p_rel_diff_vs_fp64": dp}
-        log(f"FP64 solve {r64['seconds']:.2f}s ({r64['iterations']} its); mixed {fw['seconds']:.2f}s; "
-            f"|u-u64|/|u64| = {du:.2e}, |p-p64|/|p64| = {dp:.2e}")
-        del u64, p64
-
-    fp32 = result["a_apply"]["fp32"]
-    achieved = A_FLOPS_PER_TET_FP32 * n_tets / (fp32["ms_sweep_kernel"] * 1e-3) / 1e12
-    traffic = read_traffic() if (args.level, args.n_tan, args.n_rad) == (4, 10, 2) else None
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                "kernel": "k_sweep<float, blend, A> (A-apply plane sweep, finest level)",
-                "flops_per_launch": A_FLOPS_PER_TET_FP32 * n_tets,
-                "frac_of_nonpacked_fp32_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                "hbm_gbs_algorithmic": (2 * Nu + Np) * 4 / (fp32["ms_sweep_kernel"] * 1e-3) / 1e9,
-                "hbm_frac_algorithmic": (2 * Nu + Np) * 4 / (fp32["ms_sweep_kernel"] * 1e-3) / 1e9 / PEAK_HBM_GBS}
-
-    cpu = None
-    if not args.no_cpu:
-        log("CPU oracle baseline")
-        cpu = cpu_baseline()
-        log(f"oracle: {cpu['sample']}")
-
-    value = (Nu + Np) / t_step / 1e6
-    line = {
-        "metric": "A-apply GDoF/s + time-to-1e-8 Stokes solve, FP32-MG vs FP64, 1 MI355X",
-        "value": value, "unit": "MDoF/s",
-        "value_definition": "(N_u + N_p) / seconds per step; step = set_log_viscosity + rhs + mixed forward "
-                            "solve to 1e-8 + adjoint solve to 1e-8 + gradient",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": (f"blended spherical shell [0.55,1], icosahedral {args.n_tan}x{args.n_rad} macro mesh "
-                                f"({60 * args.n_tan ** 2 * args.n_rad} macro-tets), level {args.level}, P2-P1, "
-                                "viscosity contrast 1e4, compressible (rho=exp(0.5(1-r))), tol 1e-8"),
-                   "N_u": Nu, "N_p": Np, "micro_tets": n_tets, "parallelism": "single GPU"},
-        "a_apply_gdof_s": {"fp32": fp32["gdof_s"], "fp64": result["a_apply"]["fp64"]["gdof_s"]},
-        "a_apply": result["a_apply"],
-        "solve_fp32mg_vs_fp64": result.get("solve_fp32mg_vs_fp64"),
-        "step_breakdown": result["step_breakdown"],
-        "roofline": roofline,
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
-    }
-    print(json.dumps(line), flush=True)
+        if args.l_eta_study:
+            # Fig. AIterations setting: the first 10 FGMRES iterations of a solve,
+            # A-block CG iterations and their time, per choice of l_eta (-1: P1
+            # viscosity on every level)
+            base = inputs.base_viscosity_profile()
+            f = None
+            study = {}
+            for l_eta in (-1, 0, 1):
+                prm = default_params(precision=32, tol_rel=1e-12, max_outer=10)
+                sc.set_temperature_viscosity(T2, base, l_eta=l_eta, lnrho=lnrho, params=prm)
+                if f is None:
+                    f = sc.rhs_buoyancy(T2)
+                u, p, rep = sc.solve(f, params=prm, allow_noconv=True)
+                torch.cuda.synchronize()
+                study[str(l_eta)] = {k: rep[k] for k in ("iterations", "rel_residual", "a_solves", "a_cg_its",
+                                                        "vcycles", "coarse_its", "seconds")}
+                log(f"l_eta {l_eta}: {rep['iterations']} FGMRES its, rel res {rep['rel_residual']:.2e}, "
+                    f"A-block CG its {rep['a_cg_its']}, {rep['seconds']:.1f}s")
+            print(json.dumps({"l_eta_study": study, "E_A": 4.610, "V_A": 2.996,
+                              "eta_base": "inputs.base_viscosity_profile()", "level": args.level}), flush=True)
+            return
 
 
 if __name__ == "__main__":

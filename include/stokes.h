@@ -109,20 +109,40 @@ typedef struct {
   double history[256];     /* relative residual after each FGMRES iteration */
 } stk_report;
 
-/* Sec. 4.1: build the macro mesh, refine to `level`, number the nodes and
- * upload the tables.  `hip_stream` is a hipStream_t (NULL = default).
- * STK_EINVAL also when the coarsest level (min_level) has more than 262144
- * P2 nodes or 596523 micro-tets: its CG keeps the element matrices. */
+/* Sec. 4.1 (macro mesh of the hollow icosahedron, structured refinement of
+ * every macro-tet into 8^level micro-tets, blending map) and Sec. 5.2.2 (the
+ * multigrid hierarchy min_level .. level): build the macro mesh, refine,
+ * number the nodes and upload the tables.  The context lives on the HIP
+ * device that is current on the calling thread (hipSetDevice before the
+ * call; torch.cuda.device(...) in Python); every later call on the context
+ * must run with that device current.  `hip_stream` is a hipStream_t of that
+ * device (NULL = its default stream).  *out receives a library-owned handle,
+ * released by stk_destroy.  STK_EINVAL (before any device call) for a bad
+ * descriptor, for a mesh whose P2 or P1 node count reaches 2^31 (the kernels
+ * use signed 32-bit node indices), or when the coarsest level has more than
+ * 262144 P2 nodes or 596523 micro-tets (its CG keeps the element matrices);
+ * STK_ENOMEM when device memory runs out. */
 int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out);
+/* Frees every device and host resource of the context after synchronising
+ * its stream; ctx may be NULL. */
 int stk_destroy(stk_ctx* ctx);
+/* The paper's solver parameters (App. "Solver Parameters", table
+ * parametertable) plus the readings noted in stk_solver_params. */
 void stk_default_params(stk_solver_params* p);
+/* Message of the last error on the calling thread (valid until the next call). */
 const char* stk_last_error(void);
 
-/* Node counts of `level` (min_level..level): N_u = 3 n_p2, N_p = n_p1. */
+/* Sec. 4.2 (P2 velocity and P1 pressure on the refined mesh; Sec. 7 counts
+ * the degrees of freedom with the boundary included): node counts of
+ * `level` (min_level..level), N_u = 3 n_p2, N_p = n_p1.  Host outputs,
+ * nullable. */
 int stk_sizes(const stk_ctx* ctx, int level, int64_t* n_p2, int64_t* n_p1);
-/* Host outputs: which = 2 (P2 nodes) or 1 (P1 nodes); xyz: 3*n physical
- * (blended) coordinates, nullable; flags: per node 1 = on r_in / cube
- * boundary, 2 = on r_out, 0 = interior, nullable. */
+/* Sec. 4.1 / 4.2 (the P2 nodes are the vertices and edge midpoints of the
+ * unblended micro-tets, mapped by the blending map; the P1 nodes are the
+ * vertices): node positions in the library's order.  Host outputs, caller
+ * allocated: which = 2 (P2 nodes) or 1 (P1 nodes); xyz: 3*n doubles, node
+ * major, physical (blended) coordinates, nullable; flags: n bytes, per node
+ * 1 = on r_in / cube boundary, 2 = on r_out, 0 = interior, nullable. */
 int stk_coords(const stk_ctx* ctx, int level, int which, double* xyz, uint8_t* flags);
 
 /* Fields on the finest level (device, n_p1 doubles): nodal viscosity eta > 0
@@ -159,27 +179,44 @@ int stk_rhs_buoyancy(stk_ctx* ctx, const double* T_p2, double scale, double* f_u
 int stk_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int bc);
 int stk_apply_B(stk_ctx* ctx, int level, int prec, const void* u, void* q, int with_C, int bc);
 int stk_apply_Bt(stk_ctx* ctx, int level, int prec, const void* p, void* y, int with_Ct, int bc);
-/* Fused K [u; p] = [A u + B^T p; (B + C) u] on the finest level (transpose=1:
- * [A u + (B + C)^T p; B u]); bc as above for the velocity parts. */
+/* Sec. 5.1 (eq. SaddlePointStructure, the block operator [[A, B^T],
+ * [B + C, 0]] FGMRES applies): fused K [u; p] = [A u + B^T p; (B + C) u] on
+ * the finest level (transpose=1: [A u + (B + C)^T p; B u]); bc as above for
+ * the velocity parts; C needs ln rho.  Outputs overwritten. */
 int stk_apply_K(stk_ctx* ctx, int prec, const void* u, const void* p, void* yu, void* yp, int transpose, int bc);
-/* P1 mass with weight 1/eta (Sec. 5.2.3, M_{1/eta}). */
+/* P1 mass with weight 1/eta (Sec. 5.2.3, eq. schurMass, M_{1/eta}; the
+ * consistent mass with 1/eta_h at the quadrature points): q = M p, p and q
+ * n_p1 values of `prec` on `level`; q overwritten. */
 int stk_apply_mass(stk_ctx* ctx, int level, int prec, const void* p, void* q);
-/* diag(A) on `level` without projections (device, 3 n_p2 doubles). */
+/* Sec. 5.2.2 (the Jacobi-Chebyshev smoother uses diag(A)): the diagonal of
+ * A on `level` without projections, device output of 3 n_p2 doubles,
+ * overwritten. */
 int stk_diag_A(stk_ctx* ctx, int level, double* d);
-/* Chebyshev interval [lo, hi] of D^-1 A used on `level` (host outputs); set
- * overrides it. */
+/* Sec. 5.2.2 (Chebyshev smoother of the V-cycle; the paper does not state
+ * how its interval is found): the interval [lo, hi] of D^-1 A used on
+ * `level`, host outputs.  stk_set_fields computes it as [cheb_lo, cheb_hi]
+ * times an FP64 power-iteration estimate of lambda_max(D^-1 A) with the
+ * projections applied; stk_set_cheb_bounds overrides it for later fields. */
 int stk_cheb_bounds(stk_ctx* ctx, int level, double* lo, double* hi);
 int stk_set_cheb_bounds(stk_ctx* ctx, int level, double lo, double hi);
 /* `steps` applications of the degree-`degree` Jacobi-Chebyshev polynomial to
  * A x = b on `level` with projections (Sec. 5.2.2); x updated in place.  b
  * and x are expected admissible (projected); x leaves projected. */
 int stk_smooth(stk_ctx* ctx, int level, int prec, const void* b, void* x, int degree, int steps);
-/* Canonical P2 prolongation from `level`-1 to `level` (ef overwritten) and
- * its transpose (rc overwritten), with projections on the output. */
+/* Sec. 5.1 (projections applied in the multigrid prolongation and
+ * restriction) and Sec. 5.2.2 (geometric multigrid on the nested levels):
+ * the canonical P2 prolongation from `level`-1 to `level` (the coarse
+ * function evaluated at the fine nodes; ec: 3 n_p2(level-1), ef: 3
+ * n_p2(level), overwritten) and its transpose, the restriction (rf: 3
+ * n_p2(level), rc: 3 n_p2(level-1), overwritten), with the projection P_v
+ * on the output.  level > min_level. */
 int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef);
 int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, void* rc);
-/* One V-cycle on the finest level, x = V(b); which = 0: A-block cycle
- * (m_A, deg_A), 1: BFBT cycle Ac (m_V, deg_V). */
+/* Sec. 5.2.2 (Fig. ASolverStructure: V-cycle with Chebyshev pre- and
+ * post-smoothing and a coarse-grid CG) and Sec. 5.2.3 (the cheaper cycle A_C
+ * inside the V-cycle BFBT): one V-cycle on the finest level from a zero
+ * start, x = V(b); which = 0: A-block cycle (m_A, deg_A), 1: BFBT cycle A_C
+ * (m_V, deg_V).  b, x: 3 n_p2 values of `prec`, x overwritten. */
 int stk_vcycle(stk_ctx* ctx, const stk_solver_params* params, int prec, const void* b, void* x, int which);
 
 /* One application of the block preconditioner chosen in params (uzawa,
@@ -196,21 +233,38 @@ int stk_precondition(stk_ctx* ctx, const stk_solver_params* params, const double
  * rep nullable.  Returns STK_ENOCONV with the best iterate if not converged. */
 int stk_solve(stk_ctx* ctx, const stk_solver_params* params, const double* f_u, const double* g_p,
               const double* u_dirichlet, double* u, double* p, stk_report* rep);
-/* Adjoint solve K^T [lu; lp] = [ju; jp] with homogeneous constraints. */
+/* Adjoint of the Stokes solve (the transpose of the system of eq.
+ * SaddlePointStructure, solved by the same FGMRES with the preconditioner of
+ * K^T): K^T [lu; lp] = [ju; jp] with homogeneous constraints; ju (3 n_p2),
+ * jp (n_p1) device doubles in, lu, lp out (overwritten). */
 int stk_solve_adjoint(stk_ctx* ctx, const stk_solver_params* params, const double* ju, const double* jp,
                       double* lu, double* lp, stk_report* rep);
-/* Gradient of J for eta_h = sum exp(m_k) psi_k and f = scale * buoyancy(T):
- * g_m[k] = - lu^T (dA/dm_k) u (n_p1), g_T[i] = lu^T df/dT_i (n_p2); both
- * overwritten, device doubles. */
+/* Gradient of an objective J(u) through the solve, with A of Sec. 5.1 for
+ * the viscosity eta_h = sum_k exp(m_k) psi_k (the P1 interpolant of Sec.
+ * 5.2.2) and the buoyancy right-hand side f = scale * buoyancy(T) of Sec.
+ * 5.1: given the solution u and the adjoint velocity lu (stk_solve_adjoint
+ * with ju = dJ/du), g_m[k] = - lu^T (dA/dm_k) u (n_p1) and g_T[i] = lu^T
+ * df/dT_i (n_p2); both device doubles, overwritten. */
 int stk_gradient(stk_ctx* ctx, const double* u, const double* lu, double scale, double* g_m, double* g_T);
 
-/* Times `reps` back-to-back A-applies of `level` (input and output projected)
- * between HIP events on the context stream: *ms_apply = average time of the
- * whole operator (plane-sweep kernel, gather of shared nodes, projection);
- * *ms_kernel (nullable) = average time of the plane-sweep kernel alone,
- * launched `reps` more times.  y is overwritten. */
+/* Measurement of the A-apply of Sec. 5.1: times `reps` back-to-back
+ * A-applies of `level` (input and output projected) between HIP events on
+ * the context stream: *ms_apply = average time of the whole operator
+ * (plane-sweep kernel, gather of shared nodes, projection); *ms_kernel
+ * (nullable) = average time of the plane-sweep kernel alone, launched `reps`
+ * more times.  y is overwritten. */
 int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int reps, double* ms_apply,
                      double* ms_kernel);
+/* Measurement of the A-apply of Sec. 5.1 inside a caller's own timed loop:
+ * enable = 1 clears the timer and from then on brackets every plane-sweep
+ * kernel of an A-apply on the finest level (stk_apply_A, any precision) with
+ * a pair of HIP events on the context stream; enable = 0 stops, waits for
+ * the recorded events and returns the summed kernel time in *ms_total and
+ * the number of timed launches in *launches (both host, nullable).  At most
+ * 4096 launches are timed per enable (later ones are not recorded).
+ * Element-parallel levels (2^level <= 2) have no sweep kernel and are not
+ * timed. */
+int stk_kernel_timer(stk_ctx* ctx, int enable, double* ms_total, int* launches);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,7 @@ SIGNATURES = {
     "stk_solve_adjoint": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, ctypes.POINTER(Report)],
     "stk_gradient": [_CTX, _P, _P, _D, _P, _P],
     "stk_time_apply_A": [_CTX, _I, _I, _P, _P, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)],
+    "stk_kernel_timer": [_CTX, _I, ctypes.POINTER(_D), ctypes.POINTER(_I)],
 }
 
 _lib = None

@@ -1,6 +1,7 @@
 """Thin Python layer over the C ABI: torch tensors carry device memory and the
 stream; every operation runs in the library's HIP kernels."""
 import ctypes
+import sys
 
 import numpy as np
 import torch
@@ -37,7 +38,12 @@ def _prec(t):
 
 
 class StokesContext:
-    """A mesh hierarchy and its fields on one GPU (see include/stokes.h)."""
+    """A mesh hierarchy and its fields on one GPU (see include/stokes.h).
+
+    Every vector argument is checked here (device, contiguity, dtype and
+    length) before the library sees its pointer, so a wrong tensor raises
+    ValueError instead of reaching a kernel.  Usable as a context manager;
+    close() releases the device memory."""
 
     def __init__(self, kind="shell", level=1, min_level=0, n_tan=1, n_rad=1, r_in=0.55, r_out=1.0,
                  bc_inner=BC_DIRICHLET, bc_outer=BC_FREESLIP, device="cuda:0"):
@@ -56,17 +62,55 @@ class StokesContext:
             check(self.lib.stk_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
         self.params = None
+        self.generation = 0   # counts field changes (set_fields, set_log_viscosity, ...)
 
     def close(self):
         if getattr(self, "h", None):
             self.lib.stk_destroy(self.h)
             self.h = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
+        # during interpreter shutdown the HIP runtime (and a profiler's hooks)
+        # may already be gone: leave the memory to the process exit then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+    # -- argument checks ------------------------------------------------------------
+    def _vec(self, t, n, dtypes=(torch.float64,), name="vector"):
+        """Pointer of a contiguous device tensor with n elements of one of `dtypes`."""
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor")
+        if not t.is_cuda or t.device.index != (self.device.index or 0):
+            raise ValueError(f"{name}: expected a tensor on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor")
+        if t.dtype not in dtypes:
+            raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+        if t.numel() != n:
+            raise ValueError(f"{name}: {t.numel()} elements, expected {n}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _u(self, t, level=None, dtypes=(torch.float64,), name="velocity"):
+        return self._vec(t, 3 * self.sizes(level)[0], dtypes, name)
+
+    def _p(self, t, level=None, dtypes=(torch.float64,), name="pressure"):
+        return self._vec(t, self.sizes(level)[1], dtypes, name)
+
+    def _s2(self, t, level=None, name="P2 scalar"):
+        return self._vec(t, self.sizes(level)[0], (torch.float64,), name)
 
     # -- sizes and node coordinates ------------------------------------------
     def sizes(self, level=None):
@@ -93,55 +137,70 @@ class StokesContext:
 
     # -- fields ------------------------------------------------------------------
     def set_fields(self, eta, lnrho=None, params=None):
+        a, b = self._p(eta, name="eta"), self._p(lnrho, name="lnrho")
         self.params = params or default_params()
-        check(self.lib.stk_set_fields(self.h, _ptr(eta), _ptr(lnrho), ctypes.byref(self.params)))
+        self.generation += 1
+        check(self.lib.stk_set_fields(self.h, a, b, ctypes.byref(self.params)))
 
     def set_log_viscosity(self, m, lnrho=None, params=None):
+        a, b = self._p(m, name="m"), self._p(lnrho, name="lnrho")
         self.params = params or default_params()
-        check(self.lib.stk_set_log_viscosity(self.h, _ptr(m), _ptr(lnrho), ctypes.byref(self.params)))
+        self.generation += 1
+        check(self.lib.stk_set_log_viscosity(self.h, a, b, ctypes.byref(self.params)))
 
     def set_temperature_viscosity(self, T, eta_base, E_A=4.610, V_A=2.996, l_eta=-1, lnrho=None, params=None):
         """eta(x, T) of the geodynamic model from the P2 temperature T (device,
         FP64); quadrature-point evaluation on levels min_level .. l_eta."""
+        a, b = self._s2(T, name="T"), self._p(lnrho, name="lnrho")
         self.params = params or default_params()
         base = np.ascontiguousarray(eta_base, dtype=np.float64)
+        self.generation += 1
         check(self.lib.stk_set_temperature_viscosity(
-            self.h, _ptr(T), _ptr(lnrho), base.ctypes.data_as(ctypes.c_void_p), len(base), float(E_A), float(V_A),
+            self.h, a, b, base.ctypes.data_as(ctypes.c_void_p), len(base), float(E_A), float(V_A),
             int(l_eta), ctypes.byref(self.params)))
 
     def rhs_buoyancy(self, T, scale=1.0, out=None):
         out = self.zeros_u() if out is None else out
-        check(self.lib.stk_rhs_buoyancy(self.h, _ptr(T), float(scale), _ptr(out)))
+        check(self.lib.stk_rhs_buoyancy(self.h, self._s2(T, name="T"), float(scale), self._u(out, name="out")))
         return out
 
     # -- operators -------------------------------------------------------------------
     def apply_A(self, x, level=None, bc=3, out=None):
         level = self.level if level is None else level
         out = torch.empty_like(x) if out is None else out
-        check(self.lib.stk_apply_A(self.h, level, _prec(x), _ptr(x), _ptr(out), bc))
+        fl = (x.dtype,)
+        a = self._u(x, level, (torch.float64, torch.float32), "x")
+        check(self.lib.stk_apply_A(self.h, level, _prec(x), a, self._u(out, level, fl, "out"), bc))
         return out
 
     def apply_B(self, u, level=None, with_C=False, bc=1, out=None):
         level = self.level if level is None else level
         out = self.zeros_p(level, u.dtype) if out is None else out
-        check(self.lib.stk_apply_B(self.h, level, _prec(u), _ptr(u), _ptr(out), int(with_C), bc))
+        a = self._u(u, level, (torch.float64, torch.float32), "u")
+        b = self._p(out, level, (u.dtype,), "out")
+        check(self.lib.stk_apply_B(self.h, level, _prec(u), a, b, int(with_C), bc))
         return out
 
     def apply_Bt(self, p, level=None, with_Ct=False, bc=2, out=None):
         level = self.level if level is None else level
         out = self.zeros_u(level, p.dtype) if out is None else out
-        check(self.lib.stk_apply_Bt(self.h, level, _prec(p), _ptr(p), _ptr(out), int(with_Ct), bc))
+        a = self._p(p, level, (torch.float64, torch.float32), "p")
+        b = self._u(out, level, (p.dtype,), "out")
+        check(self.lib.stk_apply_Bt(self.h, level, _prec(p), a, b, int(with_Ct), bc))
         return out
 
     def apply_K(self, u, p, transpose=False, bc=3):
+        a = self._u(u, None, (torch.float64, torch.float32), "u")
+        b = self._p(p, None, (u.dtype,), "p")
         yu, yp = torch.empty_like(u), torch.empty_like(p)
-        check(self.lib.stk_apply_K(self.h, _prec(u), _ptr(u), _ptr(p), _ptr(yu), _ptr(yp), int(transpose), bc))
+        check(self.lib.stk_apply_K(self.h, _prec(u), a, b, _ptr(yu), _ptr(yp), int(transpose), bc))
         return yu, yp
 
     def apply_mass(self, p, level=None):
         level = self.level if level is None else level
+        a = self._p(p, level, (torch.float64, torch.float32), "p")
         out = torch.empty_like(p)
-        check(self.lib.stk_apply_mass(self.h, level, _prec(p), _ptr(p), _ptr(out)))
+        check(self.lib.stk_apply_mass(self.h, level, _prec(p), a, _ptr(out)))
         return out
 
     def diag_A(self, level=None):
@@ -161,32 +220,38 @@ class StokesContext:
 
     def smooth(self, b, x, level=None, degree=2, steps=3):
         level = self.level if level is None else level
-        check(self.lib.stk_smooth(self.h, level, _prec(b), _ptr(b), _ptr(x), degree, steps))
+        pb = self._u(b, level, (torch.float64, torch.float32), "b")
+        px = self._u(x, level, (b.dtype,), "x")
+        check(self.lib.stk_smooth(self.h, level, _prec(b), pb, px, degree, steps))
         return x
 
     def prolong(self, ec, level):
+        a = self._u(ec, level - 1, (torch.float64, torch.float32), "ec")
         out = self.zeros_u(level, ec.dtype)
-        check(self.lib.stk_prolong(self.h, level, _prec(ec), _ptr(ec), _ptr(out)))
+        check(self.lib.stk_prolong(self.h, level, _prec(ec), a, _ptr(out)))
         return out
 
     def restrict(self, rf, level):
+        a = self._u(rf, level, (torch.float64, torch.float32), "rf")
         out = self.zeros_u(level - 1, rf.dtype)
-        check(self.lib.stk_restrict(self.h, level, _prec(rf), _ptr(rf), _ptr(out)))
+        check(self.lib.stk_restrict(self.h, level, _prec(rf), a, _ptr(out)))
         return out
 
     def vcycle(self, b, params=None, which=0):
         params = params or self.params or default_params()
+        a = self._u(b, None, (torch.float64, torch.float32), "b")
         x = torch.empty_like(b)
-        check(self.lib.stk_vcycle(self.h, ctypes.byref(params), _prec(b), _ptr(b), _ptr(x), which))
+        check(self.lib.stk_vcycle(self.h, ctypes.byref(params), _prec(b), a, _ptr(x), which))
         return x
 
     # -- solves ------------------------------------------------------------------------
     def solve(self, f, g=None, u_dirichlet=None, params=None, allow_noconv=False):
         params = params or self.params or default_params()
+        pf, pg = self._u(f, name="f"), self._p(g, name="g")
+        pd = self._u(u_dirichlet, name="u_dirichlet")
         u, p = self.zeros_u(), self.zeros_p()
         rep = Report()
-        rc = self.lib.stk_solve(self.h, ctypes.byref(params), _ptr(f), _ptr(g), _ptr(u_dirichlet), _ptr(u),
-                                _ptr(p), ctypes.byref(rep))
+        rc = self.lib.stk_solve(self.h, ctypes.byref(params), pf, pg, pd, _ptr(u), _ptr(p), ctypes.byref(rep))
         if not (allow_noconv and rc == _lib.STK_ENOCONV):
             check(rc)
         return u, p, rep.as_dict()
@@ -194,29 +259,38 @@ class StokesContext:
     def precondition(self, ru, rp, params=None, transpose=False):
         """One application of the block preconditioner to the residual [ru; rp]."""
         params = params or self.params or default_params()
+        a, b = self._u(ru, name="ru"), self._p(rp, name="rp")
         zu, zp = self.zeros_u(), self.zeros_p()
-        check(self.lib.stk_precondition(self.h, ctypes.byref(params), _ptr(ru), _ptr(rp), _ptr(zu), _ptr(zp),
-                                        int(transpose)))
+        check(self.lib.stk_precondition(self.h, ctypes.byref(params), a, b, _ptr(zu), _ptr(zp), int(transpose)))
         return zu, zp
 
     def solve_adjoint(self, ju, jp=None, params=None):
         params = params or self.params or default_params()
         jp = self.zeros_p() if jp is None else jp
+        a, b = self._u(ju, name="ju"), self._p(jp, name="jp")
         lu, lp = self.zeros_u(), self.zeros_p()
         rep = Report()
-        check(self.lib.stk_solve_adjoint(self.h, ctypes.byref(params), _ptr(ju), _ptr(jp), _ptr(lu), _ptr(lp),
-                                         ctypes.byref(rep)))
+        check(self.lib.stk_solve_adjoint(self.h, ctypes.byref(params), a, b, _ptr(lu), _ptr(lp), ctypes.byref(rep)))
         return lu, lp, rep.as_dict()
 
     def gradient(self, u, lu, scale=1.0):
+        a, b = self._u(u, name="u"), self._u(lu, name="lu")
         gm, gT = self.zeros_p(), torch.zeros(self.sizes()[0], dtype=torch.float64, device=self.device)
-        check(self.lib.stk_gradient(self.h, _ptr(u), _ptr(lu), float(scale), _ptr(gm), _ptr(gT)))
+        check(self.lib.stk_gradient(self.h, a, b, float(scale), _ptr(gm), _ptr(gT)))
         return gm, gT
 
     def time_apply_A(self, x, y, reps=20, level=None):
         """(ms per A-apply operator, ms per plane-sweep kernel launch)."""
         level = self.level if level is None else level
+        a = self._u(x, level, (torch.float64, torch.float32), "x")
+        b = self._u(y, level, (x.dtype,), "y")
         ms, mk = ctypes.c_double(), ctypes.c_double()
-        check(self.lib.stk_time_apply_A(self.h, level, _prec(x), _ptr(x), _ptr(y), reps, ctypes.byref(ms),
-                                        ctypes.byref(mk)))
+        check(self.lib.stk_time_apply_A(self.h, level, _prec(x), a, b, reps, ctypes.byref(ms), ctypes.byref(mk)))
         return ms.value, mk.value
+
+    def kernel_timer(self, enable):
+        """enable=True: start bracketing every finest-level A sweep kernel with
+        HIP events; enable=False: stop and return (summed ms, launches)."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        check(self.lib.stk_kernel_timer(self.h, int(bool(enable)), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

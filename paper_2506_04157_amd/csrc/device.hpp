@@ -112,9 +112,12 @@ struct BcDev {
 // Fused plane-sweep apply; sl2 / sl1 are the slot buffers of the level
 // (3 * nmacro * nsh2 and nmacro * nsh1 values).  Outputs are fully written
 // (no zero fill needed); bcmode & BCM_OUT projects the velocity output.
+// ev0 / ev1 (nullable): events recorded on s right before and after the
+// plane-sweep kernel (not around the gather and projection).
 template <typename R>
 void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, const R* p, const R* eta,
-                   const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s);
+                   const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // LDS layout of the sweep kernel (byte offsets, 16-byte aligned):
 //   sy   [3 cap2][3] double  P2 accumulators             (velocity output)
 //   syp  [2 cap1]    double  P1 accumulators             (pressure-type output)

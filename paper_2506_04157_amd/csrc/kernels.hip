@@ -2305,7 +2305,9 @@ static void stokes_dispatch(const LevelDev& L, const R* u, const R* p, const R* 
 
 template <typename R>
 void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, const R* p, const R* eta,
-                   const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s) {
+                   const R* lnrho, R* yu, R* yp, R* sl2, R* sl1, int bcmode, hipStream_t s, hipEvent_t ev0,
+                   hipEvent_t ev1) {
+  if (ev0) (void)hipEventRecord(ev0, s);
   switch (flags) {
 #define CASE(F) case F: stokes_dispatch<R, F>(L, u, p, eta, lnrho, yu, yp, sl2, sl1, bcmode, s); break;
     CASE(F_A)
@@ -2321,6 +2323,7 @@ void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, co
 #undef CASE
     default: return;
   }
+  if (ev1) (void)hipEventRecord(ev1, s);
   const bool OU = flags & (F_A | F_BT | F_CT), OP = flags & (F_B | F_C | F_M);
   if (OU && L.g2.nnodes > 0 && !L.elemwise)
     hipLaunchKernelGGL((k_gather<R, 3>), dim3((L.g2.nnodes + 255) / 256), dim3(256), 0, s, L.g2, sl2,
@@ -2331,9 +2334,11 @@ void launch_stokes(int flags, const LevelDev& L, const BcDev& bc, const R* u, co
   if (OU && (bcmode & BCM_OUT)) launch_project<R>(bc, L.n2, yu, s);
 }
 template void launch_stokes<double>(int, const LevelDev&, const BcDev&, const double*, const double*, const double*,
-                                    const double*, double*, double*, double*, double*, int, hipStream_t);
+                                    const double*, double*, double*, double*, double*, int, hipStream_t, hipEvent_t,
+                                    hipEvent_t);
 template void launch_stokes<float>(int, const LevelDev&, const BcDev&, const float*, const float*, const float*,
-                                   const float*, float*, float*, float*, float*, int, hipStream_t);
+                                   const float*, float*, float*, float*, float*, int, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 
 template <typename R>
 void launch_diag(const LevelDev& L, const R* eta, R* d, hipStream_t s) {

@@ -312,7 +312,7 @@ Level build_level(const MacroMesh& mm, const Topology& top, int L) {
     const int64_t edgeBase = faceBase + (int64_t)top.faces.size() * fi;
     const int64_t vertBase = edgeBase + (int64_t)top.edges.size() * ei;
     const int64_t total = vertBase + mm.nv();
-    if (total >= (int64_t)UINT32_MAX) throw std::runtime_error("node count exceeds 32-bit indices");
+    if (total >= (int64_t)INT32_MAX) throw std::runtime_error("node count exceeds signed 32-bit indices");
     const int64_t nloc = tet_count(m);
     std::vector<uint32_t>& l2g = pass == 0 ? lv.l2g2 : lv.l2g1;
     l2g.resize((size_t)nm * nloc);

@@ -211,6 +211,10 @@ struct stk_ctx {
   stk_report* rep = nullptr;
   // FGMRES storage
   DBuf<double> fg;
+  // stk_kernel_timer: event pairs around the finest-level A sweeps
+  bool timer_on = false;
+  int timer_n = 0;
+  std::vector<hipEvent_t> timer_ev;
   bool verbose = std::getenv("STK_VERBOSE") != nullptr;   // progress lines on stderr
   int L() const { return desc.level; }
   int lmin() const { return desc.min_level; }
@@ -274,9 +278,23 @@ void sweep(Ctx& c, int l, int flags, const R* u, const R* p, const R* eta, const
   LevelData& L = c.at(l);
   launch_stokes<R>(flags, L.d, L.bc, u, p, eta, rho, yu, yp, L.sl2<R>(), L.sl1<R>(), bc, c.s);
 }
+constexpr int TIMER_MAX = 4096;
 template <class R>
 void applyA(Ctx& c, int l, const R* x, R* y, int bc) {
-  sweep<R>(c, l, F_A, x, nullptr, c.at(l).etap<R>(), nullptr, y, nullptr, bc);
+  LevelData& L = c.at(l);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.timer_on && l == c.L() && !L.d.elemwise && c.timer_n < TIMER_MAX) {
+    while ((int)c.timer_ev.size() < 2 * (c.timer_n + 1)) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      c.timer_ev.push_back(e);
+    }
+    e0 = c.timer_ev[2 * c.timer_n];
+    e1 = c.timer_ev[2 * c.timer_n + 1];
+    ++c.timer_n;
+  }
+  launch_stokes<R>(F_A, L.d, L.bc, x, nullptr, L.etap<R>(), nullptr, y, nullptr, L.sl2<R>(), L.sl1<R>(), bc, c.s,
+                   e0, e1);
 }
 template <class R>
 void applyB(Ctx& c, int l, const R* u, R* q, bool withC, int bc) {
@@ -1188,6 +1206,23 @@ void set_temperature_viscosity_internal(Ctx& c, const double* T2, const double* 
   set_fields_internal(c, F.eta.p, lnrho, par);
 }
 
+// Node counts of the finest level in closed form (Sec. 4.1: N = n_tan 2^L
+// points per icosahedron edge and M = n_rad 2^L radial intervals give
+// (10 (2N)^2 + 2)(2M + 1) P2 and (10 N^2 + 2)(M + 1) P1 nodes on the shell;
+// the cube has (2^{L+1} + 1)^3 and (2^L + 1)^3), computed in long double so
+// that no descriptor overflows them.
+void closed_form_counts(const stk_mesh_desc& d, long double& n2, long double& n1) {
+  const long double s = std::ldexp(1.0L, d.level);
+  if (d.kind == STK_MESH_CUBE) {
+    n2 = std::pow(2.0L * s + 1.0L, 3);
+    n1 = std::pow(s + 1.0L, 3);
+  } else {
+    const long double N = (long double)d.n_tan * s, M = (long double)d.n_rad * s;
+    n2 = (10.0L * 4.0L * N * N + 2.0L) * (2.0L * M + 1.0L);
+    n1 = (10.0L * N * N + 2.0L) * (M + 1.0L);
+  }
+}
+
 void need_ready(Ctx* c) {
   REQUIRE(c, "null context");
   if (!c->ready) throw StkError(STK_ENOTREADY, "stk_set_fields has not been called");
@@ -1243,6 +1278,15 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
       REQUIRE(desc->n_tan >= 1 && desc->n_rad >= 1, "n_tan and n_rad must be >= 1");
       REQUIRE(desc->r_in > 0 && desc->r_out > desc->r_in, "need 0 < r_in < r_out");
     }
+    {
+      // the kernels index nodes with signed 32-bit integers (shared nodes of
+      // a macro are encoded as negative slot numbers), so both node counts
+      // must stay below 2^31
+      long double n2, n1;
+      closed_form_counts(*desc, n2, n1);
+      REQUIRE(n2 < 2147483648.0L && n1 < 2147483648.0L,
+              "mesh too large: the P2 and P1 node counts must be below 2^31");
+    }
     std::unique_ptr<stk_ctx> c(new stk_ctx());
     c->desc = *desc;
     c->s = (hipStream_t)hip_stream;
@@ -1281,6 +1325,7 @@ int stk_destroy(stk_ctx* ctx) {
   return guard([&] {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->s);
+    for (hipEvent_t e : ctx->timer_ev) (void)hipEventDestroy(e);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     if (ctx->hcg) (void)hipHostFree(ctx->hcg);
     for (int k = 0; k < 2; ++k)
@@ -1630,6 +1675,33 @@ int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, 
     (void)hipEventDestroy(e2);
     *ms_apply = a / reps;
     if (ms_kernel) *ms_kernel = b / reps;
+  });
+}
+
+int stk_kernel_timer(stk_ctx* ctx, int enable, double* ms_total, int* launches) {
+  return guard([&] {
+    REQUIRE(ctx, "null context");
+    if (enable) {
+      while (ctx->timer_ev.size() < 128) {   // 64 pairs up front; more are made on demand
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ctx->timer_ev.push_back(e);
+      }
+      ctx->timer_on = true;
+      ctx->timer_n = 0;
+      return;
+    }
+    ctx->timer_on = false;
+    double tot = 0;
+    for (int i = 0; i < ctx->timer_n; ++i) {
+      HIPCHK(hipEventSynchronize(ctx->timer_ev[2 * i + 1]));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->timer_ev[2 * i], ctx->timer_ev[2 * i + 1]));
+      tot += ms;
+    }
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = ctx->timer_n;
+    ctx->timer_n = 0;
   });
 }
 

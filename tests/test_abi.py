@@ -46,3 +46,24 @@ def test_host_only_entry_points():
     d = _lib.MeshDesc(kind=0, level=1, min_level=0, bc_inner=2)
     assert lib.stk_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.STK_EINVAL
     assert lib.stk_create(None, None, ctypes.byref(h)) == _lib.STK_EINVAL
+
+
+def test_node_count_limit_refused_before_device_work():
+    """The kernels index nodes with signed 32-bit integers: meshes with 2^31
+    or more P2 (or P1) nodes are refused from the closed-form counts before
+    any device call (a 15x4 shell at level 5 has 2.37e9 P2 nodes; the 10x2
+    shell at level 5, 5.28e8, is below the limit and is not refused for its
+    size)."""
+    from oracle.mesh import shell_counts
+    from paper_2506_04157_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libstokes.so not built")
+    lib = _lib.load()
+    assert shell_counts(15, 4, 5)[0] >= 2 ** 31 > shell_counts(10, 2, 5)[0]
+    h = ctypes.c_void_p()
+    d = _lib.MeshDesc(kind=1, n_tan=15, n_rad=4, r_in=0.55, r_out=1.0, level=5, min_level=0, bc_inner=1, bc_outer=2)
+    assert lib.stk_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.STK_EINVAL
+    assert b"2^31" in lib.stk_last_error()
+    d = _lib.MeshDesc(kind=1, n_tan=1000, n_rad=1000, r_in=0.55, r_out=1.0, level=7, min_level=0, bc_inner=1,
+                      bc_outer=2)
+    assert lib.stk_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.STK_EINVAL

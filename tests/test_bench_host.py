@@ -30,7 +30,7 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_figure_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     f = tmp_path / "traffic.txt"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {64: str(f), 32: str(tmp_path / "none.txt")})
     assert bench.read_traffic() is None                      # absent
     f.write_text(f"# comment: 1\nkernel_source_sha256_16: {bench.kernel_sha()}\n"
                  "hbm_bytes_per_launch: 1234.0\n")
@@ -108,3 +108,16 @@ def test_summarize_profile_groups_the_roofline_kernel_by_grid(tmp_path):
     assert "total kernel time 0.000 s over 2 kernels" in text
     assert "grid       6144:      2 launches, average        3.0 us" in text
     assert "grid       1536:      1 launches, average        3.0 us" in text
+
+
+def test_roofline_fields():
+    """The roofline object: algorithmic flops of the launch over its time
+    against the FP64 (or FP32) peak, algorithmic bytes over HBM."""
+    r = bench._roofline(64, 1000, 300, 20, 2.0, None)
+    flops = bench.A_FLOPS_PER_TET * 1000
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP64_TFLOPS
+    assert r["achieved"] == pytest.approx(flops / 2e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 78.6)
+    assert r["hbm_gbs_algorithmic"] == pytest.approx((2 * 300 + 20) * 8 / 2e-3 / 1e9)
+    r32 = bench._roofline(32, 1000, 300, 20, 2.0, 4960.0)
+    assert r32["peak"] == bench.PEAK_FP32_TFLOPS and r32["traffic_over_algorithmic"] == pytest.approx(2.0)
