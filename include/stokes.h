@@ -205,13 +205,18 @@ int stk_set_cheb_bounds(stk_ctx* ctx, int level, double lo, double hi);
 int stk_smooth(stk_ctx* ctx, int level, int prec, const void* b, void* x, int degree, int steps);
 /* Sec. 5.1 (projections applied in the multigrid prolongation and
  * restriction) and Sec. 5.2.2 (geometric multigrid on the nested levels):
- * the canonical P2 prolongation from `level`-1 to `level` (the coarse
- * function evaluated at the fine nodes; ec: 3 n_p2(level-1), ef: 3
- * n_p2(level), overwritten) and its transpose, the restriction (rf: 3
- * n_p2(level), rc: 3 n_p2(level-1), overwritten), with the projection P_v
- * on the output.  level > min_level. */
-int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef);
-int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, void* rc);
+ * the canonical P2 prolongation P from `level`-1 to `level` (the coarse
+ * function evaluated at the fine nodes) and its transpose, the restriction,
+ * on vectors of `prec`; level > min_level.
+ * stk_prolong: ec holds 3 n_p2(level-1) values, ef 3 n_p2(level);
+ *   add = 0: ef = P_v P ec (overwritten); add = 1: ef += P_v P ec (the
+ *   V-cycle's coarse-grid correction).
+ * stk_restrict: rf and tf (nullable) hold 3 n_p2(level) values, rc
+ *   3 n_p2(level-1) (overwritten); tf = NULL: rc = P_v P^T rf; otherwise
+ *   rc = P_v P^T P_v (rf - tf) (the V-cycle's restriction of the residual
+ *   b - A x with t = A x). */
+int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef, int add);
+int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, const void* tf, void* rc);
 /* Sec. 5.2.2 (Fig. ASolverStructure: V-cycle with Chebyshev pre- and
  * post-smoothing and a coarse-grid CG) and Sec. 5.2.3 (the cheaper cycle A_C
  * inside the V-cycle BFBT): one V-cycle on the finest level from a zero

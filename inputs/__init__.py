@@ -145,3 +145,28 @@ def base_viscosity_profile(n=65, r_in=R_IN, r_out=R_OUT):
     knots = np.array([r_in, 0.85, 0.88, 0.95, 0.97, r_out])
     log10 = np.array([1.5, 1.0, -1.0, -1.0, 2.0, 2.0])
     return 10.0 ** np.interp(r, knots, log10)
+
+
+def splitmix64(state, n):
+    """The first n 64-bit outputs of the splitmix64 generator (Steele, Lea and
+    Flood, OOPSLA 2014) started from `state`: the state advances by the
+    golden-ratio increment 0x9E3779B97F4A7C15 and each output is the state
+    passed through the generator's two xor-shift-multiply rounds and a final
+    xor-shift."""
+    M = (1 << 64) - 1
+    out = []
+    st = state & M
+    for _ in range(n):
+        st = (st + 0x9E3779B97F4A7C15) & M
+        z = st
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def splitmix64_uniform(state, n):
+    """n values uniform in [-1, 1) from splitmix64: the top 53 bits of each
+    output give the double.  Tests use it to reproduce a start vector the
+    library draws with the same published generator."""
+    return np.array([(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0 for z in splitmix64(state, n)])

@@ -69,8 +69,8 @@ SIGNATURES = {
     "stk_cheb_bounds": [_CTX, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "stk_set_cheb_bounds": [_CTX, _I, _D, _D],
     "stk_smooth": [_CTX, _I, _I, _P, _P, _I, _I],
-    "stk_prolong": [_CTX, _I, _I, _P, _P],
-    "stk_restrict": [_CTX, _I, _I, _P, _P],
+    "stk_prolong": [_CTX, _I, _I, _P, _P, _I],
+    "stk_restrict": [_CTX, _I, _I, _P, _P, _P],
     "stk_vcycle": [_CTX, ctypes.POINTER(SolverParams), _I, _P, _P, _I],
     "stk_precondition": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, _I],
     "stk_solve": [_CTX, ctypes.POINTER(SolverParams), _P, _P, _P, _P, _P, ctypes.POINTER(Report)],

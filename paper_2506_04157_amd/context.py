@@ -225,16 +225,24 @@ class StokesContext:
         check(self.lib.stk_smooth(self.h, level, _prec(b), pb, px, degree, steps))
         return x
 
-    def prolong(self, ec, level):
+    def prolong(self, ec, level, add_to=None):
+        """P_v P ec on `level`; add_to: a fine vector that receives += P_v P ec
+        in place (and is returned)."""
         a = self._u(ec, level - 1, (torch.float64, torch.float32), "ec")
-        out = self.zeros_u(level, ec.dtype)
-        check(self.lib.stk_prolong(self.h, level, _prec(ec), a, _ptr(out)))
+        if add_to is None:
+            out = self.zeros_u(level, ec.dtype)
+        else:
+            out = add_to
+        b = self._u(out, level, (ec.dtype,), "add_to")
+        check(self.lib.stk_prolong(self.h, level, _prec(ec), a, b, int(add_to is not None)))
         return out
 
-    def restrict(self, rf, level):
+    def restrict(self, rf, level, minus=None):
+        """P_v P^T rf, or P_v P^T P_v (rf - minus) with a fine vector `minus`."""
         a = self._u(rf, level, (torch.float64, torch.float32), "rf")
+        t = self._u(minus, level, (rf.dtype,), "minus")
         out = self.zeros_u(level - 1, rf.dtype)
-        check(self.lib.stk_restrict(self.h, level, _prec(rf), a, _ptr(out)))
+        check(self.lib.stk_restrict(self.h, level, _prec(rf), a, t, _ptr(out)))
         return out
 
     def vcycle(self, b, params=None, which=0):

@@ -1494,29 +1494,44 @@ int stk_smooth(stk_ctx* ctx, int level, int prec, const void* b, void* x, int de
   });
 }
 
-int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef) {
+int stk_prolong(stk_ctx* ctx, int level, int prec, const void* ec, void* ef, int add) {
   return guard([&] {
     REQUIRE(ctx && ec && ef, "null argument");
     check_level(ctx, level);
     REQUIRE(level > ctx->lmin(), "prolongation needs level > min_level");
+    REQUIRE(add == 0 || add == 1, "add must be 0 or 1");
     LevelData &C = ctx->at(level - 1), &F = ctx->at(level);
-    PREC_DISPATCH(prec, launch_prolong<double>(C.d, F.d, (const double*)ec, (double*)ef, BCM_OUT, ctx->s),
-                  launch_prolong<float>(C.d, F.d, (const float*)ec, (float*)ef, BCM_OUT, ctx->s));
+    if (add)
+      PREC_DISPATCH(prec, launch_prolong_add<double>(C.d, F.d, (const double*)ec, (double*)ef, BCM_OUT, ctx->s),
+                    launch_prolong_add<float>(C.d, F.d, (const float*)ec, (float*)ef, BCM_OUT, ctx->s));
+    else
+      PREC_DISPATCH(prec, launch_prolong<double>(C.d, F.d, (const double*)ec, (double*)ef, BCM_OUT, ctx->s),
+                    launch_prolong<float>(C.d, F.d, (const float*)ec, (float*)ef, BCM_OUT, ctx->s));
     HIPCHK(hipGetLastError());
   });
 }
 
-int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, void* rc) {
+int stk_restrict(stk_ctx* ctx, int level, int prec, const void* rf, const void* tf, void* rc) {
   return guard([&] {
     REQUIRE(ctx && rf && rc, "null argument");
     check_level(ctx, level);
     REQUIRE(level > ctx->lmin(), "restriction needs level > min_level");
     LevelData &C = ctx->at(level - 1), &F = ctx->at(level);
-    PREC_DISPATCH(prec,
-                  (vfill<double>((double*)rc, 0.0, 3 * C.h.n2, ctx->s),
-                   launch_restrict<double>(C.d, F.d, (const double*)rf, (double*)rc, BCM_OUT, ctx->s)),
-                  (vfill<float>((float*)rc, 0.f, 3 * C.h.n2, ctx->s),
-                   launch_restrict<float>(C.d, F.d, (const float*)rf, (float*)rc, BCM_OUT, ctx->s)));
+    const long long nc = 3 * C.h.n2;
+    if (tf)
+      PREC_DISPATCH(prec,
+                    (vfill<double>((double*)rc, 0.0, nc, ctx->s),
+                     launch_restrict_diff<double>(C.d, F.d, (const double*)rf, (const double*)tf, (double*)rc,
+                                                  BCM_IN | BCM_OUT, ctx->s)),
+                    (vfill<float>((float*)rc, 0.f, nc, ctx->s),
+                     launch_restrict_diff<float>(C.d, F.d, (const float*)rf, (const float*)tf, (float*)rc,
+                                                 BCM_IN | BCM_OUT, ctx->s)));
+    else
+      PREC_DISPATCH(prec,
+                    (vfill<double>((double*)rc, 0.0, nc, ctx->s),
+                     launch_restrict<double>(C.d, F.d, (const double*)rf, (double*)rc, BCM_OUT, ctx->s)),
+                    (vfill<float>((float*)rc, 0.f, nc, ctx->s),
+                     launch_restrict<float>(C.d, F.d, (const float*)rf, (float*)rc, BCM_OUT, ctx->s)));
     HIPCHK(hipGetLastError());
   });
 }

@@ -78,3 +78,10 @@ class Pair:
 
 def relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def rowerr(y, ref, scale):
+    """Largest per-entry error relative to the entry's own scale (for an
+    operator row: sum_j |a_ij x_j|), so that one wrong node cannot hide in a
+    norm over all nodes."""
+    return float(np.max(np.abs(y - ref) / np.maximum(scale, 1e-300)))

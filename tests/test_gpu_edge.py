@@ -100,8 +100,8 @@ def test_binding_refuses_wrong_tensors_before_the_library():
                                 torch.zeros(3 * n2, dtype=torch.float32, device=dev)),
             lambda: sc.apply_A(torch.zeros(3 * n2, dtype=torch.float16, device=dev)),
             lambda: sc.apply_A(torch.zeros(3 * n2 + 1, dtype=torch.float64, device=dev)),
-            lambda: sc.apply_A(torch.zeros(3 * n2, device=dev), out=torch.zeros(3 * n2, dtype=torch.float32,
-                                                                                 device=dev)),
+            lambda: sc.apply_A(torch.zeros(3 * n2, dtype=torch.float64, device=dev),
+                               out=torch.zeros(3 * n2, dtype=torch.float32, device=dev)),           # mixed dtypes
             lambda: sc.apply_B(torch.zeros(3 * n2, dtype=torch.float64, device=dev),
                                out=torch.zeros(n1 - 1, dtype=torch.float64, device=dev)),
             lambda: sc.apply_Bt(torch.zeros(n1, dtype=torch.float64, device=dev)[::2]),       # not contiguous

@@ -2,18 +2,26 @@
 macro-tets, level 4, N_u = 2.0e8) in the launch configuration the benchmark
 times, on sampled outputs the oracle can compute on its own: the rows of A and
 B at the nodes inside one macro-tet depend only on that macro's micro-tets, so
-a one-macro oracle mesh reproduces them exactly.  Inputs are smooth functions
-of the node coordinates, evaluated by each side at its own nodes.  Also the
-symmetry of the projected A at full size.
+a one-macro oracle mesh reproduces them exactly.  The same holds for the fused
+K and K^T rows, B^T + C^T, the prolongation at macro-interior fine nodes and
+the restriction at macro-interior coarse nodes (a coarse P2 basis function
+vanishes on every face that does not hold its node), and for one Chebyshev
+step at nodes at least three micro-tet layers inside the macro (the step
+reaches two layers).  Inputs are smooth functions of the node coordinates,
+evaluated by each side at its own nodes.  Errors are per entry, against the
+entry's own scale.  Also the symmetry of the projected A at full size.
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import torch
 from scipy.spatial import cKDTree
 
 import inputs
 from oracle.fem import assemble_A, assemble_B
 from oracle.mesh import MacroMesh, RefinedMesh, shell_macros
+from oracle.solvers import chebyshev, prolongation, vector_prolongation
+from tests._util import rowerr
 
 pytestmark = pytest.mark.gpu
 
@@ -31,16 +39,16 @@ def full():
     sc = StokesContext("shell", level=L, min_level=0, n_tan=NT, n_rad=NR)
     X2, _ = sc.coords(which=2)
     X1, _ = sc.coords(which=1)
-    sc.set_fields(torch.tensor(_eta(X1), device="cuda"))
+    sc.set_fields(torch.tensor(_eta(X1), device="cuda"), torch.tensor(inputs.ln_density(X1), device="cuda"))
     yield sc, X2, X1
     sc.close()
 
 
-def _one_macro(mac_id):
+def _one_macro(mac_id, level=L):
     mm = shell_macros(NT, NR, 0.55, 1.0)
     t = mm.tets[mac_id]
     one = MacroMesh("shell", mm.vertices[t], [[0, 1, 2, 3]], mm.layer[t], 0.55, 1.0, NR)
-    return RefinedMesh(one, L)
+    return RefinedMesh(one, level)
 
 
 def _block_match(Xg, n_block, Xo):
@@ -92,3 +100,111 @@ def test_projected_A_is_symmetric_at_full_size(full):
     xAy = torch.dot(x, sc.apply_A(y, bc=3)).item()
     yAx = torch.dot(y, sc.apply_A(x, bc=3)).item()
     assert abs(xAy - yAx) <= 1e-12 * abs(xAy)
+
+
+def _interior(m, margin=1):
+    """Masks of the P2 and P1 nodes whose barycentric lattice weights are all
+    >= margin (P2 lattice units for the P2 nodes, P1 units for the P1 nodes)."""
+    return (m.keys2[:, 4:] >= margin).all(axis=1), (m.keys1[:, 4:] >= margin).all(axis=1)
+
+
+def _scalar(seed, X):
+    return inputs.smooth_vector_field(seed, X)[:, 0].copy()
+
+
+@pytest.mark.parametrize("mac_id", [0, 11999])
+def test_sampled_rows_of_K_Kt_and_BtCt(full, mac_id):
+    """Fused K = [[A, B^T], [B + C, 0]] and K^T (FP64; no projection) and
+    B^T + C^T (FP64 and FP32) at the macro-interior rows."""
+    sc, X2, X1 = full
+    m = _one_macro(mac_id)
+    in2, in1 = _interior(m)
+    g2 = _block_match(X2, int(in2.sum()), m.X2[in2])
+    g1 = _block_match(X1, int(in1.sum()), m.X1[in1])
+    u_or = inputs.smooth_vector_field(7, m.X2).T.ravel()
+    p_or = _scalar(8, m.X1)
+    A = assemble_A(m, _eta(m.X1))
+    B = assemble_B(m)
+    C = assemble_B(m, inputs.ln_density(m.X1), only_C=True)
+    aA, aB, aC = abs(A), abs(B), abs(C)
+    au, ap = abs(u_or), abs(p_or)
+    N2 = len(X2)
+    u = torch.tensor(inputs.smooth_vector_field(7, X2).T.ravel(), device="cuda")
+    p = torch.tensor(_scalar(8, X1), device="cuda")
+    sel = lambda v: v.reshape(3, -1)[:, in2]
+    for transpose in (False, True):
+        yu, yp = sc.apply_K(u, p, transpose=transpose, bc=0)
+        yu = yu.cpu().numpy().reshape(3, N2)[:, g2]
+        yp = yp.cpu().numpy()[g1]
+        if transpose:
+            ru, rp = A @ u_or + (B + C).T @ p_or, B @ u_or
+            su, sp_ = aA @ au + (aB + aC).T @ ap, aB @ au
+        else:
+            ru, rp = A @ u_or + B.T @ p_or, (B + C) @ u_or
+            su, sp_ = aA @ au + aB.T @ ap, (aB + aC) @ au
+        eu, ep = rowerr(yu, sel(ru), sel(su)), rowerr(yp, rp[in1], sp_[in1])
+        print(mac_id, "K^T" if transpose else "K", eu, ep)
+        assert eu <= 1e-13 and ep <= 1e-13
+    ref, scale = sel((B + C).T @ p_or), sel((aB + aC).T @ ap)
+    for dtype, tol in [(torch.float64, 1e-13), (torch.float32, 1e-5)]:
+        y = sc.apply_Bt(p.to(dtype), with_Ct=True, bc=0).double().cpu().numpy().reshape(3, N2)[:, g2]
+        e = rowerr(y, ref, scale)
+        print(mac_id, "Bt+Ct", dtype, e)
+        assert e <= tol
+
+
+@pytest.mark.parametrize("mac_id", [0, 11999])
+def test_sampled_fp32_transfers_at_full_size(full, mac_id):
+    """The V-cycle's FP32 transfers between levels 3 and 4: x += P_v P e_c at
+    macro-interior fine nodes and P_v P^T P_v (b - t) at macro-interior coarse
+    nodes, against the one-macro prolongation matrix."""
+    sc, X2, X1 = full
+    X2c, _ = sc.coords(L - 1, 2)
+    mf, mc = _one_macro(mac_id), _one_macro(mac_id, L - 1)
+    Pro = vector_prolongation(prolongation(mc, mf))
+    inf, _ = _interior(mf)
+    inc, _ = _interior(mc)
+    gf = _block_match(X2, int(inf.sum()), mf.X2[inf])
+    gc = _block_match(X2c, int(inc.sum()), mc.X2[inc])
+    f32 = lambda seed, X: torch.tensor(inputs.smooth_vector_field(seed, X).T.ravel(), dtype=torch.float32,
+                                       device="cuda")
+    orv = lambda seed, X: inputs.smooth_vector_field(seed, X).T.ravel()
+    # prolongation with accumulation
+    xs = sc.prolong(f32(9, X2c), L, add_to=f32(10, X2)).double().cpu().numpy().reshape(3, -1)[:, gf]
+    ec, x0 = orv(9, mc.X2), orv(10, mf.X2)
+    ref = (x0 + Pro @ ec).reshape(3, -1)[:, inf]
+    scale = (abs(x0) + abs(Pro) @ abs(ec)).reshape(3, -1)[:, inf]
+    e = rowerr(xs, ref, scale)
+    print(mac_id, "prolong-add", e)
+    assert e <= 2e-6
+    # restriction of a difference
+    rc = sc.restrict(f32(11, X2), L, minus=f32(12, X2)).double().cpu().numpy().reshape(3, -1)[:, gc]
+    rf, tf = orv(11, mf.X2), orv(12, mf.X2)
+    ref = (Pro.T @ (rf - tf)).reshape(3, -1)[:, inc]
+    scale = (abs(Pro).T @ (abs(rf) + abs(tf))).reshape(3, -1)[:, inc]
+    e = rowerr(rc, ref, scale)
+    print(mac_id, "restrict-diff", e)
+    assert e <= 2e-6
+
+
+@pytest.mark.parametrize("mac_id", [5432])
+def test_sampled_fp32_chebyshev_step_at_full_size(full, mac_id):
+    """One FP32 Chebyshev step of degree 2 on level 4 with the context's own
+    interval, at nodes at least three micro-tet layers inside one macro,
+    against the oracle's smoother on the one-macro matrix."""
+    sc, X2, X1 = full
+    lo, hi = sc.cheb_bounds(L)
+    m = _one_macro(mac_id)
+    deep, _ = _interior(m, margin=6)
+    g2 = _block_match(X2, int((m.keys2[:, 4:] > 0).all(axis=1).sum()), m.X2[deep])
+    b = torch.tensor(inputs.smooth_vector_field(13, X2).T.ravel(), dtype=torch.float32, device="cuda")
+    x = torch.tensor(inputs.smooth_vector_field(14, X2).T.ravel(), dtype=torch.float32, device="cuda")
+    sc.smooth(b, x, level=L, degree=2, steps=1)
+    xg = x.double().cpu().numpy().reshape(3, -1)[:, g2]
+    A = assemble_A(m, _eta(m.X1))
+    I = sp.identity(A.shape[0], format="csr")
+    ref = chebyshev(A, 1.0 / A.diagonal(), I, inputs.smooth_vector_field(13, m.X2).T.ravel(),
+                    inputs.smooth_vector_field(14, m.X2).T.ravel(), lo, hi, 2, 1).reshape(3, -1)[:, deep]
+    e = np.abs(xg - ref).max() / np.abs(ref).max()
+    print(mac_id, "chebyshev", int(deep.sum()), "nodes", e)
+    assert e <= 1e-5

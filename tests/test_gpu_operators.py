@@ -1,6 +1,8 @@
 """GPU parity of the operator applies against the assembled FP64 oracle.
 
-Bars: FP64 applies 1e-12 relative (Euclidean norm), FP32 applies 1e-5.
+Bars: FP64 applies 1e-12 relative (Euclidean norm), FP32 applies 1e-5; and
+per entry, against the entry's scale sum_j |a_ij x_j| (so that a single wrong
+node cannot hide in the norm): 1e-13 for FP64, 1e-5 for FP32.
 """
 import numpy as np
 import pytest
@@ -8,7 +10,7 @@ import torch
 
 import inputs
 from oracle.fem import assemble_A, assemble_B, assemble_M_inv_eta, rhs_buoyancy
-from tests._util import Pair, relerr
+from tests._util import Pair, relerr, rowerr
 
 pytestmark = pytest.mark.gpu
 
@@ -35,13 +37,20 @@ def case(request):
     return dict(P=P, m=m, eta=eta, A=A, B=B, C=C, M=M, Pu=Pu, x=x, p=p)
 
 
+ROW_TOL = {torch.float64: 1e-13, torch.float32: 1e-5}
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 @pytest.mark.parametrize("bc", [0, 3])
 def test_apply_A(case, dtype, tol, bc):
     P, A, Pu, x = case["P"], case["A"], case["Pu"], case["x"]
     y = P.u_to_or(P.ctx.apply_A(P.u_to_lib(x, dtype=dtype), bc=bc))
-    ref = A @ x if bc == 0 else Pu @ (A @ (Pu @ x))
+    if bc == 0:
+        ref, scale = A @ x, abs(A) @ abs(x)
+    else:
+        ref, scale = Pu @ (A @ (Pu @ x)), abs(Pu) @ (abs(A) @ (abs(Pu) @ abs(x)))
     assert relerr(y, ref) < tol
+    assert rowerr(y, ref, scale) < ROW_TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
@@ -49,14 +58,16 @@ def test_apply_A(case, dtype, tol, bc):
 def test_apply_B_and_Bt(case, dtype, tol, with_C):
     P, B, C, Pu, x, p = case["P"], case["B"], case["C"], case["Pu"], case["x"], case["p"]
     Bb = B + C if with_C else B
+    aB = abs(B) + abs(C) if with_C else abs(B)
+    rt = ROW_TOL[dtype]
     q = P.p_to_or(P.ctx.apply_B(P.u_to_lib(x, dtype=dtype), with_C=with_C, bc=0))
-    assert relerr(q, Bb @ x) < tol
+    assert relerr(q, Bb @ x) < tol and rowerr(q, Bb @ x, aB @ abs(x)) < rt
     q = P.p_to_or(P.ctx.apply_B(P.u_to_lib(x, dtype=dtype), with_C=with_C, bc=1))
-    assert relerr(q, Bb @ (Pu @ x)) < tol
+    assert relerr(q, Bb @ (Pu @ x)) < tol and rowerr(q, Bb @ (Pu @ x), aB @ (abs(Pu) @ abs(x))) < rt
     y = P.u_to_or(P.ctx.apply_Bt(P.p_to_lib(p, dtype=dtype), with_Ct=with_C, bc=0))
-    assert relerr(y, Bb.T @ p) < tol
+    assert relerr(y, Bb.T @ p) < tol and rowerr(y, Bb.T @ p, aB.T @ abs(p)) < rt
     y = P.u_to_or(P.ctx.apply_Bt(P.p_to_lib(p, dtype=dtype), with_Ct=with_C, bc=2))
-    assert relerr(y, Pu @ (Bb.T @ p)) < tol
+    assert relerr(y, Pu @ (Bb.T @ p)) < tol and rowerr(y, Pu @ (Bb.T @ p), abs(Pu) @ (aB.T @ abs(p))) < rt
 
 
 @pytest.mark.parametrize("transpose", [False, True])
@@ -76,7 +87,7 @@ def test_mass_and_diag(case):
     P, M, A, p = case["P"], case["M"], case["A"], case["p"]
     for dtype, tol in [(torch.float64, 1e-12), (torch.float32, 1e-5)]:
         q = P.p_to_or(P.ctx.apply_mass(P.p_to_lib(p, dtype=dtype)))
-        assert relerr(q, M @ p) < tol
+        assert relerr(q, M @ p) < tol and rowerr(q, M @ p, abs(M) @ abs(p)) < ROW_TOL[dtype]
     d = P.u_to_or(P.ctx.diag_A())
     assert relerr(d, A.diagonal()) < 1e-12
 

@@ -35,6 +35,13 @@ def test_prolongation_and_restriction(kind, L, lmin):
             rf = inputs.uniform(8, 3 * mf.n2)
             rc = P.u_to_or(P.ctx.restrict(P.u_to_lib(rf, l, dtype), l), l - 1)
             assert relerr(rc, Pc @ (Pro.T @ rf)) < tol
+            # the V-cycle's fused forms: x += P_v P e_c and P_v P^T P_v (b - t)
+            x0 = inputs.uniform(9, 3 * mf.n2)
+            xs = P.ctx.prolong(P.u_to_lib(ec, l - 1, dtype), l, add_to=P.u_to_lib(x0, l, dtype))
+            assert relerr(P.u_to_or(xs, l), x0 + Pf @ (Pro @ ec)) < tol
+            tf = inputs.uniform(10, 3 * mf.n2)
+            rd = P.ctx.restrict(P.u_to_lib(rf, l, dtype), l, minus=P.u_to_lib(tf, l, dtype))
+            assert relerr(P.u_to_or(rd, l - 1), Pc @ (Pro.T @ (Pf @ (rf - tf)))) < tol
 
 
 def _oracle_levels(P, eta_fine, bounds):
@@ -68,6 +75,45 @@ def _power_bounds(levels, lmin):
             x /= lam
         b[lmin + i] = (0.12 * lam, 1.2 * lam)
     return b
+
+
+def test_spectral_bound_matches_power_iteration_and_covers_the_spectrum():
+    """lambda-hat of every level: the library's FP64 power iteration on
+    P D^-1 P A P (D = diag(A), no projection) from its splitmix64 start vector
+    (Sec. 5.2.2: the Chebyshev smoother's interval; the method is the reading
+    of the build).  The oracle repeats the same iteration on its assembled A
+    from the same start vector (drawn here with the same published
+    generator, in the library's node order) and must agree to 1e-10; and the
+    interval's top 1.2 lambda-hat must lie above the largest eigenvalue of
+    D^-1 A on range(P), computed by ARPACK."""
+    print("\n[lambda-hat shell L2]", flush=True)
+    P = Pair("shell", 2, min_level=0)
+    m = P.meshes[2]
+    eta = _eta(m)
+    params = default_params(power_its=15)
+    P.ctx.set_fields(P.p_to_lib(eta), params=params)
+    levels = _oracle_levels(P, eta, {})
+    for l in (1, 2):
+        d = levels[l]
+        lo, hi = P.ctx.cheb_bounds(l)
+        lam_gpu = hi / params.cheb_hi
+        assert abs(lo / params.cheb_lo - lam_gpu) <= 1e-14 * lam_gpu
+        n = d["A"].shape[0]
+        x0 = inputs.splitmix64_uniform(0x9E3779B97F4A7C15 ^ l, n)        # library order
+        x = d["P"] @ P.u_to_or(torch.tensor(x0), l)
+        x /= np.linalg.norm(x)
+        for _ in range(params.power_its):
+            x = d["P"] @ (d["Dinv"] * (d["P"] @ (d["A"] @ (d["P"] @ x))))
+            lam = np.linalg.norm(x)
+            x /= lam
+        print(l, lam_gpu, lam, abs(lam_gpu - lam) / lam)
+        assert abs(lam_gpu - lam) <= 1e-10 * lam
+        op = spla.LinearOperator((n, n), dtype=np.float64,
+                                 matvec=lambda v: d["P"] @ (d["Dinv"] * (d["P"] @ (d["A"] @ (d["P"] @ v)))))
+        lmax = float(np.max(np.real(spla.eigs(op, k=1, which="LR", tol=1e-10,
+                                              v0=np.ones(n), return_eigenvectors=False))))
+        print("  lambda_max", lmax, "lambda-hat / lambda_max", lam_gpu / lmax)
+        assert hi >= lmax and lam_gpu <= 1.2 * lmax
 
 
 @pytest.mark.parametrize("kind,L,lmin", [("cube", 3, 1), ("shell", 2, 0)])
@@ -242,52 +288,65 @@ def test_adjoint_solve_and_gradient():
 
 @pytest.mark.parametrize("precision", [64, 32])
 def test_autograd_matches_central_differences(precision):
-    """dJ/dm and dJ/dT of J = 1/2 |u - u_obs|^2 within 1e-6 (relative, over
-    the vector of seeded directional derivatives) of central differences
-    with h = 1e-6."""
-    from paper_2506_04157_amd import StokesSolve
-    print(f"\n[autograd prec {precision}]", flush=True)
-    P = Pair("shell", 2, min_level=0)
-    m = P.meshes[2]
-    field = inputs.SHField(2)
-    m0 = np.log(inputs.viscosity_contrast(field.temperature(m.X1), 1e4))
-    T0 = field.temperature(m.X2)
-    uobs = P.u_to_lib(0.01 * inputs.uniform(5, 3 * m.n2))
-    params = default_params(tol_rel=1e-13, precision=precision, max_outer=400)
+    """The adjoint gradient against central differences, direction by
+    direction: J = 1/2 |u - u_obs|^2 with u_obs the solution for the
+    log-viscosity m + 0.1 zeta (zeta a seeded smooth field, seed 5), on the
+    240-macro shell (n_t = 2, n_r = 1) at level 3, viscosity contrast 1e4,
+    C = 0.  For 20 seeded directions (seed 4) of m and 20 of T,
+    |fd - g.d| <= 1e-6 |fd| with h = 1e-6.
 
-    def J(mv, Tv, grad=False):
-        mt = P.p_to_lib(mv).requires_grad_(grad)
-        Tt = P.s2_to_lib(Tv).requires_grad_(grad)
-        u, p = StokesSolve.apply(mt, Tt, P.ctx, params)
-        j = 0.5 * ((u - uobs) ** 2).sum()
-        if grad:
-            j.backward()
-            return j.item(), P.p_to_or(mt.grad), P.s2_to_or(Tt.grad)
-        return u.detach()
-
-    def central(up, um):
-        # J(+) - J(-) = (u+ - u-) . ((u+ + u-)/2 - u_obs): the same central
-        # difference without the cancellation of two nearly equal J values
-        return ((up - um) * (0.5 * (up + um) - uobs)).sum().item() / (2 * h)
-
-    j0, gm, gT = J(m0, T0, grad=True)
+    The perturbed solutions are u0 + du, where du solves K(m +- h d) du =
+    b(T +- h dT) - K(m +- h d) [u0; p0] from the base solution [u0; p0]: the
+    correction is O(h), so a relative tolerance on its own solve bounds the
+    error of u+ - u- relative to h |du/dm d|, not to |u|; central differences
+    of two solves each converged relative to |f| would carry the solver's
+    error divided by h."""
+    from paper_2506_04157_amd import StokesContext, StokesSolve
+    print(f"\n[autograd FD prec {precision}]", flush=True)
     h = 1e-6
-    fdm, adm, fdT, adT = [], [], [], []
-    for k in range(3):
-        dmv = inputs.normal(40 + k, m.n1)
-        dT = inputs.normal(50 + k, m.n2)
-        fdm.append(central(J(m0 + h * dmv, T0), J(m0 - h * dmv, T0)))
-        fdT.append(central(J(m0, T0 + h * dT), J(m0, T0 - h * dT)))
-        adm.append(gm @ dmv)
-        adT.append(gT @ dT)
-        print(k, fdm[-1], adm[-1], fdT[-1], adT[-1])
-    # the directional derivatives over all seeded directions, compared as a
-    # vector: the differences of the perturbed solves carry the solver's
-    # residual tolerance divided by h, which dominates single directions
-    # whose derivative happens to be small
-    fdm, adm, fdT, adT = map(np.asarray, (fdm, adm, fdT, adT))
-    assert np.linalg.norm(fdm - adm) <= 1e-6 * np.linalg.norm(fdm)
-    assert np.linalg.norm(fdT - adT) <= 1e-6 * np.linalg.norm(fdT)
+    with StokesContext("shell", level=3, min_level=0, n_tan=2, n_rad=1) as sc:
+        n2, n1 = sc.sizes()
+        X2, _ = sc.coords(which=2)
+        X1, _ = sc.coords(which=1)
+        field = inputs.SHField(2)
+        m0 = np.log(inputs.viscosity_contrast(field.temperature(X1), 1e4))
+        T0 = field.temperature(X2)
+        zeta = 2.0 * inputs.SHField(5).temperature(X1) - 1.0
+        dev = lambda v: torch.tensor(v, dtype=torch.float64, device="cuda")
+        p_obs = default_params(tol_rel=1e-13, precision=64, max_outer=400)
+        sc.set_log_viscosity(dev(m0 + 0.1 * zeta), params=p_obs)
+        uobs, _, _ = sc.solve(sc.rhs_buoyancy(dev(T0)), params=p_obs)
+        params = default_params(tol_rel=1e-13, precision=precision, max_outer=400)
+        mt, Tt = dev(m0).requires_grad_(True), dev(T0).requires_grad_(True)
+        u, p = StokesSolve.apply(mt, Tt, sc, params)
+        (0.5 * ((u - uobs) ** 2).sum()).backward()
+        gm, gT = mt.grad.cpu().numpy(), Tt.grad.cpu().numpy()
+        u0, p0 = u.detach(), p.detach()
+        corr = default_params(tol_rel=1e-12, precision=precision, max_outer=400)
+
+        def perturbed(mv, Tv):
+            sc.set_log_viscosity(dev(mv), params=corr)
+            yu, yp = sc.apply_K(u0, p0, bc=3)
+            du, _, rep = sc.solve(sc.rhs_buoyancy(dev(Tv)) - yu, g=-yp, params=corr)
+            assert rep["rel_residual"] <= 1e-12
+            return du
+
+        def central(dp, dm_):
+            # (J+ - J-)/(2h) = (u+ - u-) . ((u+ + u-)/2 - u_obs) / (2h), u+- = u0 + du+-
+            return ((dp - dm_) * (u0 + 0.5 * (dp + dm_) - uobs)).sum().item() / (2 * h)
+
+        worst = 0.0
+        for k in range(20):
+            dmv = inputs.normal([4, k], n1)
+            dTv = inputs.normal([4, 100 + k], n2)
+            fdm = central(perturbed(m0 + h * dmv, T0), perturbed(m0 - h * dmv, T0))
+            fdT = central(perturbed(m0, T0 + h * dTv), perturbed(m0, T0 - h * dTv))
+            em, eT = abs(fdm - gm @ dmv) / abs(fdm), abs(fdT - gT @ dTv) / abs(fdT)
+            worst = max(worst, em, eT)
+            print(k, f"m: fd {fdm:.10e} g.d {gm @ dmv:.10e} rel {em:.2e} | "
+                     f"T: fd {fdT:.10e} g.d {gT @ dTv:.10e} rel {eT:.2e}", flush=True)
+            assert em <= 1e-6 and eT <= 1e-6, k
+        print("largest relative difference", worst)
 
 
 def test_coarsest_level_size_limit():

@@ -36,3 +36,13 @@ def test_base_viscosity_profile_is_positive_and_layered():
     r = np.linspace(inputs.R_IN, inputs.R_OUT, 65)
     assert (b > 0).all() and b.max() / b.min() > 1e2
     assert b[r >= 0.97].min() > b[(r > 0.88) & (r < 0.95)].max()         # stiff lithosphere over a weak layer
+
+
+def test_splitmix64_matches_its_published_outputs():
+    """The generator's widely reproduced reference sequence for the start
+    state 1234567, and the mapping of the top 53 bits to [-1, 1)."""
+    assert inputs.splitmix64(1234567, 5) == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                                             4593380528125082431, 16408922859458223821]
+    u = inputs.splitmix64_uniform(1234567, 5)
+    assert np.allclose(u, [(z >> 11) / 2.0 ** 52 - 1.0 for z in inputs.splitmix64(1234567, 5)], rtol=0, atol=0)
+    assert (u >= -1).all() and (u < 1).all()
