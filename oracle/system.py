@@ -18,6 +18,15 @@ computed here as the solution of a square nonsingular system:
     [ Q^T A Q   Q^T B^T  0 ] [u~]   [ Q^T (f - A u_D) ]
     [ Bbar Q    0        1 ] [p ] = [ g - Bbar u_D    ]
     [ 0         1^T      0 ] [mu]   [ 0               ]
+
+* with free slip on both spheres (the boundary conditions of Sec. 2 with
+  the surface condition also of free-slip type) the rigid rotations
+  e_k x X are admissible and strain free, so the problem does not determine
+  them (on the blended mesh A annihilates them only up to the discretisation
+  error).  They are removed as the pressure constant is: the nodal velocity
+  is Euclidean-orthogonal to the three rotation vectors R (R^T u = 0), and
+  three more multipliers nu absorb the rotational part of the momentum
+  residual (columns Q^T R in the first block row, rows R^T Q below).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -70,11 +79,26 @@ def projector(mesh, dirichlet_flags, freeslip_flags):
     return Q @ Q.T
 
 
-def solve_stokes(A, Bbar, f, g, Q, u_D=None, Bt=None):
+def rigid_rotations(mesh):
+    """The rigid rotations e_k x X at the P2 nodes, k = 0, 1, 2, as the
+    columns of a (3 n2, 3) array in the component-major velocity layout."""
+    X = mesh.X2
+    R = np.zeros((3 * mesh.n2, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        R[:, k] = np.cross(e, X).T.ravel()
+    return R
+
+
+def solve_stokes(A, Bbar, f, g, Q, u_D=None, Bt=None, rotations=None):
     """Direct solve of the constrained system; returns (u, p, mu).
 
     Bt (optional) is the matrix of the gradient block; by default Bbar^T is
     not used: the gradient block is B^T with B = Bbar - C supplied by caller.
+    rotations (optional, (3 n2, k)): velocity modes the solution is made
+    Euclidean-orthogonal to, each with a multiplier (the rigid rotations
+    under free slip on both spheres).
     """
     n1 = Bbar.shape[0]
     if u_D is None:
@@ -97,12 +121,32 @@ def solve_stokes(A, Bbar, f, g, Q, u_D=None, Bt=None):
     b = np.concatenate([Q.T @ (f - A @ u_D), g - Bbar @ u_D])
     e = np.zeros(nu + n1)
     e[k] = 1.0
-    c = np.concatenate([np.zeros(nu), np.ones(n1)])
-    yb, ye, yc = lu.solve(b), lu.solve(e), lu.solve(c)
-    # x = yb + t ye - mu yc with  c^T x = 0  and  e^T x = t
-    M2 = np.array([[c @ ye, -(c @ yc)], [e @ ye - 1.0, -(e @ yc)]])
-    t, mu = np.linalg.solve(M2, -np.array([c @ yb, e @ yb]))
-    sol = yb + t * ye - mu * yc
+    # border columns: the pressure mean (c), then the constrained velocity modes
+    W = [np.concatenate([np.zeros(nu), np.ones(n1)])]
+    if rotations is not None:
+        QR = Q.T @ rotations
+        W += [np.concatenate([QR[:, j], np.zeros(n1)]) for j in range(QR.shape[1])]
+    W = np.array(W).T                                   # (nu + n1, nw)
+    ye = lu.solve(e)
+    YW = np.column_stack([lu.solve(W[:, j]) for j in range(W.shape[1])])
+    # (K0 + e e^T) x - t e + W lam = rm with t = e^T x and W^T x = rb:
+    # x = yb + t ye - YW lam; unknowns z = (t, lam)
+    cols = np.column_stack([ye, -YW])
+    rows = np.vstack([W.T, e])
+    Mz = rows @ cols
+    Mz[-1, 0] -= 1.0
+
+    def bordered(rm, rb):
+        yb = lu.solve(rm)
+        z = np.linalg.solve(Mz, np.concatenate([rb, [0.0]]) - rows @ yb)
+        return yb + cols @ z, z
+
+    sol, z = bordered(b, np.zeros(W.shape[1]))
+    # one step of iterative refinement on K0 x + W lam = b, W^T x = 0: the
+    # factorised matrix is nearly singular when rotations are constrained
+    dx, dz = bordered(b - (K0 @ sol + W @ z[1:]), -(W.T @ sol))
+    sol, z = sol + dx, z + dz
+    mu = z[1]
     u = Q @ sol[:nu] + u_D
     p = sol[nu:nu + n1]
     return u, p, mu

@@ -272,13 +272,15 @@ class StokesContext:
         check(self.lib.stk_precondition(self.h, ctypes.byref(params), a, b, _ptr(zu), _ptr(zp), int(transpose)))
         return zu, zp
 
-    def solve_adjoint(self, ju, jp=None, params=None):
+    def solve_adjoint(self, ju, jp=None, params=None, allow_noconv=False):
         params = params or self.params or default_params()
         jp = self.zeros_p() if jp is None else jp
         a, b = self._u(ju, name="ju"), self._p(jp, name="jp")
         lu, lp = self.zeros_u(), self.zeros_p()
         rep = Report()
-        check(self.lib.stk_solve_adjoint(self.h, ctypes.byref(params), a, b, _ptr(lu), _ptr(lp), ctypes.byref(rep)))
+        rc = self.lib.stk_solve_adjoint(self.h, ctypes.byref(params), a, b, _ptr(lu), _ptr(lp), ctypes.byref(rep))
+        if not (allow_noconv and rc == _lib.STK_ENOCONV):
+            check(rc)
         return lu, lp, rep.as_dict()
 
     def gradient(self, u, lu, scale=1.0):

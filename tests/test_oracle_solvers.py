@@ -7,7 +7,7 @@ from oracle.fem import assemble_A, assemble_B
 from oracle.mesh import RefinedMesh, cube_macros, shell_macros
 from oracle.solvers import (adjoint_uzawa, inexact_uzawa, bfbt, chebyshev, chebyshev_error_polynomial, fgmres, pcg,
                             prolongation, symmetric_uzawa, vcycle, vector_prolongation)
-from oracle.system import solve_stokes, velocity_basis
+from oracle.system import rigid_rotations, solve_stokes, velocity_basis
 
 
 def test_chebyshev_matches_closed_form_error_polynomial():
@@ -188,3 +188,57 @@ def test_direct_solve_satisfies_constraints_free_slip():
     rp = (B + C) @ u
     assert np.linalg.norm(ru) < 1e-10 * np.linalg.norm(f)
     assert np.linalg.norm(rp - rp.mean()) < 1e-10 * np.linalg.norm(f)
+
+
+def _free_slip_both(level=2):
+    m = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), level)
+    rng = np.random.default_rng(8)
+    A = assemble_A(m, np.exp(rng.uniform(-2, 2, m.n1)))
+    B = assemble_B(m)
+    C = assemble_B(m, 0.5 * (1 - np.linalg.norm(m.X1, axis=1)), only_C=True)
+    Q, dm, fs = velocity_basis(m, set(), {1, 2})
+    return m, A, B, C, Q, fs, rigid_rotations(m)
+
+
+def test_rigid_rotations_are_admissible_and_near_null_under_free_slip_on_both_spheres():
+    """The rotations e_k x X are tangential at every sphere node (so P_v leaves
+    them unchanged), and Q^T A Q has exactly three eigenvalues far below the
+    rest: the blended A annihilates the rotations only up to the
+    discretisation error, so without a constraint the solution's rotational
+    part is set by that error."""
+    m, A, B, C, Q, fs, R = _free_slip_both()
+    Pm = Q @ Q.T
+    assert np.abs(Pm @ R - R).max() < 1e-13 * np.abs(R).max()
+    QAQ = (Q.T @ A @ Q).tocsc()
+    small = np.sort(spla.eigsh(QAQ, k=5, sigma=-1e-9, which="LM", return_eigenvectors=False))
+    big = spla.eigsh(QAQ, k=1, which="LA", return_eigenvectors=False)[0]
+    assert small[2] < 1e-5 * big and small[3] > 30 * small[2]
+
+
+def test_direct_solve_free_slip_on_both_spheres_removes_rotations():
+    """The constrained solve: u tangential on both spheres, R^T u = 0, the
+    momentum residual in span(R) (its projection vanishes), the continuity
+    residual constant; and a body force that is itself a rigid rotation drives
+    no flow, while a solve without the constraint does pick up a rotation."""
+    m, A, B, C, Q, fs, R = _free_slip_both()
+    Bb = B + C
+    f = np.random.default_rng(9).standard_normal(3 * m.n2)
+    u, p, mu = solve_stokes(A, Bb, f, np.zeros(m.n1), Q, Bt=B.T, rotations=R)
+    U = u.reshape(3, -1).T
+    n = m.X2[fs] / np.linalg.norm(m.X2[fs], axis=1, keepdims=True)
+    assert np.abs(np.einsum("kd,kd->k", U[fs], n)).max() < 1e-13 * np.abs(U).max()
+    assert np.abs(R.T @ u).max() < 1e-11 * np.linalg.norm(R, axis=0).max() * np.linalg.norm(u)
+    Qr, _ = np.linalg.qr(Q.T @ R)
+    ru = Q.T @ (f - A @ u - B.T @ p)
+    ru -= Qr @ (Qr.T @ ru)
+    rp = Bb @ u
+    assert np.linalg.norm(ru) < 1e-10 * np.linalg.norm(f)
+    assert np.linalg.norm(rp - rp.mean()) < 1e-10 * np.linalg.norm(f)
+    assert abs(p.mean()) < 1e-13 * np.abs(p).max()
+    # a rigid-rotation body force
+    u0, p0, _ = solve_stokes(A, Bb, R @ np.array([0.3, -1.2, 0.7]), np.zeros(m.n1), Q, Bt=B.T, rotations=R)
+    assert np.abs(u0).max() < 1e-10 and np.abs(p0).max() < 1e-10
+    # without the constraint the same forcing spins the shell
+    u1, _, _ = solve_stokes(A, Bb, f, np.zeros(m.n1), Q, Bt=B.T)
+    rot = np.linalg.lstsq(R, u1, rcond=None)[0]
+    assert np.linalg.norm(R @ rot) > 10 * np.linalg.norm(u)
