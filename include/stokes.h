@@ -184,6 +184,20 @@ int stk_apply_Bt(stk_ctx* ctx, int level, int prec, const void* p, void* y, int 
  * the finest level (transpose=1: [A u + (B + C)^T p; B u]); bc as above for
  * the velocity parts; C needs ln rho.  Outputs overwritten. */
 int stk_apply_K(stk_ctx* ctx, int prec, const void* u, const void* p, void* yu, void* yp, int transpose, int bc);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * A-apply of stk_apply_A with the same arguments and result, which allocates
+ * nothing.  The sweep's shared-node slots (3 nmacro nsh2 + nmacro nsh1 values
+ * of `prec` on `level`, nsh the shared nodes of one macro) live in a fixed
+ * device array of STK_NOALLOC_SCRATCH_BYTES that every GPU the library runs
+ * on holds until the process ends; a level whose slots need more is refused
+ * with STK_EINVAL before any launch.  All calls on one GPU share that array:
+ * calls that overlap on one GPU (other streams, threads or contexts) race and
+ * give wrong results.  Every call rewrites all the slots it reads, so nothing
+ * has to be cleared between calls.  The array's address is looked up once
+ * per device by stk_create. */
+#define STK_NOALLOC_SCRATCH_BYTES (128u << 20)
+int stk_apply_A_noalloc(stk_ctx* ctx, int level, int prec, const void* x, void* y, int bc);
 /* P1 mass with weight 1/eta (Sec. 5.2.3, eq. schurMass, M_{1/eta}; the
  * consistent mass with 1/eta_h at the quadrature points): q = M p, p and q
  * n_p1 values of `prec` on `level`; q overwritten. */

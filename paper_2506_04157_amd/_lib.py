@@ -64,6 +64,7 @@ SIGNATURES = {
     "stk_apply_B": [_CTX, _I, _I, _P, _P, _I, _I],
     "stk_apply_Bt": [_CTX, _I, _I, _P, _P, _I, _I],
     "stk_apply_K": [_CTX, _I, _P, _P, _P, _P, _I, _I],
+    "stk_apply_A_noalloc": [_CTX, _I, _I, _P, _P, _I],
     "stk_apply_mass": [_CTX, _I, _I, _P, _P],
     "stk_diag_A": [_CTX, _I, _P],
     "stk_cheb_bounds": [_CTX, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)],

@@ -173,6 +173,15 @@ class StokesContext:
         check(self.lib.stk_apply_A(self.h, level, _prec(x), a, self._u(out, level, fl, "out"), bc))
         return out
 
+    def apply_A_noalloc(self, x, out, level=None, bc=3):
+        """A-apply through the entry point that allocates no device memory
+        (its scratch is a fixed per-GPU array); `out` is caller-provided."""
+        level = self.level if level is None else level
+        a = self._u(x, level, (torch.float64, torch.float32), "x")
+        b = self._u(out, level, (x.dtype,), "out")
+        check(self.lib.stk_apply_A_noalloc(self.h, level, _prec(x), a, b, bc))
+        return out
+
     def apply_B(self, u, level=None, with_C=False, bc=1, out=None):
         level = self.level if level is None else level
         out = self.zeros_p(level, u.dtype) if out is None else out

@@ -224,6 +224,15 @@ template <typename R> void vdot(const R* x, const R* y, long long n, double* par
 template <typename R>
 void vaxpy2_nrm(R a, const R* p, R* x, R b, const R* q, R* r, long long n, double* partial, double* out, hipStream_t s);
 void vsum_partials(double* partial, int np, double* out, hipStream_t s);
+
+// Fixed device array (per GPU) holding the shared-node slots of the
+// allocation-free A-apply; its size in bytes equals STK_NOALLOC_SCRATCH_BYTES.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+// Looks up the array's address on `device` (which must be current) once and
+// keeps it; call at context creation.
+hipError_t noalloc_scratch_init(int device);
+// The array's address on `device`, or nullptr before noalloc_scratch_init.
+void* noalloc_scratch(int device);
 constexpr int DOT_BLOCKS = 1024;
 // device-resident Jacobi CG pieces (scalars in sc[], partial sums in part[],
 // 5 * DOT_BLOCKS doubles; iteration i uses parity i & 1: see kernels.hip)

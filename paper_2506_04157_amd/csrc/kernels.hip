@@ -23,6 +23,8 @@
 // accumulates with LDS atomics; the flush stores nodes that only this
 // workgroup touches and atomically adds the rest (brick faces and macro
 // interfaces) into a zero-filled output.
+#include <mutex>
+
 #include "device.hpp"
 
 namespace stk {
@@ -2508,5 +2510,36 @@ template void vconvert<double, float>(const double*, float*, long long, hipStrea
 INST_CG(double)
 INST_CG(float)
 template void vconvert<float, double>(const float*, double*, long long, hipStream_t);
+
+// ---- fixed scratch of the allocation-free A-apply ------------------------------
+// The shared-node slots of one plane-sweep apply for callers that cannot
+// allocate device memory.  Every GPU the library runs on holds one copy until
+// the process ends.  In host code this name stands for the device symbol and
+// is not an address: host code uses the per-device address that
+// hipGetSymbolAddress returns (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 }  // namespace stk

@@ -189,6 +189,7 @@ enum { Q_0 = 0, Q_1, Q_2, Q_3, Q_4, Q_5, Q_6, Q_7, Q_8, Q_9, Q_ONES, Q_MD, Q_U0,
 
 struct stk_ctx {
   stk_mesh_desc desc{};
+  int device = 0;          // HIP device current at stk_create
   MacroMesh mm;
   Topology top;
   std::vector<std::unique_ptr<LevelData>> lv;   // index = level; [0, min_level) unused
@@ -1290,6 +1291,8 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
     std::unique_ptr<stk_ctx> c(new stk_ctx());
     c->desc = *desc;
     c->s = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&c->device));
+    HIPCHK(noalloc_scratch_init(c->device));   // address of this GPU's fixed scratch array
     c->mm = desc->kind == STK_MESH_CUBE ? make_cube() : make_shell(desc->n_tan, desc->n_rad, desc->r_in, desc->r_out);
     c->top = build_topology(c->mm);
     std::vector<double> geo = macro_geometry(c->mm);
@@ -1401,6 +1404,33 @@ int stk_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, int b
     REQUIRE(x && y, "null vector");
     PREC_DISPATCH(prec, applyA<double>(*ctx, level, (const double*)x, (double*)y, bc & 3),
                   applyA<float>(*ctx, level, (const float*)x, (float*)y, bc & 3));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_A_noalloc(stk_ctx* ctx, int level, int prec, const void* x, void* y, int bc) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(x && y, "null vector");
+    REQUIRE(prec == 32 || prec == 64, "prec must be 32 or 64");
+    static_assert(NOALLOC_SCRATCH_BYTES == (size_t)STK_NOALLOC_SCRATCH_BYTES, "scratch size mismatch");
+    LevelData& L = ctx->at(level);
+    const size_t rb = prec == 64 ? sizeof(double) : sizeof(float);
+    const size_t n2s = L.d.elemwise ? 0 : (size_t)3 * L.d.nmacro * L.d.sw.nsh2;
+    const size_t n1s = L.d.elemwise ? 0 : (size_t)L.d.nmacro * L.d.sw.nsh1;
+    const size_t off1 = (n2s * rb + 255) & ~(size_t)255;
+    const size_t need = off1 + n1s * rb;
+    REQUIRE(need <= NOALLOC_SCRATCH_BYTES,
+            "level too large for the allocation-free A-apply: its slots need " + std::to_string(need) +
+                " bytes, the fixed scratch holds " + std::to_string(NOALLOC_SCRATCH_BYTES));
+    unsigned char* base = static_cast<unsigned char*>(noalloc_scratch(ctx->device));
+    REQUIRE(base, "fixed scratch not initialised on this device");
+    PREC_DISPATCH(prec,
+                  launch_stokes<double>(F_A, L.d, L.bc, (const double*)x, nullptr, L.etap<double>(), nullptr,
+                                        (double*)y, nullptr, (double*)base, (double*)(base + off1), bc & 3, ctx->s),
+                  launch_stokes<float>(F_A, L.d, L.bc, (const float*)x, nullptr, L.etap<float>(), nullptr,
+                                       (float*)y, nullptr, (float*)base, (float*)(base + off1), bc & 3, ctx->s));
     HIPCHK(hipGetLastError());
   });
 }
