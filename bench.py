@@ -309,6 +309,12 @@ def main():
                     help="only the A-apply timings (for counter collection)")
     ap.add_argument("--transfer-only", action="store_true",
                     help="only the finest-level FP32 restriction and prolongation (for counter collection)")
+    ap.add_argument("--contrast-study", action="store_true",
+                    help="only the high-contrast study: viscosity contrast 1e6 (depth factor, temperature, a "
+                         "seeded slab), mixed and all-FP64 solves to 1e-8 on the shell and level given")
+    ap.add_argument("--large-apply", action="store_true",
+                    help="only the A-apply throughput (FP64 and FP32) with the device memory in use; "
+                         "use with --n-tan 20 --n-rad 4 for the largest shell")
     ap.add_argument("--l-eta-study", action="store_true",
                     help="only the coarse-viscosity study: A-block CG iterations and time of 10 FGMRES "
                          "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
@@ -317,7 +323,7 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not "
               "part of this build", file=sys.stderr)
         sys.exit(2)
-    if args.apply_only or args.transfer_only or args.l_eta_study:
+    if args.apply_only or args.transfer_only or args.l_eta_study or args.contrast_study or args.large_apply:
         return studies(args)
 
     n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
@@ -508,11 +514,16 @@ def studies(args):
     os.environ.setdefault("STK_VERBOSE", "1")
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
+    free_before = torch.cuda.mem_get_info(dev)
     with StokesContext("shell", level=args.level, min_level=0, n_tan=args.n_tan, n_rad=args.n_rad,
                        device=dev) as sc:
         n2, n1 = sc.sizes()
         Nu, Np = 3 * n2, n1
         log(f"context {time.perf_counter() - t0:.1f}s  N_u={Nu} N_p={Np}")
+        if args.large_apply:
+            return large_apply(args, sc, dev, Nu, Np, free_before, time.perf_counter() - t0)
+        if args.contrast_study:
+            return contrast_study(args, sc, dev, Nu, Np)
         X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
         X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
         field = inputs.SHField(2)
@@ -588,6 +599,76 @@ def studies(args):
             print(json.dumps({"l_eta_study": study, "E_A": 4.610, "V_A": 2.996,
                               "eta_base": "inputs.base_viscosity_profile()", "level": args.level}), flush=True)
             return
+
+
+def large_apply(args, sc, dev, Nu, Np, free_before, t_ctx):
+    """A-apply throughput on a large shell in both precisions, with the device
+    memory the context and the vectors occupy (hipMemGetInfo through torch)."""
+    import numpy as np
+    import torch
+
+    import inputs
+    n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
+    X1 = sc.coords(which=1)[0]
+    eta = torch.tensor(inputs.viscosity_1e6(X1, inputs.SHField(2).temperature(X1)), device=dev)
+    del X1
+    sc.set_fields(eta)
+    del eta
+    out = {"workload": f"shell {args.n_tan}x{args.n_rad} ({60 * args.n_tan ** 2 * args.n_rad} macro-tets), "
+                       f"level {args.level}, viscosity contrast 1e6", "N_u": Nu, "N_p": Np, "micro_tets": n_tets,
+           "context_s": t_ctx}
+    for dt_, name in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+        x = torch.tensor(inputs.uniform(0, Nu), dtype=dt_, device=dev)
+        y = torch.empty_like(x)
+        sc.time_apply_A(x, y, reps=2)
+        free, total = torch.cuda.mem_get_info(dev)
+        ms, mk = sc.time_apply_A(x, y, reps=10)
+        prec = 64 if name == "fp64" else 32
+        out[name] = {"gdof_s": Nu / ms / 1e6, "ms_per_apply": ms, "ms_sweep_kernel": mk,
+                     "roofline": _roofline(prec, n_tets, Nu, Np, mk, None),
+                     "device_bytes_in_use": total - free, "device_bytes_total": total,
+                     "in_use_before_context": free_before[1] - free_before[0]}
+        log(f"{name}: {ms:.2f} ms per apply ({Nu / ms / 1e6:.1f} GDoF/s), sweep {mk:.2f} ms; "
+            f"{(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f} in use")
+        del x, y
+    print(json.dumps({"large_apply": out}), flush=True)
+
+
+def contrast_study(args, sc, dev, Nu, Np):
+    """Mixed-precision against all-FP64 solves to 1e-8 at viscosity contrast
+    1e6 (Sec. 5.2.2: FP64 Chebyshev bounds, FP32 smoothing)."""
+    import numpy as np
+    import torch
+
+    import inputs
+    X2 = sc.coords(which=2)[0]
+    X1 = sc.coords(which=1)[0]
+    field = inputs.SHField(2)
+    eta1 = inputs.viscosity_1e6(X1, field.temperature(X1))
+    lnrho = torch.tensor(inputs.ln_density(X1), device=dev)
+    T2 = torch.tensor(field.temperature(X2), device=dev)
+    del X2, X1
+    out = {"workload": f"shell {args.n_tan}x{args.n_rad} level {args.level}, N_u={Nu}, N_p={Np}",
+           "eta_max_over_min": float(eta1.max() / eta1.min()), "eta_min": float(eta1.min()),
+           "eta_max": float(eta1.max())}
+    eta = torch.tensor(eta1, device=dev)
+    del eta1
+    res = {}
+    for prec in (32, 64):
+        prm = default_params(precision=prec, tol_rel=1e-8, max_outer=200)
+        sc.set_fields(eta, lnrho, prm)
+        f = sc.rhs_buoyancy(T2)
+        u, p, rep = sc.solve(f, params=prm, allow_noconv=True)
+        torch.cuda.synchronize()
+        res[prec] = (u, p)
+        out["fp64" if prec == 64 else "mixed"] = {k: rep[k] for k in (
+            "seconds", "iterations", "rel_residual", "a_cg_its", "s_cg_its", "vcycles", "coarse_its", "mass_its")}
+        log(f"prec {prec}: {rep['iterations']} its, rel {rep['rel_residual']:.2e}, {rep['seconds']:.1f}s")
+    (u32, p32), (u64, p64) = res[32], res[64]
+    out["mixed_vs_fp64"] = {"speedup": out["fp64"]["seconds"] / out["mixed"]["seconds"],
+                            "u_rel_diff": (torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)).item(),
+                            "p_rel_diff": (torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)).item()}
+    print(json.dumps({"contrast_study": out}), flush=True)
 
 
 if __name__ == "__main__":

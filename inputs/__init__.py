@@ -90,17 +90,30 @@ def viscosity_contrast(T, contrast=1e4):
     return np.exp(np.log(contrast) * (0.5 - np.asarray(T)))
 
 
-def viscosity_1e6(xyz, T, seed=3, r_in=R_IN, r_out=R_OUT):
-    """Depth factor 100^((r_out - r)/(r_out - r_in)), temperature factor
-    100^(0.5 - T) and a x100 slab {r >= 0.75, angle(x, c) <= 15 deg} around a
-    seeded direction c: contrast about 1e6 over the shell."""
+def viscosity_1e6(xyz, T, seed=3, contrast=1e6, r_in=R_IN, r_out=R_OUT):
+    """eta = 100^((r_out - r)/(r_out - r_in)) * exp(a (0.5 - T)) * (100 in a slab
+    {r >= 0.75, angle(x, c) <= 15 deg} around a seeded direction c, else 1),
+    with the temperature exponent a >= 0 chosen so that max/min of eta over
+    the given points is `contrast` (a depth factor of 100 and the slab alone
+    reach only about 1.3e3).  log eta is affine in a, so its spread is a
+    convex piecewise-linear function of a, found by bisection."""
     xyz = np.asarray(xyz, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
     r = np.linalg.norm(xyz, axis=1)
     c = np.random.default_rng(seed).standard_normal(3)
     c /= np.linalg.norm(c)
     cosang = (xyz @ c) / r
     slab = (r >= 0.75) & (cosang >= np.cos(np.deg2rad(15.0)))
-    return (100.0 ** ((r_out - r) / (r_out - r_in))) * (100.0 ** (0.5 - np.asarray(T))) * np.where(slab, 100.0, 1.0)
+    b = np.log(100.0) * (r_out - r) / (r_out - r_in) + np.where(slab, np.log(100.0), 0.0)
+    spread = lambda a: np.ptp(b + a * (0.5 - T))
+    target = np.log(contrast)
+    lo, hi = 0.0, 1.0
+    while spread(hi) < target:
+        hi *= 2.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if spread(mid) < target else (lo, mid)
+    return np.exp(b + 0.5 * (lo + hi) * (0.5 - T))
 
 
 def ln_density(xyz):

@@ -46,3 +46,15 @@ def test_splitmix64_matches_its_published_outputs():
     u = inputs.splitmix64_uniform(1234567, 5)
     assert np.allclose(u, [(z >> 11) / 2.0 ** 52 - 1.0 for z in inputs.splitmix64(1234567, 5)], rtol=0, atol=0)
     assert (u >= -1).all() and (u < 1).all()
+
+
+def test_viscosity_1e6_reaches_its_contrast_with_depth_slab_and_temperature():
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=(20000, 3))
+    x = d / np.linalg.norm(d, axis=1)[:, None] * rng.uniform(0.55, 1.0, 20000)[:, None]
+    T = inputs.SHField(2).temperature(x)
+    eta = inputs.viscosity_1e6(x, T)
+    assert abs(np.log(eta.max() / eta.min()) - np.log(1e6)) < 1e-9
+    # depth: at fixed T outside the slab eta falls by 100 from r_in to r_out
+    e2 = inputs.viscosity_1e6(np.array([[0.55, 0, 0], [1.0, 0, 0], [0.3, 0.4, 0.1]]), np.array([0.5, 0.5, 0.2]))
+    assert np.isclose(e2[0] / e2[1], 100.0)
