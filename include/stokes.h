@@ -249,7 +249,13 @@ int stk_precondition(stk_ctx* ctx, const stk_solver_params* params, const double
 /* Stokes solve (Sec. 5.2.4): f_u (3 n_p2), g_p (n_p1, nullable = 0),
  * u_dirichlet (3 n_p2, nullable = 0; read at Dirichlet nodes only); outputs
  * u (3 n_p2, includes the Dirichlet values), p (n_p1, arithmetic mean 0).
- * rep nullable.  Returns STK_ENOCONV with the best iterate if not converged. */
+ * With free slip on both spheres (bc_inner = bc_outer = STK_BC_FREESLIP)
+ * the rigid rotations e_k x X are admissible and strain free (Sec. 2), so
+ * the solves remove them as P_p removes the pressure constant: u is
+ * Euclidean-orthogonal to the three rotation vectors and the residual is
+ * measured with their span projected off (the operator entry points apply
+ * P_v only).  rep nullable.  Returns STK_ENOCONV with the best iterate if
+ * not converged. */
 int stk_solve(stk_ctx* ctx, const stk_solver_params* params, const double* f_u, const double* g_p,
               const double* u_dirichlet, double* u, double* p, stk_report* rep);
 /* Adjoint of the Stokes solve (the transpose of the system of eq.

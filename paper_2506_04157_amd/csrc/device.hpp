@@ -225,6 +225,17 @@ template <typename R>
 void vaxpy2_nrm(R a, const R* p, R* x, R b, const R* q, R* r, long long n, double* partial, double* out, hipStream_t s);
 void vsum_partials(double* partial, int np, double* out, hipStream_t s);
 
+// Removal of the rigid rotations e_k x X from a finest-level velocity (free
+// slip on both spheres): X the node positions (node-major, 3 per P2 node),
+// gi the inverse of G = sum_i (|X_i|^2 I - X_i X_i^T) (row-major)
+struct RotDev {
+  const double* X;
+  double gi[9];
+};
+// v -= (G^-1 m) x X with m = sum_i X_i x v_i; partial: 3 * DOT_BLOCKS doubles
+template <typename R>
+void launch_rot_remove(const RotDev& rd, long long n2, R* v, double* partial, hipStream_t s);
+
 // Fixed device array (per GPU) holding the shared-node slots of the
 // allocation-free A-apply; its size in bytes equals STK_NOALLOC_SCRATCH_BYTES.
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;

@@ -16,13 +16,17 @@
 // Quadrature: symmetric 4-point rule of degree 2 (the paper does not state
 // its rule; this reading keeps the Taylor-Hood rates and positive weights).
 //
-// Work decomposition: one workgroup per (macro-tet, brick of 4^3 cubes of
-// the macro's cube lattice).  The brick's P2 box (9^3 nodes) and P1 box (5^3)
-// are staged in LDS through the macro's local-to-global table; wave w of the
-// 6 waves handles micro-tets of type w, one per lane (64 cubes per brick), and
-// accumulates with LDS atomics; the flush stores nodes that only this
-// workgroup touches and atomically adds the rest (brick faces and macro
-// interfaces) into a zero-filled output.
+// Work decomposition of the operator applies (k_sweep): one workgroup per
+// (macro-tet, strip of the macro's lattice rows) sweeps the micro-tet layers
+// along the macro's third lattice direction, with a ring of P2 and P1 planes
+// staged in LDS; each lane takes one micro-tet of the current layer at a time
+// and adds its element result to FP64 LDS accumulators.  Completed planes are
+// written out: nodes that only this workgroup touches with plain stores, nodes
+// shared with other macros or strips into per-macro slots that k_gather sums
+// in a fixed order (no global atomics).  The coarsest levels (2^level <= 2)
+// use k_elemwise, one thread per micro-tet with global atomics.  diag(A), the
+// M_{1/eta} brick kernel, the right-hand side and the gradient work on bricks
+// of 4^3 lattice cubes staged in LDS.
 #include <mutex>
 
 #include "device.hpp"
@@ -1726,6 +1730,43 @@ __device__ __forceinline__ double block_sum(const double* part, int np, double* 
   __syncthreads();
   return v;
 }
+// ---- rigid rotations (free slip on both spheres) -------------------------------
+// Moments sum_i X_i x v_i of a velocity over the P2 nodes: FP64 partial sums
+// per block, component k at partial[k * DOT_BLOCKS + block].
+template <typename R>
+__global__ __launch_bounds__(256) void k_rot_moment(const double* __restrict__ X, const R* __restrict__ v, long long n2,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[3][256];
+  double a = 0, b = 0, c = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    const double x = X[3 * i], y = X[3 * i + 1], z = X[3 * i + 2];
+    const double u = (double)v[i], w = (double)v[i + n2], q = (double)v[i + 2 * n2];
+    a += y * q - z * w;
+    b += z * u - x * q;
+    c += x * w - y * u;
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) partial[k * DOT_BLOCKS + blockIdx.x] = red[k][0];
+  }
+}
+// v_i -= w x X_i, w = G^-1 m: every block sums the moment partials itself, in
+// the same order, so no separate scalar kernel is needed.
+template <typename R>
+__global__ __launch_bounds__(256) void k_rot_remove(RotDev rd, long long n2, R* __restrict__ v,
+                                                    const double* __restrict__ partial, int np);
+
 __device__ __forceinline__ void block_partials(double a, double b, double* pa, double* pb, double (*red)[256]) {
   red[0][threadIdx.x] = a;
   red[1][threadIdx.x] = b;
@@ -1742,6 +1783,24 @@ __device__ __forceinline__ void block_partials(double a, double b, double* pa, d
     pb[blockIdx.x] = red[1][0];
   }
 }
+template <typename R>
+__global__ __launch_bounds__(256) void k_rot_remove(RotDev rd, long long n2, R* __restrict__ v,
+                                                    const double* __restrict__ partial, int np) {
+  __shared__ double red[256];
+  double m[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = block_sum(partial + k * DOT_BLOCKS, np, red);
+  double w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w[k] = rd.gi[3 * k] * m[0] + rd.gi[3 * k + 1] * m[1] + rd.gi[3 * k + 2] * m[2];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    const double x = rd.X[3 * i], y = rd.X[3 * i + 1], z = rd.X[3 * i + 2];
+    v[i] = R((double)v[i] - (w[1] * z - w[2] * y));
+    v[i + n2] = R((double)v[i + n2] - (w[2] * x - w[0] * z));
+    v[i + 2 * n2] = R((double)v[i + 2 * n2] - (w[0] * y - w[1] * x));
+  }
+}
+
 __device__ __forceinline__ double* cg_rr(double* part, int parity) { return part + DOT_BLOCKS + 2 * DOT_BLOCKS * parity; }
 __device__ __forceinline__ double* cg_rz(double* part, int parity) { return cg_rr(part, parity) + DOT_BLOCKS; }
 __device__ __forceinline__ const double* cg_rr(const double* part, int parity) {
@@ -2445,6 +2504,16 @@ void launch_project(const BcDev& bc, long long n2, R* v, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL((k_project<R>), dim3((n + 255) / 256), dim3(256), 0, s, bc, n2, v);
 }
+template <typename R>
+void launch_rot_remove(const RotDev& rd, long long n2, R* v, double* partial, hipStream_t s) {
+  // at most DOT_BLOCKS blocks: the partial buffer holds DOT_BLOCKS per component,
+  // and every block of the second kernel sums all of them
+  const int nb = vgrid(n2) < DOT_BLOCKS ? vgrid(n2) : DOT_BLOCKS;
+  hipLaunchKernelGGL((k_rot_moment<R>), dim3(nb), dim3(256), 0, s, rd.X, v, n2, partial);
+  hipLaunchKernelGGL((k_rot_remove<R>), dim3(nb), dim3(256), 0, s, rd, n2, v, partial, nb);
+}
+template void launch_rot_remove<double>(const RotDev&, long long, double*, double*, hipStream_t);
+template void launch_rot_remove<float>(const RotDev&, long long, float*, double*, hipStream_t);
 template void launch_project<double>(const BcDev&, long long, double*, hipStream_t);
 template void launch_project<float>(const BcDev&, long long, float*, hipStream_t);
 

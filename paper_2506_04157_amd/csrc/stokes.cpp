@@ -205,6 +205,11 @@ struct stk_ctx {
   hipEvent_t cgev[2] = {nullptr, nullptr};
   bool ready = false;
   bool has_rho = false;
+  // free slip on both spheres: the rigid rotations are removed from the
+  // finest-level velocities the solvers work with
+  bool rot = false;
+  DBuf<double> rotX, rotbuf;
+  RotDev rotd{};
   DBuf<double> lnrho;
   DBuf<float> lnrhof;
   DBuf<double> vbase;      // radial base viscosity samples (quadrature-point viscosity)
@@ -250,9 +255,16 @@ double cg_step_nrm(Ctx& c, double alpha, const R* p, R* x, const R* q, R* r, lon
   return std::sqrt(*c.hpin);
 }
 
+// P_v (Dirichlet -> 0, free slip -> tangential); on the finest level with
+// free slip on both spheres also the removal of the rigid rotations
+template <class R>
+void rot_remove(Ctx& c, R* v) {
+  launch_rot_remove<R>(c.rotd, n2of(c, c.L()), v, c.rotbuf.p, c.s);
+}
 template <class R>
 void project(Ctx& c, int l, R* v) {
   launch_project<R>(c.at(l).bc, n2of(c, l), v, c.s);
+  if (c.rot && l == c.L()) rot_remove<R>(c, v);
 }
 
 template <class R>
@@ -495,6 +507,7 @@ void solve_A(Ctx& c, const R* b, R* x) {
   for (int it = 1; it <= c.par.max_inner; ++it) {
     if (c.rep) c.rep->a_cg_its++;
     applyA<R>(c, l, p, q, BCM_IN | BCM_OUT);
+    if (c.rot) rot_remove<R>(c, q);
     const double alpha = rz / dot<R>(c, p, q, N);
     if (cg_step_nrm<R>(c, alpha, p, x, q, r, N) <= c.par.tol_A * nb) break;
     vcycle<R>(c, l, r, z, c.par.m_A, c.par.deg_A);
@@ -726,6 +739,7 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
   auto Hs = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
   auto Kapply = [&](const double* x, double* y) {
     applyK<double>(c, x, x + N, y, y + N, transpose, BCM_IN | BCM_OUT);
+    if (c.rot) rot_remove<double>(c, y);
     project_mean<double>(c, y + N);
   };
   auto precond = [&](const double* v, double* z) { precondition(c, v, z, transpose); };
@@ -1312,6 +1326,37 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
       c->lv[l].reset(new LevelData());
       c->lv[l]->h = build_level(c->mm, c->top, l);
       upload_level(*c, l);
+    }
+    if (desc->kind == STK_MESH_SHELL && desc->bc_inner == STK_BC_FREESLIP && desc->bc_outer == STK_BC_FREESLIP) {
+      // the rigid rotations e_k x X: node positions of the finest level and
+      // the inverse of their Gram matrix G = sum_i (|X_i|^2 I - X_i X_i^T)
+      const Level& h = c->lv[desc->level]->h;
+      std::vector<double> X((size_t)3 * h.n2);
+      level_coords(c->mm, c->top, h, 2, X.data(), nullptr);
+      double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (long long i = 0; i < h.n2; ++i) {
+        const double* x = &X[3 * i];
+        const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) G[3 * a + b] += (a == b ? r2 : 0.0) - x[a] * x[b];
+      }
+      const double det = G[0] * (G[4] * G[8] - G[5] * G[7]) - G[1] * (G[3] * G[8] - G[5] * G[6]) +
+                         G[2] * (G[3] * G[7] - G[4] * G[6]);
+      REQUIRE(det > 0, "degenerate node set for the rotation constraint");
+      double* gi = c->rotd.gi;
+      gi[0] = (G[4] * G[8] - G[5] * G[7]) / det;
+      gi[1] = (G[2] * G[7] - G[1] * G[8]) / det;
+      gi[2] = (G[1] * G[5] - G[2] * G[4]) / det;
+      gi[3] = (G[5] * G[6] - G[3] * G[8]) / det;
+      gi[4] = (G[0] * G[8] - G[2] * G[6]) / det;
+      gi[5] = (G[2] * G[3] - G[0] * G[5]) / det;
+      gi[6] = (G[3] * G[7] - G[4] * G[6]) / det;
+      gi[7] = (G[1] * G[6] - G[0] * G[7]) / det;
+      gi[8] = (G[0] * G[4] - G[1] * G[3]) / det;
+      c->rotX.upload(X);
+      c->rotbuf.alloc(3 * DOT_BLOCKS);
+      c->rotd.X = c->rotX.p;
+      c->rot = true;
     }
     c->dotbuf.alloc(2 * DOT_BLOCKS + 8);
     c->cgbuf.alloc(16);

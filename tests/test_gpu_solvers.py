@@ -388,3 +388,50 @@ def test_coarsest_level_size_limit():
     with pytest.raises(StokesError) as err:
         StokesContext("shell", level=2, min_level=2, n_tan=10, n_rad=2)   # 768,000 coarsest micro-tets
     assert err.value.code == STK_EINVAL and "min_level" in str(err.value)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_solve_shell_free_slip_on_both_spheres(precision):
+    """Free slip on both spheres (NEXT-3): the rigid rotations e_k x X are
+    admissible and strain free, so the solves remove them (R^T u = 0, the
+    momentum residual projected off span(R)).  The GPU solution solves the
+    oracle's constrained system (three rotation multipliers) to the stated
+    tolerance and is close to its direct solution; compressible, viscosity
+    contrast 1e4."""
+    from oracle.system import rigid_rotations
+    print(f"\n[solve shell free slip both prec {precision}]", flush=True)
+    P = Pair("shell", 2, min_level=0, n_tan=1, n_rad=1, bc_inner=2, bc_outer=2)
+    m = P.meshes[2]
+    field = inputs.SHField(2)
+    eta = inputs.viscosity_contrast(field.temperature(m.X1), 1e4)
+    lnrho = inputs.ln_density(m.X1)
+    f = rhs_buoyancy(m, field.temperature(m.X2))
+    R = rigid_rotations(m)
+    A = assemble_A(m, eta)
+    B = assemble_B(m)
+    Bb = B + assemble_B(m, lnrho, only_C=True)
+    _, Q = P.projector()
+    uo, po, _ = solve_stokes(A, Bb, f, np.zeros(m.n1), Q, Bt=B.T, rotations=R)
+    params = default_params(tol_rel=1e-10, precision=precision)
+    P.ctx.set_fields(P.p_to_lib(eta), P.p_to_lib(lnrho), params=params)
+    u, p, rep = P.ctx.solve(P.u_to_lib(f), params=params)
+    print(rep["iterations"], rep["rel_residual"], rep["seconds"])
+    ug, pg = P.u_to_or(u), P.p_to_or(p)
+    assert rep["rel_residual"] <= 1e-10
+    # no rigid rotation in the solution
+    assert np.abs(R.T @ ug).max() <= 1e-12 * np.linalg.norm(R, axis=0).max() * np.linalg.norm(ug)
+    # the residual in the oracle's system, with span(R) projected off
+    Pm = Q @ Q.T
+    Qr, _ = np.linalg.qr(R)
+    ru = Pm @ (f - A @ ug - B.T @ pg)
+    ru -= Qr @ (Qr.T @ ru)
+    rp = Bb @ ug
+    rp = rp - rp.mean()
+    fr = Pm @ f - Qr @ (Qr.T @ (Pm @ f))
+    assert np.hypot(np.linalg.norm(ru), np.linalg.norm(rp)) <= 2e-10 * np.linalg.norm(fr)
+    assert relerr(ug, uo) < 1e-5 and relerr(pg, po) < 1e-5
+    # tangential on both spheres
+    U = ug.reshape(3, -1).T
+    bnd = m.flag2 > 0
+    nrm = m.X2[bnd] / np.linalg.norm(m.X2[bnd], axis=1)[:, None]
+    assert np.abs(np.einsum("ij,ij->i", U[bnd], nrm)).max() <= 1e-12 * np.abs(U).max()
