@@ -9,6 +9,11 @@ Definitions (Sec. 5.1, "Linear algebraic formulation"; stress tensor of Sec. 2):
 * B_ij = - int div phi_j psi_i dx,   C_ij = - int (grad ln rho . phi_j) psi_i dx
 * M_{1/eta, ij} = int psi_i psi_j / eta dx      (Sec. 5.2.3, Schur approximation)
 * f_i = int T r_hat . phi_i dx                  (buoyancy with unit scaling)
+* M_{sqrt eta}: the P2 vector mass with weight sqrt(s_K eta_h) and
+  K_{1/sqrt eta}: the P1 Poisson (Neumann) matrix with weight
+  (s_K eta_h)^{-1/2}, s_K = a^2 on the elements touching the Dirichlet
+  boundary and 1 elsewhere (the weighted BFBT, eq. schurWBFBT and the
+  scaled viscosities eta_l, eta_r that follow it)
 
 eta, ln rho are P1 interpolants of nodal values, T is a P2 interpolant; on
 the coarse levels up to l_eta the viscosity is instead evaluated at the
@@ -21,7 +26,7 @@ dof (c, node) -> c * n2 + node.
 import numpy as np
 import scipy.sparse as sp
 
-from .quadrature import rule_q4
+from .quadrature import rule_q4, rule_stroud
 
 # --- P2 / P1 shape functions in barycentric coordinates -------------------
 EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
@@ -228,6 +233,56 @@ def assemble_M_inv_eta(mesh, eta1, rule=None):
         rows.append(np.repeat(p, 4, axis=1).ravel())
         cols.append(np.tile(p, (1, 4)).ravel())
         vals.append(Me.ravel())
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(mesh.n1, mesh.n1)).tocsr()
+
+
+def dirichlet_element_scale(mesh, dirichlet_flags, a):
+    """s_K of the weighted BFBT (eq. schurWBFBT): a^2 on the set D_eta of
+    elements whose closure meets the Dirichlet boundary (a vertex on it is
+    enough), 1 elsewhere."""
+    on = np.isin(mesh.flag1, list(dirichlet_flags)) & (mesh.flag1 != 0)
+    return np.where(on[mesh.e1].any(axis=1), a * a, 1.0)
+
+
+def assemble_vector_mass(mesh, eta1, elem_scale=None, rule=None):
+    """M_{sqrt eta}: (c, a), (c', b) entry delta_cc' int sqrt(s_K eta_h) N_a N_b dx
+    (component-major velocity layout).  The P2 mass integrand has degree 4,
+    so the default rule is the 27-point conical product (degree 5): the
+    4-point rule of the Stokes blocks would make the element matrices rank 4
+    and the mass singular."""
+    rule = rule if rule is not None else rule_stroud(3)
+    n2 = mesh.n2
+    rows, cols, vals = [], [], []
+    for sel in _chunks(mesh.ne, 4096):
+        W, G2, G1, X, N2, N1 = geometry(mesh, sel, rule)
+        eta_q = np.einsum("qk,ek->eq", N1, eta1[mesh.e1[sel]])
+        s_e = 1.0 if elem_scale is None else elem_scale[sel][:, None]
+        Me = np.einsum("eq,qa,qb->eab", W * np.sqrt(s_e * eta_q), N2, N2)
+        e = mesh.e2[sel]
+        for c in range(3):
+            d = e + c * n2
+            rows.append(np.repeat(d, 10, axis=1).ravel())
+            cols.append(np.tile(d, (1, 10)).ravel())
+            vals.append(Me.ravel())
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(3 * n2, 3 * n2)).tocsr()
+
+
+def assemble_poisson_p1(mesh, eta1, elem_scale=None, rule=None):
+    """K_{1/sqrt eta}: int (s_K eta_h)^{-1/2} grad psi_i . grad psi_j dx on the P1
+    space, with natural (Neumann) boundary conditions: constants span its
+    kernel."""
+    rows, cols, vals = [], [], []
+    for sel in _chunks(mesh.ne):
+        W, G2, G1, X, N2, N1 = geometry(mesh, sel, rule)
+        eta_q = np.einsum("qk,ek->eq", N1, eta1[mesh.e1[sel]])
+        s_e = 1.0 if elem_scale is None else elem_scale[sel][:, None]
+        Ke = np.einsum("eq,eqid,eqjd->eij", W / np.sqrt(s_e * eta_q), G1, G1)
+        p = mesh.e1[sel]
+        rows.append(np.repeat(p, 4, axis=1).ravel())
+        cols.append(np.tile(p, (1, 4)).ravel())
+        vals.append(Ke.ravel())
     return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(mesh.n1, mesh.n1)).tocsr()
 

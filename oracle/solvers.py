@@ -18,6 +18,8 @@ Plain linear algebra on the oracle's sparse matrices, in FP64:
 * ``pcg``             preconditioned CG stopped on a relative residual.
 * ``bfbt``            the BFBT-type Schur approximation, eq. (schurV), with
                       caller-supplied inner operators.
+* ``wbfbt``           the weighted BFBT, eq. (schurWBFBT), with its Poisson
+                      replacements K_{1/sqrt eta}^-1 (caller-supplied).
 * ``symmetric_uzawa``, ``inexact_uzawa``, ``adjoint_uzawa``  one step of
                       eqs. (SymmetricUzawaStep1), (InexactUzawaStep1) and
                       (AdjointInexactUzawaStep1) from zero (Sec. 5.2.1).
@@ -144,6 +146,16 @@ def bfbt(r, B, Bt, A, Ahat_inv, solve_BAB):
     y = solve_BAB(r)
     y = B @ Ahat_inv(A @ Ahat_inv(Bt @ y))
     return solve_BAB(y)
+
+
+def wbfbt(r, B, Bt, A, Ml_inv, Mr_inv, Kl_inv, Kr_inv):
+    """The weighted BFBT of eq. schurWBFBT with the Poisson replacements and
+    the scaled viscosities that follow it:
+    S_w^-1 r = K_l^-1 (B M_l^-1 A M_r^-1 B^T) K_r^-1 r, with M the sqrt(eta)
+    vector masses and K the 1/sqrt(eta) Poisson operators of eta_l, eta_r
+    (caller-supplied inverses, constraints applied by the caller)."""
+    y = Kr_inv(r)
+    return Kl_inv(B @ Ml_inv(A @ Mr_inv(Bt @ y)))
 
 
 def symmetric_uzawa(ru, rp, A, Bt, Bbar, Ahat_inv, Shat_inv, sigma, omega):

@@ -312,3 +312,102 @@ def test_buoyancy_uses_the_p2_temperature_at_the_points():
     # negative control: T from its vertex values only (P1 interpolation)
     Tp1 = np.einsum("qk,ek->eq", lam, Tfn(m.x2)[m.e2[:, :4]])
     assert np.abs(assemble(Tp1) - ref).max() > 1e-4 * np.abs(ref).max()
+
+
+# --- weighted BFBT operators (eq. schurWBFBT) -------------------------------------
+
+def _exact_p2_mass_and_p1_stiffness(verts):
+    """The P2 mass int N_a N_b and the P1 stiffness int grad lam_i . grad lam_j
+    on one affine tet, integrated exactly from the symbolic basis."""
+    x1, x2, x3 = sy.symbols("x1 x2 x3")
+    V = [sy.Matrix([sy.Rational(int(round(c * 8)), 8) for c in v]) for v in verts]
+    J = sy.Matrix.hstack(V[1] - V[0], V[2] - V[0], V[3] - V[0])
+    detJ = abs(J.det())
+    Jit = J.inv().T
+    lam = [1 - x1 - x2 - x3, x1, x2, x3]
+    edges = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+    N = [lam[i] * (2 * lam[i] - 1) for i in range(4)] + [4 * lam[i] * lam[j] for (i, j) in edges]
+
+    def integ(expr):
+        p = sy.Poly(sy.expand(expr), x1, x2, x3)
+        return sum(coef * sy.Rational(factorial(a) * factorial(b) * factorial(c), factorial(a + b + c + 3))
+                   for (a, b, c), coef in p.terms()) * detJ
+
+    M = np.array([[float(integ(N[a] * N[b])) for b in range(10)] for a in range(10)])
+    G = [Jit * sy.Matrix([sy.diff(l, v) for v in (x1, x2, x3)]) for l in lam]
+    K = np.array([[float(G[i].dot(G[j]) * detJ / 6) for j in range(4)] for i in range(4)])
+    return M, K
+
+
+def test_vector_mass_and_poisson_exact_on_affine_tet():
+    """Constant eta = 4 on one affine tet: M_{sqrt eta} is 2 x the exact P2
+    mass in each component block (the 27-point rule integrates the degree-4
+    integrand exactly) and K_{1/sqrt eta} is 1/2 x the exact P1 stiffness;
+    the element factor s_K multiplies them by a and 1/a."""
+    from oracle.fem import assemble_poisson_p1, assemble_vector_mass
+
+    verts = [[0.125, 0.0, 0.25], [1.0, 0.25, 0.0], [0.25, 1.125, 0.125], [0.0, 0.375, 0.875]]
+    M_ex, K_ex = _exact_p2_mass_and_p1_stiffness(verts)
+    one = _OneTet(verts)
+    one.e2 = np.arange(10)[None]
+    one.e1 = np.arange(4)[None]
+    one.n2, one.n1, one.ne = 10, 4, 1
+    eta = np.full(4, 4.0)
+    M = assemble_vector_mass(one, eta).toarray()
+    for c in range(3):
+        blk = M[c * 10:(c + 1) * 10, c * 10:(c + 1) * 10]
+        assert np.allclose(blk, 2.0 * M_ex, rtol=0, atol=1e-15)
+    assert np.abs(M[:10, 10:]).max() == 0.0
+    assert np.linalg.matrix_rank(M[:10, :10]) == 10
+    K = assemble_poisson_p1(one, eta).toarray()
+    assert np.allclose(K, 0.5 * K_ex, rtol=0, atol=1e-14)
+    s = np.array([9.0])
+    assert np.allclose(assemble_vector_mass(one, eta, s).toarray(), 3.0 * M, atol=1e-15)
+    assert np.allclose(assemble_poisson_p1(one, eta, s).toarray(), K / 3.0, atol=1e-15)
+    # the 4-point rule of the Stokes blocks would leave the P2 mass singular
+    from oracle.quadrature import rule_q4
+    assert np.linalg.matrix_rank(assemble_vector_mass(one, eta, rule=rule_q4()).toarray()[:10, :10]) == 4
+
+
+def test_vector_mass_takes_sqrt_eta_at_the_points_and_poisson_kernel():
+    """An affine viscosity (its own P1 interpolant) on affine cube elements:
+    M_{sqrt eta} equals the quadrature of sqrt(eta(x_q)) N_a N_b with eta taken
+    analytically at the physical points, and differs from the reading that
+    interpolates sqrt(eta) nodally.  The Poisson matrix annihilates
+    constants, is symmetric, and x^T K x = int |grad x|^2 / sqrt(eta) for a
+    linear x."""
+    from oracle.fem import assemble_poisson_p1, assemble_vector_mass
+    from oracle.quadrature import rule_stroud
+
+    m = RefinedMesh(cube_macros(), 1)
+    eta_fn = lambda X: 1.0 + 3.0 * X[..., 0] + 2.0 * X[..., 1] + X[..., 2]
+    eta = eta_fn(m.X1)
+    M = assemble_vector_mass(m, eta)
+    rule = rule_stroud(3)
+    ref = np.zeros((m.n2, m.n2))
+    W, G2, G1, X, N2, N1 = geometry(m, np.arange(m.ne), rule)
+    Me = np.einsum("eq,qa,qb->eab", W * np.sqrt(eta_fn(X)), N2, N2)
+    for e in range(m.ne):
+        ref[np.ix_(m.e2[e], m.e2[e])] += Me[e]
+    assert np.abs(M[:m.n2, :m.n2].toarray() - ref).max() < 1e-15 * np.abs(ref).max() * 100
+    # nodal interpolation of sqrt(eta) is a different matrix
+    Mi = np.einsum("eq,eq,qa,qb->eab", W, np.einsum("qk,ek->eq", N1, np.sqrt(eta)[m.e1]), N2, N2)
+    assert np.abs(Mi - Me).max() > 1e-6 * np.abs(Me).max()
+    K = assemble_poisson_p1(m, eta)
+    assert np.abs(K @ np.ones(m.n1)).max() < 1e-13 * abs(K).max()
+    assert abs(K - K.T).max() < 1e-15 * abs(K).max()
+    g = np.array([0.3, -1.1, 0.7])
+    x = m.X1 @ g
+    W, G2, G1, X, N2, N1 = geometry(m, np.arange(m.ne))
+    expect = np.sum(W / np.sqrt(eta_fn(X))) * (g @ g)
+    assert abs(x @ (K @ x) - expect) < 1e-12 * expect
+
+
+def test_dirichlet_element_scale_marks_the_elements_touching_the_dirichlet_sphere():
+    from oracle.fem import dirichlet_element_scale
+    m = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 1)
+    s = dirichlet_element_scale(m, {1}, 10.0)
+    r = np.linalg.norm(m.X1[m.e1], axis=2)
+    touch = (np.abs(r - 0.55) < 1e-12).any(axis=1)
+    assert np.array_equal(s == 100.0, touch) and np.all(s[~touch] == 1.0) and touch.any() and (~touch).any()
+    assert np.all(dirichlet_element_scale(m, {1}, 1.0) == 1.0)

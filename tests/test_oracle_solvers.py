@@ -5,7 +5,7 @@ import scipy.sparse.linalg as spla
 
 from oracle.fem import assemble_A, assemble_B
 from oracle.mesh import RefinedMesh, cube_macros, shell_macros
-from oracle.solvers import (adjoint_uzawa, inexact_uzawa, bfbt, chebyshev, chebyshev_error_polynomial, fgmres, pcg,
+from oracle.solvers import (adjoint_uzawa, inexact_uzawa, bfbt, wbfbt, chebyshev, chebyshev_error_polynomial, fgmres, pcg,
                             prolongation, symmetric_uzawa, vcycle, vector_prolongation)
 from oracle.system import rigid_rotations, solve_stokes, velocity_basis
 
@@ -98,6 +98,32 @@ def test_bfbt_identity_for_square_B():
     s = bfbt(r, B, B.T, A, Ainv, lambda v: np.linalg.solve(BAB, v))
     exact = np.linalg.solve(B @ np.linalg.solve(A, B.T), r)
     assert np.allclose(s, exact, rtol=1e-10)
+
+
+def test_wbfbt_identity_for_square_B_and_exact_poisson_operators():
+    """With a square invertible B and the Poisson operators taken exactly as
+    K_l = B M_l^-1 B^T, K_r = B M_r^-1 B^T, the weighted BFBT is the exact
+    inverse Schur complement for any SPD masses M_l, M_r (different left and
+    right weights, as with a_l != a_r); swapping l and r, or dropping one
+    mass, breaks it."""
+    rng = np.random.default_rng(3)
+    n = 6
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + n * np.eye(n)
+    B = rng.standard_normal((n, n))
+    Ms = []
+    for _ in range(2):
+        Y = rng.standard_normal((n, n))
+        Ms.append(Y @ Y.T + n * np.eye(n))
+    Ml, Mr = Ms
+    Kl, Kr = B @ np.linalg.solve(Ml, B.T), B @ np.linalg.solve(Mr, B.T)
+    r = rng.standard_normal(n)
+    sol = lambda Mat: (lambda v: np.linalg.solve(Mat, v))
+    s = wbfbt(r, B, B.T, A, sol(Ml), sol(Mr), sol(Kl), sol(Kr))
+    exact = np.linalg.solve(B @ np.linalg.solve(A, B.T), r)
+    assert np.allclose(s, exact, rtol=1e-10)
+    wrong = wbfbt(r, B, B.T, A, sol(Mr), sol(Ml), sol(Kl), sol(Kr))
+    assert not np.allclose(wrong, exact, rtol=1e-3)
 
 
 def test_fgmres_with_exact_symmetric_uzawa_converges_in_one_step():
