@@ -315,6 +315,11 @@ def main():
     ap.add_argument("--large-apply", action="store_true",
                     help="only the A-apply throughput (FP64 and FP32) with the device memory in use; "
                          "use with --n-tan 20 --n-rad 4 for the largest shell")
+    ap.add_argument("--schur-study", action="store_true",
+                    help="only the comparison of block preconditioners and Schur approximations (Sec. 7.4 "
+                         "setting): every Uzawa variant with the V-cycle BFBT, mass, and symmetric and "
+                         "asymmetric weighted BFBT, stopped at an absolute residual of 1e-8; use with "
+                         "--n-tan 2 --n-rad 1")
     ap.add_argument("--l-eta-study", action="store_true",
                     help="only the coarse-viscosity study: A-block CG iterations and time of 10 FGMRES "
                          "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
@@ -323,7 +328,8 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not "
               "part of this build", file=sys.stderr)
         sys.exit(2)
-    if args.apply_only or args.transfer_only or args.l_eta_study or args.contrast_study or args.large_apply:
+    if (args.apply_only or args.transfer_only or args.l_eta_study or args.contrast_study or args.large_apply
+            or args.schur_study):
         return studies(args)
 
     n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
@@ -524,6 +530,8 @@ def studies(args):
             return large_apply(args, sc, dev, Nu, Np, free_before, time.perf_counter() - t0)
         if args.contrast_study:
             return contrast_study(args, sc, dev, Nu, Np)
+        if args.schur_study:
+            return schur_study(args, sc, dev, Nu, Np)
         X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
         X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
         field = inputs.SHField(2)
@@ -604,21 +612,25 @@ def studies(args):
 def large_apply(args, sc, dev, Nu, Np, free_before, t_ctx):
     """A-apply throughput on a large shell in both precisions, with the device
     memory the context and the vectors occupy (hipMemGetInfo through torch)."""
-    import numpy as np
     import torch
 
     import inputs
     n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
     X1 = sc.coords(which=1)[0]
-    eta = torch.tensor(inputs.viscosity_1e6(X1, inputs.SHField(2).temperature(X1)), device=dev)
-    del X1
+    T1 = inputs.SHField(2).temperature_torch(torch.tensor(X1, device=dev)).cpu().numpy()
+    eta = torch.tensor(inputs.viscosity_1e6(X1, T1), device=dev)
+    del X1, T1
+    log("viscosity set up")
     sc.set_fields(eta)
     del eta
     out = {"workload": f"shell {args.n_tan}x{args.n_rad} ({60 * args.n_tan ** 2 * args.n_rad} macro-tets), "
                        f"level {args.level}, viscosity contrast 1e6", "N_u": Nu, "N_p": Np, "micro_tets": n_tets,
            "context_s": t_ctx}
     for dt_, name in ((torch.float64, "fp64"), (torch.float32, "fp32")):
-        x = torch.tensor(inputs.uniform(0, Nu), dtype=dt_, device=dev)
+        # a seeded vector drawn on the device (the host draw of 1.6e9 values is slow)
+        g = torch.Generator(device=dev)
+        g.manual_seed(0)
+        x = (2.0 * torch.rand(Nu, dtype=torch.float64, device=dev, generator=g) - 1.0).to(dt_)
         y = torch.empty_like(x)
         sc.time_apply_A(x, y, reps=2)
         free, total = torch.cuda.mem_get_info(dev)
@@ -637,17 +649,20 @@ def large_apply(args, sc, dev, Nu, Np, free_before, t_ctx):
 def contrast_study(args, sc, dev, Nu, Np):
     """Mixed-precision against all-FP64 solves to 1e-8 at viscosity contrast
     1e6 (Sec. 5.2.2: FP64 Chebyshev bounds, FP32 smoothing)."""
-    import numpy as np
     import torch
 
     import inputs
-    X2 = sc.coords(which=2)[0]
-    X1 = sc.coords(which=1)[0]
+    from paper_2506_04157_amd import default_params
     field = inputs.SHField(2)
-    eta1 = inputs.viscosity_1e6(X1, field.temperature(X1))
+    X1 = sc.coords(which=1)[0]
+    T1 = field.temperature_torch(torch.tensor(X1, device=dev)).cpu().numpy()
+    log("P1 temperature evaluated")
+    eta1 = inputs.viscosity_1e6(X1, T1)
+    log(f"viscosity: contrast {eta1.max() / eta1.min():.3e}")
     lnrho = torch.tensor(inputs.ln_density(X1), device=dev)
-    T2 = torch.tensor(field.temperature(X2), device=dev)
-    del X2, X1
+    del X1, T1
+    T2 = field.temperature_torch(torch.tensor(sc.coords(which=2)[0], device=dev)).contiguous()
+    log("P2 temperature evaluated")
     out = {"workload": f"shell {args.n_tan}x{args.n_rad} level {args.level}, N_u={Nu}, N_p={Np}",
            "eta_max_over_min": float(eta1.max() / eta1.min()), "eta_min": float(eta1.min()),
            "eta_max": float(eta1.max())}
@@ -669,6 +684,60 @@ def contrast_study(args, sc, dev, Nu, Np):
                             "u_rel_diff": (torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)).item(),
                             "p_rel_diff": (torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)).item()}
     print(json.dumps({"contrast_study": out}), flush=True)
+
+
+def schur_study(args, sc, dev, Nu, Np):
+    """Block preconditioners x Schur approximations on one synthetic shell
+    problem (the comparison of Sec. 7.4, Fig. SchurCompInit): FGMRES stopped at
+    an absolute residual of 1e-8, A-block tolerance 1e-2 for the symmetric
+    Uzawa and 1e-4 for the inexact and adjoint ones, Uzawa omega 0.0125 for
+    the weighted BFBT (the paper's best value in that test), a_r = 10, a_l = 1
+    for its asymmetric scaling; FP32 preconditioner inside FP64 FGMRES."""
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2506_04157_amd import default_params
+    from paper_2506_04157_amd._lib import (SCHUR_MASS, SCHUR_VBFBT, SCHUR_WBFBT, UZAWA_ADJOINT, UZAWA_INEXACT,
+                                           UZAWA_SYMMETRIC)
+    field = inputs.SHField(2)
+    X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
+    X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
+    mlog = (float(np.log(1e4)) * (0.5 - field.temperature_torch(X1))).contiguous()
+    lnrho = (0.5 * (1.0 - torch.linalg.norm(X1, dim=1))).contiguous()
+    T2 = field.temperature_torch(X2).contiguous()
+    del X1, X2
+    schurs = [("vbfbt", dict(schur=SCHUR_VBFBT)), ("mass", dict(schur=SCHUR_MASS)),
+              ("wbfbt", dict(schur=SCHUR_WBFBT, omega=0.0125)),
+              ("wbfbt_asym", dict(schur=SCHUR_WBFBT, omega=0.0125, a_r=10.0, a_l=1.0))]
+    uzawas = [("symmetric", dict(uzawa=UZAWA_SYMMETRIC, tol_A=1e-2)),
+              ("inexact", dict(uzawa=UZAWA_INEXACT, tol_A=1e-4)),
+              ("adjoint", dict(uzawa=UZAWA_ADJOINT, tol_A=1e-4))]
+    out = {"workload": f"shell {args.n_tan}x{args.n_rad} level {args.level}, N_u={Nu}, N_p={Np}, contrast 1e4",
+           "stop": "absolute residual 1e-8 or 100 FGMRES iterations", "runs": {}}
+    t0 = time.perf_counter()
+    f = None
+    for sname, skw in schurs:
+        for uname, ukw in uzawas:
+            kw = dict(precision=32, tol_rel=1e-30, tol_abs=1e-8, max_outer=100)
+            kw.update(skw)
+            kw.update(ukw)
+            prm = default_params(**kw)
+            sc.set_log_viscosity(mlog, lnrho, prm)
+            if f is None:
+                f = sc.rhs_buoyancy(T2)
+            u, p, rep = sc.solve(f, params=prm, allow_noconv=True)
+            torch.cuda.synchronize()
+            key = f"{uname}+{sname}"
+            out["runs"][key] = {k: rep[k] for k in ("iterations", "rel_residual", "abs_residual", "seconds",
+                                                    "a_cg_its", "s_cg_its", "mass_its")}
+            out["runs"][key]["history"] = rep["history"]
+            log(f"{key}: {rep['iterations']} its, abs {rep['abs_residual']:.2e}, {rep['seconds']:.1f}s")
+            if time.perf_counter() - t0 > args.budget:
+                out["stopped_early"] = True
+                print(json.dumps({"schur_study": out}), flush=True)
+                return
+    print(json.dumps({"schur_study": out}), flush=True)
 
 
 if __name__ == "__main__":

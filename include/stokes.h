@@ -88,11 +88,15 @@ typedef struct {
   int schur;           /* Schur approximation (Sec. 5.2.3): STK_SCHUR_VBFBT (eq. schurV,
                           default), STK_SCHUR_MASS (eq. schurMass, M_{1/eta} CG to
                           tol_invmass), STK_SCHUR_DIAG_BFBT (diag(A)-BFBT: the BFBT form
-                          with C = D = diag(A)) */
+                          with C = D = diag(A)), STK_SCHUR_WBFBT (the weighted BFBT,
+                          eq. schurWBFBT with its Poisson replacements) */
+  double a_l, a_r;     /* w-BFBT scalings of eta_l, eta_r near the Dirichlet boundary: 1, 1 */
+  double tol_wbfbt;    /* CG on the Poisson operators K_{1/sqrt eta}: 1e-10 (relative or absolute) */
+  double tol_vmass;    /* CG on the vector masses M_{sqrt eta}: 1e-4 */
 } stk_solver_params;
 
 enum { STK_UZAWA_SYMMETRIC = 0, STK_UZAWA_INEXACT = 1, STK_UZAWA_ADJOINT = 2 };
-enum { STK_SCHUR_VBFBT = 0, STK_SCHUR_MASS = 1, STK_SCHUR_DIAG_BFBT = 2 };
+enum { STK_SCHUR_VBFBT = 0, STK_SCHUR_MASS = 1, STK_SCHUR_DIAG_BFBT = 2, STK_SCHUR_WBFBT = 3 };
 
 typedef struct {
   int iterations;          /* FGMRES iterations */
@@ -202,6 +206,23 @@ int stk_apply_A_noalloc(stk_ctx* ctx, int level, int prec, const void* x, void* 
  * consistent mass with 1/eta_h at the quadrature points): q = M p, p and q
  * n_p1 values of `prec` on `level`; q overwritten. */
 int stk_apply_mass(stk_ctx* ctx, int level, int prec, const void* p, void* q);
+/* The operators of the weighted BFBT (Sec. 5.2.3, eq. schurWBFBT and the
+ * scaled viscosities eta_l, eta_r after it), for parity tests; fields must
+ * be set.  a > 0 scales eta by a^2 on the micro-tets that have a vertex on a
+ * Dirichlet boundary (the set D_eta).
+ * stk_apply_vmass: y = M_{sqrt eta} u on the finest level, the P2 vector mass
+ *   with weight sqrt(a^2 eta_h) at the points of a 27-point degree-5 rule;
+ *   u, y: 3 n_p2 values of `prec`, y overwritten; bc bits as for A.
+ * stk_apply_poisson: q = K_{1/sqrt eta} p on `level`, the P1 Poisson
+ *   (Neumann) operator with weight (a^2 eta_h)^{-1/2} (eta injected on the
+ *   coarse levels); p, q: n_p1(level) values of `prec`, q overwritten.
+ * stk_p1_transfer: the nested P1 prolongation from `level`-1 to `level`
+ *   (restrict = 0: in n_p1(level-1) values, out n_p1(level)) or its
+ *   transpose (restrict = 1), the transfers of the Poisson multigrid; out
+ *   overwritten. */
+int stk_apply_vmass(stk_ctx* ctx, int prec, double a, const void* u, void* y, int bc);
+int stk_apply_poisson(stk_ctx* ctx, int level, int prec, double a, const void* p, void* q);
+int stk_p1_transfer(stk_ctx* ctx, int level, int prec, int restrict_, const void* in, void* out);
 /* Sec. 5.2.2 (the Jacobi-Chebyshev smoother uses diag(A)): the diagonal of
  * A on `level` without projections, device output of 3 n_p2 doubles,
  * overwritten. */

@@ -64,12 +64,23 @@ def chebyshev_error_polynomial(lam, lo, hi, degree):
 
 def prolongation(coarse, fine):
     """Scalar P2 prolongation (n2_fine x n2_coarse): P[f, c] = phi_c(x~_f)."""
+    return _embedding(coarse, fine.x2, coarse.e2, p2_values, coarse.n2)
+
+
+def prolongation_p1(coarse, fine):
+    """Scalar P1 prolongation (n1_fine x n1_coarse): P[f, c] = psi_c(x~_f), the
+    nested P1 spaces of the Poisson multigrid in the weighted BFBT."""
+    return _embedding(coarse, fine.x1, coarse.e1, lambda lam: lam, coarse.n1)
+
+
+def _embedding(coarse, xf, enodes, basis, ncoarse):
+    """Coarse basis functions (values by `basis` of the barycentric
+    coordinates) evaluated at the reference points xf."""
     ev = coarse.ev                                              # (nec,4,3)
     T = np.stack([ev[:, 1] - ev[:, 0], ev[:, 2] - ev[:, 0], ev[:, 3] - ev[:, 0]], axis=2)
     Tinv = np.linalg.inv(T)
     cent = ev.mean(axis=1)
     tree = cKDTree(cent)
-    xf = fine.x2
     k = min(40, len(cent))
     _, cand = tree.query(xf, k=k)
     cand = cand.reshape(len(xf), k)
@@ -86,16 +97,16 @@ def prolongation(coarse, fine):
         idx = todo[ok]
         if len(idx) == 0:
             continue
-        N = p2_values(lam[ok])                                   # (n,10)
+        N = basis(lam[ok])                                       # (n, nodes per element)
         found[idx] = True
-        for a in range(10):
+        for a in range(N.shape[1]):
             rows.append(idx)
-            cols.append(coarse.e2[e[ok], a])
+            cols.append(enodes[e[ok], a])
             vals.append(N[:, a])
     assert found.all(), "fine node outside the coarse mesh"
     r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
     keep = np.abs(v) > 1e-14
-    return sp.csr_matrix((v[keep], (r[keep], c[keep])), shape=(fine.n2, coarse.n2))
+    return sp.csr_matrix((v[keep], (r[keep], c[keep])), shape=(len(xf), ncoarse))
 
 
 def vector_prolongation(Ps):

@@ -9,7 +9,7 @@ STK_OK, STK_EINVAL, STK_ENOMEM, STK_EHIP, STK_ENOCONV, STK_ENOTREADY = 0, -1, -2
 MESH_CUBE, MESH_SHELL = 0, 1
 BC_DIRICHLET, BC_FREESLIP = 1, 2
 UZAWA_SYMMETRIC, UZAWA_INEXACT, UZAWA_ADJOINT = 0, 1, 2
-SCHUR_VBFBT, SCHUR_MASS, SCHUR_DIAG_BFBT = 0, 1, 2
+SCHUR_VBFBT, SCHUR_MASS, SCHUR_DIAG_BFBT, SCHUR_WBFBT = 0, 1, 2, 3
 
 
 class MeshDesc(ctypes.Structure):
@@ -26,7 +26,8 @@ class SolverParams(ctypes.Structure):
                 ("deg_A", ctypes.c_int), ("m_V", ctypes.c_int), ("deg_V", ctypes.c_int),
                 ("max_inner", ctypes.c_int), ("use_Bbar", ctypes.c_int), ("power_its", ctypes.c_int),
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double), ("uzawa", ctypes.c_int),
-                ("schur", ctypes.c_int)]
+                ("schur", ctypes.c_int), ("a_l", ctypes.c_double), ("a_r", ctypes.c_double),
+                ("tol_wbfbt", ctypes.c_double), ("tol_vmass", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -66,6 +67,9 @@ SIGNATURES = {
     "stk_apply_K": [_CTX, _I, _P, _P, _P, _P, _I, _I],
     "stk_apply_A_noalloc": [_CTX, _I, _I, _P, _P, _I],
     "stk_apply_mass": [_CTX, _I, _I, _P, _P],
+    "stk_apply_vmass": [_CTX, _I, _D, _P, _P, _I],
+    "stk_apply_poisson": [_CTX, _I, _I, _D, _P, _P],
+    "stk_p1_transfer": [_CTX, _I, _I, _I, _P, _P],
     "stk_diag_A": [_CTX, _I, _P],
     "stk_cheb_bounds": [_CTX, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "stk_set_cheb_bounds": [_CTX, _I, _D, _D],

@@ -212,6 +212,31 @@ class StokesContext:
         check(self.lib.stk_apply_mass(self.h, level, _prec(p), a, _ptr(out)))
         return out
 
+    def apply_vmass(self, u, a=1.0, bc=3, out=None):
+        """M_{sqrt eta} u on the finest level (weighted BFBT), element factor a^2
+        on the micro-tets touching a Dirichlet boundary."""
+        out = torch.empty_like(u) if out is None else out
+        x = self._u(u, None, (torch.float64, torch.float32), "u")
+        check(self.lib.stk_apply_vmass(self.h, _prec(u), float(a), x, self._u(out, None, (u.dtype,), "out"), bc))
+        return out
+
+    def apply_poisson(self, p, level=None, a=1.0, out=None):
+        """K_{1/sqrt eta} p on `level` (the weighted BFBT's Poisson operator)."""
+        level = self.level if level is None else level
+        out = torch.empty_like(p) if out is None else out
+        x = self._p(p, level, (torch.float64, torch.float32), "p")
+        check(self.lib.stk_apply_poisson(self.h, level, _prec(p), float(a), x,
+                                         self._p(out, level, (p.dtype,), "out")))
+        return out
+
+    def p1_transfer(self, v, level, restrict=False):
+        """Nested P1 prolongation from level-1 to level (restrict: its transpose)."""
+        src, dst = (level, level - 1) if restrict else (level - 1, level)
+        x = self._p(v, src, (torch.float64, torch.float32), "v")
+        out = self.zeros_p(dst, v.dtype)
+        check(self.lib.stk_p1_transfer(self.h, level, _prec(v), int(bool(restrict)), x, _ptr(out)))
+        return out
+
     def diag_A(self, level=None):
         level = self.level if level is None else level
         out = self.zeros_u(level)

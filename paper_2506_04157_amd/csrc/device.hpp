@@ -169,8 +169,33 @@ void launch_mass_stencil_build(const LevelDev& L, const double* eta, double* c64
 // y = M_{1/eta} p with the assembled stencil; slots: nmacro * L.ms.nsh values
 template <typename R>
 void launch_mass_stencil(const LevelDev& L, const R* p, R* y, R* slots, hipStream_t s);
+// y = S p with any stencil of the M_{1/eta} layout (coefficients coef)
+template <typename R>
+void launch_stencil(const LevelDev& L, const R* coef, const R* p, R* y, R* slots, hipStream_t s);
 // LDS bytes of the stencil apply
 size_t mass_stencil_lds_bytes(int nloc1, int real_bytes);
+// weighted BFBT (eq. schurWBFBT): the P1 Poisson stencil K_{1/sqrt eta} with
+// the element factor a2 on the micro-tets touching a Dirichlet boundary
+void launch_poisson_stencil_build(const LevelDev& L, const double* eta, double a2, double* c64, float* c32,
+                                  hipStream_t s);
+// d = diagonal of a P1 stencil (overwritten)
+template <typename R>
+void launch_stencil_diag(const LevelDev& L, const double* c64, R* d, hipStream_t s);
+// nested P1 transfers between levels: ef = P ec, rc = P^T rf (both overwritten)
+template <typename R>
+void launch_p1_prolong(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, hipStream_t s);
+template <typename R>
+void launch_p1_restrict(const LevelDev& Lc, const LevelDev& Lf, const R* rf, R* rc, hipStream_t s);
+// 27-point conical-product rule of the vector mass: barycentric points, weights
+constexpr int VMASS_NQ = 27;
+struct VmassRule {
+  double lam[VMASS_NQ][4];
+  double w[VMASS_NQ];
+};
+// y = M_{sqrt eta} u (or its diagonal), y overwritten; bcmode & BCM_IN projects u
+template <typename R>
+void launch_vmass(const LevelDev& L, const VmassRule& qr, const R* eta, R a2, const R* u, R* y, bool diag, int bcmode,
+                  hipStream_t s);
 // coefficients per level: nmacro * NSTORE1 * (nloc1 + 1)
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s);
 void launch_gradient(const LevelDev& L, const double* eta, const double* u, const double* lam,
@@ -232,6 +257,9 @@ struct RotDev {
   const double* X;
   double gi[9];
 };
+// v -= mean(v) without a host round trip; partial: DOT_BLOCKS doubles
+template <typename R>
+void launch_remove_mean(R* v, long long n, double* partial, hipStream_t s);
 // v -= (G^-1 m) x X with m = sum_i X_i x v_i; partial: 3 * DOT_BLOCKS doubles
 template <typename R>
 void launch_rot_remove(const RotDev& rd, long long n2, R* v, double* partial, hipStream_t s);

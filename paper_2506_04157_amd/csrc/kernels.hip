@@ -960,16 +960,13 @@ __global__ __launch_bounds__(256) void k_mass_stencil_build(LevelDev L, const do
   }
 }
 
-template <typename R> __device__ __forceinline__ const R* mcoef_of(const LevelDev& L);
-template <> __device__ __forceinline__ const double* mcoef_of<double>(const LevelDev& L) { return L.ms.c64; }
-template <> __device__ __forceinline__ const float* mcoef_of<float>(const LevelDev& L) { return L.ms.c32; }
 
 // Apply: one workgroup per macro stages p of its P1 lattice in LDS and forms
 // each row of the stencil (FP64 sums in a fixed order); macro-interior rows
 // are final, macro-boundary rows go to slots summed by k_gather.
 template <typename R>
-__global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __restrict__ p, R* __restrict__ y,
-                                                      R* __restrict__ sl) {
+__global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __restrict__ coef, const R* __restrict__ p,
+                                                      R* __restrict__ y, R* __restrict__ sl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sp = reinterpret_cast<R*>(smem_raw);
   const int nloc = L.nloc1, mac = blockIdx.x;
@@ -978,7 +975,7 @@ __global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __res
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) sp[t] = p[l1[t]];
   if (threadIdx.x == 0) sp[nloc] = R(0);
   __syncthreads();
-  const R* c = mcoef_of<R>(L) + (size_t)mac * NSTORE1 * ld;
+  const R* c = coef + (size_t)mac * NSTORE1 * ld;
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
     double acc = (double)c[t] * (double)sp[t];
 #pragma unroll
@@ -990,6 +987,290 @@ __global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __res
     const int slot = L.ms.dst[t];
     if (slot < 0) y[l1[t]] = R(acc);
     else sl[(size_t)mac * L.ms.nsh + slot] = R(acc);
+  }
+}
+
+// ---- weighted BFBT operators (eq. schurWBFBT) -----------------------------------
+// Element factor s_K of the scaled viscosities eta_l, eta_r: a^2 on the
+// micro-tets that have a vertex on a Dirichlet boundary, 1 elsewhere.
+__device__ __forceinline__ bool touches_dirichlet(const uint8_t* bact, int type, int px, int py, int pz, int n) {
+  bool on = false;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], K = pz + c_toff[type][v][2];
+    on = on || bact[wmask(I, J, K, n)] == ACT_DIR;
+  }
+  return on;
+}
+
+// The P1 Poisson stencil K_{1/sqrt eta}: per (macro, local P1 node) the row
+// sum_K sum_q W_q (s_K eta_h(x_q))^{-1/2} grad psi_v . grad psi_w over the
+// micro-tets that contain the node, in the layout of the M_{1/eta} stencil.
+// Gradients are the physical ones of the blended element, J_B^{-T} grad lambda.
+template <bool BLEND>
+__global__ __launch_bounds__(256) void k_poisson_stencil_build(LevelDev L, const double* __restrict__ eta, double a2,
+                                                               double* __restrict__ c64, float* __restrict__ c32) {
+  const int nloc = L.nloc1, n = L.n;
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)nloc * L.nmacro) return;
+  const int mac = (int)(gid / nloc), t = (int)(gid - (long long)mac * nloc);
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * nloc;
+  const double* G = L.geo + (size_t)mac * 16;
+  const uint8_t* bact = L.bact + (size_t)mac * 16;
+  double acc[NDIR1D];
+#pragma unroll
+  for (int d = 0; d < NDIR1D; ++d) acc[d] = 0.0;
+  const int k1 = L.ms.inc_ptr[t + 1];
+  for (int k = L.ms.inc_ptr[t]; k < k1; ++k) {
+    const int2 e = L.ms.inc[k];
+    const unsigned ex = (unsigned)e.x;
+    const int type = ex & 7, px = (ex >> 3) & 1023, py = (ex >> 13) & 1023, pz = ex >> 23;
+    const int v = e.y & 3;
+    double et[4], set = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      et[w] = eta[l1[lloc(px + c_toff[type][w][0], py + c_toff[type][w][1], pz + c_toff[type][w][2], n)]];
+      set += et[w];
+    }
+    const double sK = touches_dirichlet(bact, type, px, py, pz, n) ? a2 : 1.0;
+    const double* TI = L.tinv + ((size_t)mac * 6 + type) * 10;
+    const double wdetF = QW * TI[9];
+    double gl[4][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      gl[1][r] = TI[r];
+      gl[2][r] = TI[3 + r];
+      gl[3][r] = TI[6 + r];
+      gl[0][r] = -(gl[1][r] + gl[2][r] + gl[3][r]);
+    }
+    double xv[4][3], xs[3] = {0.0, 0.0, 0.0};
+    if (BLEND) {
+      elem_vertices<double>(G, type, px, py, pz, n, xv);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) xs[r] = xv[0][r] + xv[1][r] + xv[2][r] + xv[3][r];
+    }
+    double kv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double xq[3] = {0.0, 0.0, 0.0};
+      if (BLEND) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) xq[r] = QB * xs[r] + (QA - QB) * xv[q][r];
+      }
+      QGeo<double, BLEND> geo;
+      geo.eval(G, xq, wdetF);
+      const double wq = geo.W / sqrt(sK * (QB * set + (QA - QB) * et[q]));
+      double gv[3] = {gl[v][0], gl[v][1], gl[v][2]};
+      geo.JinvT(gv);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        double gw[3] = {gl[w][0], gl[w][1], gl[w][2]};
+        geo.JinvT(gw);
+        kv[w] += wq * (gv[0] * gw[0] + gv[1] * gw[1] + gv[2] * gw[2]);
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int d = (e.y >> (2 + 4 * w)) & 15;
+#pragma unroll
+      for (int dd = 0; dd < NDIR1D; ++dd)
+        if (dd == d) acc[dd] += kv[w];
+    }
+  }
+  const size_t ld = (size_t)nloc + 1;
+#pragma unroll
+  for (int d = 0; d < NSTORE1; ++d) {
+    const size_t o = ((size_t)mac * NSTORE1 + d) * ld + t;
+    c64[o] = acc[d];
+    c32[o] = (float)acc[d];
+    if (t == 0) {
+      c64[o + nloc] = 0.0;
+      c32[o + nloc] = 0.0f;
+    }
+  }
+}
+
+// diagonal of a P1 stencil (coefficient of the node itself), summed over the
+// macros that share a node: per (macro, local node) an atomic add into a
+// zero-filled vector
+template <typename R>
+__global__ __launch_bounds__(256) void k_stencil_diag(LevelDev L, const double* __restrict__ c64, R* __restrict__ d) {
+  const int nloc = L.nloc1;
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)nloc * L.nmacro) return;
+  const int mac = (int)(gid / nloc), t = (int)(gid - (long long)mac * nloc);
+  const double v = c64[(size_t)mac * NSTORE1 * ((size_t)nloc + 1) + t];
+  gadd(d + L.l2g1[(size_t)mac * nloc + t], R(v));
+}
+
+// lattice point (I, J, K) of local index t on a lattice of side m (inverse of lloc)
+__device__ __forceinline__ void lattice_of(int t, int m, int& I, int& J, int& K) {
+  K = 0;
+  for (;;) {
+    const int s = m - K, cnt = (s + 1) * (s + 2) / 2;
+    if (t < cnt) break;
+    t -= cnt;
+    ++K;
+  }
+  const int s = m - K;
+  J = 0;
+  for (;;) {
+    const int len = s - J + 1;
+    if (t < len) break;
+    t -= len;
+    ++J;
+  }
+  I = t;
+}
+
+// Nested P1 spaces: a fine lattice point is a coarse vertex (all coordinates
+// even) or the midpoint of a coarse micro-tet edge, whose direction follows
+// from the pattern of odd coordinates (the seven edge directions of the
+// refinement: a, b, c, b - a, c - a, c - b and the octahedron diagonal
+// a - b + c).  MODE 0: out = P in (fine = coarse vertex value, or the mean of
+// the two edge ends); MODE 1: out += P^T in (out zero-filled by the caller).
+// One thread per (macro, fine lattice point); each fine node is handled by
+// the macro that owns it.
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_p1_transfer(LevelDev Lc, LevelDev Lf, const R* __restrict__ in,
+                                                     R* __restrict__ out) {
+  const int nlf = Lf.nloc1, nf = Lf.n, nc = Lc.n;
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)nlf * Lf.nmacro) return;
+  const int mac = (int)(gid / nlf), t = (int)(gid - (long long)mac * nlf);
+  int I, J, K;
+  lattice_of(t, nf, I, J, K);
+  const int mask = wmask(I, J, K, nf);
+  if (Lf.own[(size_t)mac * 16 + mask] == 0) return;
+  const size_t gf = Lf.l2g1[(size_t)mac * nlf + t];
+  const uint32_t* l2c = Lc.l2g1 + (size_t)mac * Lc.nloc1;
+  const int ox = I & 1, oy = J & 1, oz = K & 1;
+  if (!(ox | oy | oz)) {
+    const size_t gc = l2c[lloc(I >> 1, J >> 1, K >> 1, nc)];
+    if (MODE == 0) out[gf] = in[gc];
+    else gadd(out + gc, in[gf]);
+    return;
+  }
+  // edge direction by the pattern of odd coordinates: x (1,0,0), y (0,1,0),
+  // z (0,0,1), x+y (-1,1,0), x+z (-1,0,1), y+z (0,-1,1), x+y+z (1,-1,1)
+  const int dx = ox ? ((oy != oz) ? -1 : 1) : 0;
+  const int dy = oy ? (oz ? -1 : 1) : 0;
+  const int dz = oz;
+  const size_t g0 = l2c[lloc((I - dx) >> 1, (J - dy) >> 1, (K - dz) >> 1, nc)];
+  const size_t g1 = l2c[lloc((I + dx) >> 1, (J + dy) >> 1, (K + dz) >> 1, nc)];
+  if (MODE == 0) {
+    out[gf] = R(0.5) * (in[g0] + in[g1]);
+  } else {
+    const R h = R(0.5) * in[gf];
+    gadd(out + g0, h);
+    gadd(out + g1, h);
+  }
+}
+
+// The P2 vector mass M_{sqrt eta} with weight sqrt(s_K eta_h(x_q)) on the
+// 27-point conical-product rule (degree 5; the 4-point rule of the Stokes
+// blocks leaves a P2 mass singular).  One thread per micro-tet of the finest
+// level; DIAG: the diagonal (same in the three components), else y += M u
+// with the input projected (bcmode & BCM_IN) and global atomics into a
+// zero-filled y.
+template <typename R, bool BLEND, bool DIAG>
+__global__ __launch_bounds__(256) void k_vmass(LevelDev L, VmassRule qr, const R* __restrict__ eta, R a2,
+                                               const R* __restrict__ u, R* __restrict__ y, int bcmode) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int n = L.n, m2 = 2 * n;
+  const int ne = n * n * n;
+  if (gid >= (long long)ne * L.nmacro) return;
+  const int mac = (int)(gid / ne);
+  const int pk = L.eall[gid - (long long)mac * ne];
+  const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const R* G = geo_of<R>(L) + (size_t)mac * 16;
+  const uint8_t* bact = L.bact + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+  int I2[10], J2[10], K2[10];
+  size_t g2[10];
+  R et[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], K = pz + c_toff[type][v][2];
+    et[v] = eta[l1[lloc(I, J, K, n)]];
+    I2[v] = 2 * I;
+    J2[v] = 2 * J;
+    K2[v] = 2 * K;
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    I2[4 + ed] = (I2[i] + I2[j]) >> 1;
+    J2[4 + ed] = (J2[i] + J2[j]) >> 1;
+    K2[4 + ed] = (K2[i] + K2[j]) >> 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+  const R sK = touches_dirichlet(bact, type, px, py, pz, n) ? a2 : R(1);
+  R xv[4][3];
+  if (BLEND) elem_vertices<R>(G, type, px, py, pz, n, xv);
+  const R* TI = tinv_of<R>(L) + ((size_t)mac * 6 + type) * 10;
+  const R detF = TI[9];
+  R uv[3][10];
+  if (!DIAG) {
+#pragma unroll
+    for (int a = 0; a < 10; ++a) {
+      R v0 = u[g2[a]], v1 = u[g2[a] + N2], v2 = u[g2[a] + 2 * N2];
+      const int mask = wmask(I2[a], J2[a], K2[a], m2);
+      if ((bcmode & BCM_IN) && mask != 15) bc_project<R>(bact[mask], G, I2[a], J2[a], K2[a], m2, v0, v1, v2);
+      uv[0][a] = v0;
+      uv[1][a] = v1;
+      uv[2][a] = v2;
+    }
+  }
+  R acc[3][10];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 10; ++a) acc[c][a] = 0;
+  for (int q = 0; q < VMASS_NQ; ++q) {
+    const R l0 = R(qr.lam[q][0]), l1 = R(qr.lam[q][1]), l2v = R(qr.lam[q][2]), l3 = R(qr.lam[q][3]);
+    const R lam[4] = {l0, l1, l2v, l3};
+    R xq[3] = {0, 0, 0};
+    if (BLEND) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) xq[r] = l0 * xv[0][r] + l1 * xv[1][r] + l2v * xv[2][r] + l3 * xv[3][r];
+    }
+    QGeo<R, BLEND> geo;
+    geo.eval(G, xq, R(qr.w[q]) * detF);
+    const R cq = geo.W * sqrt(sK * (l0 * et[0] + l1 * et[1] + l2v * et[2] + l3 * et[3]));
+    R N[10];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) N[v] = lam[v] * (R(2) * lam[v] - R(1));
+#pragma unroll
+    for (int ed = 0; ed < 6; ++ed) N[4 + ed] = R(4) * lam[EV0(ed)] * lam[EV1(ed)];
+    if (DIAG) {
+#pragma unroll
+      for (int a = 0; a < 10; ++a) acc[0][a] += cq * N[a] * N[a];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R uq = 0;
+#pragma unroll
+        for (int a = 0; a < 10; ++a) uq += N[a] * uv[c][a];
+        uq *= cq;
+#pragma unroll
+        for (int a = 0; a < 10; ++a) acc[c][a] += uq * N[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) {
+    if (DIAG) {
+      gadd(y + g2[a], acc[0][a]);
+      gadd(y + g2[a] + N2, acc[0][a]);
+      gadd(y + g2[a] + 2 * N2, acc[0][a]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gadd(y + g2[a] + c * N2, acc[c][a]);
+    }
   }
 }
 
@@ -1783,6 +2064,31 @@ __device__ __forceinline__ void block_partials(double a, double b, double* pa, d
     pb[blockIdx.x] = red[1][0];
   }
 }
+// v -= mean(v) on the device: per-block partial sums of v, then every block of
+// the second kernel sums them itself (same order) and subtracts the mean
+template <typename R>
+__global__ __launch_bounds__(256) void k_sum_partials(const R* __restrict__ v, long long n, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double a = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a += (double)v[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_sub_mean(R* __restrict__ v, long long n, const double* __restrict__ partial,
+                                                  int np) {
+  __shared__ double red[256];
+  const double mean = block_sum(partial, np, red) / (double)n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    v[i] = R((double)v[i] - mean);
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_rot_remove(RotDev rd, long long n2, R* __restrict__ v,
                                                     const double* __restrict__ partial, int np) {
@@ -2431,16 +2737,25 @@ void launch_mass_stencil_build(const LevelDev& L, const double* eta, double* c64
   else hipLaunchKernelGGL((k_mass_stencil_build<false>), grid, dim3(256), 0, s, L, eta, c64, c32);
 }
 size_t mass_stencil_lds_bytes(int nloc1, int real_bytes) { return ((size_t)nloc1 + 1) * real_bytes; }
+template <typename R> static const R* mcoef_host(const LevelDev& L);
+template <> const double* mcoef_host<double>(const LevelDev& L) { return L.ms.c64; }
+template <> const float* mcoef_host<float>(const LevelDev& L) { return L.ms.c32; }
 template <typename R>
 void launch_mass_stencil(const LevelDev& L, const R* p, R* y, R* slots, hipStream_t s) {
+  launch_stencil<R>(L, mcoef_host<R>(L), p, y, slots, s);
+}
+template <typename R>
+void launch_stencil(const LevelDev& L, const R* coef, const R* p, R* y, R* slots, hipStream_t s) {
   hipLaunchKernelGGL((k_mass_stencil<R>), dim3((unsigned)L.nmacro), dim3(256),
-                     mass_stencil_lds_bytes(L.nloc1, sizeof(R)), s, L, p, y, slots);
+                     mass_stencil_lds_bytes(L.nloc1, sizeof(R)), s, L, coef, p, y, slots);
   if (L.ms.g.nnodes > 0)
     hipLaunchKernelGGL((k_gather<R, 1>), dim3((L.ms.g.nnodes + 255) / 256), dim3(256), 0, s, L.ms.g, slots,
                        (size_t)0, y, (size_t)0);
 }
 template void launch_mass_stencil<double>(const LevelDev&, const double*, double*, double*, hipStream_t);
 template void launch_mass_stencil<float>(const LevelDev&, const float*, float*, float*, hipStream_t);
+template void launch_stencil<double>(const LevelDev&, const double*, const double*, double*, double*, hipStream_t);
+template void launch_stencil<float>(const LevelDev&, const float*, const float*, float*, float*, hipStream_t);
 
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s) {
   dim3 grid((unsigned)(L.ntiles * L.nmacro));
@@ -2512,6 +2827,14 @@ void launch_rot_remove(const RotDev& rd, long long n2, R* v, double* partial, hi
   hipLaunchKernelGGL((k_rot_moment<R>), dim3(nb), dim3(256), 0, s, rd.X, v, n2, partial);
   hipLaunchKernelGGL((k_rot_remove<R>), dim3(nb), dim3(256), 0, s, rd, n2, v, partial, nb);
 }
+template <typename R>
+void launch_remove_mean(R* v, long long n, double* partial, hipStream_t s) {
+  const int nb = vgrid(n) < DOT_BLOCKS ? vgrid(n) : DOT_BLOCKS;
+  hipLaunchKernelGGL((k_sum_partials<R>), dim3(nb), dim3(256), 0, s, v, n, partial);
+  hipLaunchKernelGGL((k_sub_mean<R>), dim3(nb), dim3(256), 0, s, v, n, partial, nb);
+}
+template void launch_remove_mean<double>(double*, long long, double*, hipStream_t);
+template void launch_remove_mean<float>(float*, long long, double*, hipStream_t);
 template void launch_rot_remove<double>(const RotDev&, long long, double*, double*, hipStream_t);
 template void launch_rot_remove<float>(const RotDev&, long long, float*, double*, hipStream_t);
 template void launch_project<double>(const BcDev&, long long, double*, hipStream_t);
@@ -2557,6 +2880,55 @@ void vaxpy2_nrm(R a, const R* p, R* x, R b, const R* q, R* r, long long n, doubl
 void vsum_partials(double* partial, int np, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, np, out);
 }
+
+void launch_poisson_stencil_build(const LevelDev& L, const double* eta, double a2, double* c64, float* c32,
+                                  hipStream_t s) {
+  const long long nt = (long long)L.nloc1 * L.nmacro;
+  dim3 grid((unsigned)((nt + 255) / 256));
+  if (L.blend) hipLaunchKernelGGL((k_poisson_stencil_build<true>), grid, dim3(256), 0, s, L, eta, a2, c64, c32);
+  else hipLaunchKernelGGL((k_poisson_stencil_build<false>), grid, dim3(256), 0, s, L, eta, a2, c64, c32);
+}
+template <typename R>
+void launch_stencil_diag(const LevelDev& L, const double* c64, R* d, hipStream_t s) {
+  const long long nt = (long long)L.nloc1 * L.nmacro;
+  vfill<R>(d, R(0), L.n1, s);
+  hipLaunchKernelGGL((k_stencil_diag<R>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, L, c64, d);
+}
+template void launch_stencil_diag<double>(const LevelDev&, const double*, double*, hipStream_t);
+template void launch_stencil_diag<float>(const LevelDev&, const double*, float*, hipStream_t);
+template <typename R>
+void launch_p1_prolong(const LevelDev& Lc, const LevelDev& Lf, const R* ec, R* ef, hipStream_t s) {
+  const long long nt = (long long)Lf.nloc1 * Lf.nmacro;
+  hipLaunchKernelGGL((k_p1_transfer<R, 0>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, Lc, Lf, ec, ef);
+}
+template <typename R>
+void launch_p1_restrict(const LevelDev& Lc, const LevelDev& Lf, const R* rf, R* rc, hipStream_t s) {
+  const long long nt = (long long)Lf.nloc1 * Lf.nmacro;
+  vfill<R>(rc, R(0), Lc.n1, s);
+  hipLaunchKernelGGL((k_p1_transfer<R, 1>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, Lc, Lf, rf, rc);
+}
+template void launch_p1_prolong<double>(const LevelDev&, const LevelDev&, const double*, double*, hipStream_t);
+template void launch_p1_prolong<float>(const LevelDev&, const LevelDev&, const float*, float*, hipStream_t);
+template void launch_p1_restrict<double>(const LevelDev&, const LevelDev&, const double*, double*, hipStream_t);
+template void launch_p1_restrict<float>(const LevelDev&, const LevelDev&, const float*, float*, hipStream_t);
+template <typename R>
+void launch_vmass(const LevelDev& L, const VmassRule& qr, const R* eta, R a2, const R* u, R* y, bool diag, int bcmode,
+                  hipStream_t s) {
+  const long long tot = (long long)L.n * L.n * L.n * L.nmacro;
+  dim3 grid((unsigned)((tot + 255) / 256));
+  vfill<R>(y, R(0), 3 * L.n2, s);
+  if (L.blend) {
+    if (diag) hipLaunchKernelGGL((k_vmass<R, true, true>), grid, dim3(256), 0, s, L, qr, eta, a2, u, y, bcmode);
+    else hipLaunchKernelGGL((k_vmass<R, true, false>), grid, dim3(256), 0, s, L, qr, eta, a2, u, y, bcmode);
+  } else {
+    if (diag) hipLaunchKernelGGL((k_vmass<R, false, true>), grid, dim3(256), 0, s, L, qr, eta, a2, u, y, bcmode);
+    else hipLaunchKernelGGL((k_vmass<R, false, false>), grid, dim3(256), 0, s, L, qr, eta, a2, u, y, bcmode);
+  }
+}
+template void launch_vmass<double>(const LevelDev&, const VmassRule&, const double*, double, const double*, double*,
+                                   bool, int, hipStream_t);
+template void launch_vmass<float>(const LevelDev&, const VmassRule&, const float*, float, const float*, float*, bool,
+                                  int, hipStream_t);
 
 #define INST_V(R)                                                                  \
   template void vfill<R>(R*, R, long long, hipStream_t);                           \

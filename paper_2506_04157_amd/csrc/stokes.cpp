@@ -133,6 +133,17 @@ struct LevelData {
   template <class R> const R* dinvp() const;
   template <class R> R* sl2();
   template <class R> R* sl1();
+  // P1 Poisson stencils K_{1/sqrt eta} of the weighted BFBT (eq. schurWBFBT)
+  // for up to two element factors a^2, with their inverse diagonals
+  struct PoissonSet {
+    double a2 = -1.0;
+    int gen = -1;
+    DBuf<double> c64, dinv64;
+    DBuf<float> c32, dinv32;
+    template <class R> const R* coef() const;
+    template <class R> const R* dinv() const;
+  };
+  PoissonSet ps[2];
   // P2 temperature of the level (quadrature-point viscosity)
   DBuf<double> T2;
   DBuf<float> T2f;
@@ -145,6 +156,10 @@ struct LevelData {
   DBuf<int> c_iptr, c_pos;
   DBuf<uint8_t> c_act;
 };
+template <> const double* LevelData::PoissonSet::coef<double>() const { return c64.p; }
+template <> const float* LevelData::PoissonSet::coef<float>() const { return c32.p; }
+template <> const double* LevelData::PoissonSet::dinv<double>() const { return dinv64.p; }
+template <> const float* LevelData::PoissonSet::dinv<float>() const { return dinv32.p; }
 template <> Pool<double>& LevelData::pool<double>() { return p64; }
 template <> Pool<float>& LevelData::pool<float>() { return p32; }
 template <> Pool<double>& LevelData::ppool<double>() { return q64; }
@@ -181,9 +196,11 @@ template <> float* LevelData::msl<float>() {
 
 // indices into the per-level velocity work pools
 enum { W_B = 0, W_X, W_R, W_D, W_T, W_CG_R, W_CG_Z, W_CG_P, W_CG_Q, W_U0, W_U1, W_U2, W_U3, W_U4, W_U5,
+       W_VM_R, W_VM_Z, W_VM_P, W_VM_Q, W_VM_T, W_VM_Z2,
        W_F0, W_F1, W_F2, W_F3, W_C_R, W_C_Z, W_C_P, W_C_Q, W_C_B, W_C_X, W_PC0, W_PC1, W_C_Y };
 // pressure-size pools
-enum { Q_0 = 0, Q_1, Q_2, Q_3, Q_4, Q_5, Q_6, Q_7, Q_8, Q_9, Q_ONES, Q_MD, Q_U0, Q_U1, Q_F0, Q_F1, Q_F2, Q_F3 };
+enum { Q_0 = 0, Q_1, Q_2, Q_3, Q_4, Q_5, Q_6, Q_7, Q_8, Q_9, Q_ONES, Q_MD, Q_U0, Q_U1, Q_F0, Q_F1, Q_F2, Q_F3,
+       Q_P1T, Q_P1R, Q_P1B, Q_P1X, Q_P1C_R, Q_P1C_Z, Q_P1C_P, Q_P1C_Q, Q_PK_R, Q_PK_Z, Q_PK_P, Q_PK_Q, Q_WB1, Q_WB2 };
 
 }  // namespace
 
@@ -205,10 +222,21 @@ struct stk_ctx {
   hipEvent_t cgev[2] = {nullptr, nullptr};
   bool ready = false;
   bool has_rho = false;
+  // weighted BFBT: the vector mass rule, the field generation the cached
+  // operators belong to, and the inverse diagonals of the vector masses
+  VmassRule vrule{};
+  int field_gen = 0;
+  struct VmassDiag {
+    double a2 = -1.0;
+    int gen = -1;
+    DBuf<double> d64;
+    DBuf<float> d32;
+  } vmd[2];
   // free slip on both spheres: the rigid rotations are removed from the
   // finest-level velocities the solvers work with
   bool rot = false;
   DBuf<double> rotX, rotbuf;
+  DBuf<double> meanbuf;    // partial sums of the device-side mean removal
   RotDev rotd{};
   DBuf<double> lnrho;
   DBuf<float> lnrhof;
@@ -621,6 +649,197 @@ void schur_vbfbt(Ctx& c, const R* rp, R* out) {
   solve_SC<R>(c, y2, out);
 }
 
+// ---- weighted BFBT (Sec. 5.2.3, eq. schurWBFBT) -----------------------------------
+// The P1 Poisson stencil K_{1/sqrt eta} of level l for the element factor a2
+// (built for the current fields on first use; two factors per level kept).
+LevelData::PoissonSet& poisson_set(Ctx& c, int l, double a2) {
+  LevelData& L = c.at(l);
+  for (auto& p : L.ps)
+    if (p.a2 == a2 && p.gen == c.field_gen) return p;
+  REQUIRE(L.d.ms.on, "the P1 stencil layout is not available on this level");
+  LevelData::PoissonSet& P = L.ps[0].gen != c.field_gen ? L.ps[0] : L.ps[1];
+  const size_t nc = (size_t)L.d.nmacro * NSTORE1 * (L.h.nloc1 + 1);
+  P.c64.alloc(nc);
+  P.c32.alloc(nc);
+  P.dinv64.alloc(L.h.n1);
+  P.dinv32.alloc(L.h.n1);
+  launch_poisson_stencil_build(L.d, L.eta.p, a2, P.c64.p, P.c32.p, c.s);
+  launch_stencil_diag<double>(L.d, P.c64.p, P.dinv64.p, c.s);
+  vinvert<double>(P.dinv64.p, P.dinv64.p, L.h.n1, c.s);
+  vconvert<double, float>(P.dinv64.p, P.dinv32.p, L.h.n1, c.s);
+  P.a2 = a2;
+  P.gen = c.field_gen;
+  return P;
+}
+
+template <class R>
+void apply_poisson(Ctx& c, int l, const LevelData::PoissonSet& P, const R* p, R* q) {
+  LevelData& L = c.at(l);
+  launch_stencil<R>(L.d, P.coef<R>(), p, q, L.msl<R>(), c.s);
+}
+
+// Multigrid V-cycle for the Poisson problem on nested P1 spaces: damped Jacobi
+// smoothing (WB_SMOOTH sweeps before and after, weight WB_OMEGA), restriction
+// P^T, coarse Jacobi-CG to WB_COARSE_TOL, prolongation P; x overwritten.  The
+// Neumann operator is singular with the constants as kernel; a right-hand side
+// of zero sum stays so under P^T (the rows of P sum to one), so the coarse
+// problems are consistent.
+constexpr int WB_SMOOTH = 2;
+constexpr double WB_OMEGA = 0.6;
+// coarse CG tolerance: the Neumann problem is consistent only up to the
+// rounding of the restriction, so FP32 stops well above its unit roundoff
+template <class R> constexpr double wb_coarse_tol() { return sizeof(R) == 8 ? 1e-10 : 1e-5; }
+template <class R>
+void vcycle_p1(Ctx& c, int l, double a2, const R* b, R* x) {
+  LevelData& L = c.at(l);
+  const long long n1 = L.h.n1;
+  const LevelData::PoissonSet& P = poisson_set(c, l, a2);
+  Pool<R>& Q = L.ppool<R>();
+  auto K = [&](const R* v, R* y) { apply_poisson<R>(c, l, P, v, y); };
+  if (l == c.lmin()) {
+    R* r = Q.get(Q_P1C_R, n1, c.s);
+    R* z = Q.get(Q_P1C_Z, n1, c.s);
+    R* p = Q.get(Q_P1C_P, n1, c.s);
+    R* q = Q.get(Q_P1C_Q, n1, c.s);
+    const int its = dev_pcg<R>(
+        c, n1, K, [&](R* v) { launch_remove_mean<R>(v, n1, c.meanbuf.p, c.s); }, P.dinv<R>(), b, x, r, z, p, q,
+        wb_coarse_tol<R>(), c.par.max_inner * 10, 4);
+    if (c.rep) c.rep->coarse_its += its;
+    return;
+  }
+  LevelData& C = c.at(l - 1);
+  R* t = Q.get(Q_P1T, n1, c.s);
+  R* r = Q.get(Q_P1R, n1, c.s);
+  R* bc = C.ppool<R>().get(Q_P1B, C.h.n1, c.s);
+  R* xc = C.ppool<R>().get(Q_P1X, C.h.n1, c.s);
+  const R* dinv = P.dinv<R>();
+  vcheb_one<R>(b, nullptr, dinv, R(WB_OMEGA), x, false, n1, c.s);   // x = w D^-1 b
+  for (int k = 1; k < WB_SMOOTH; ++k) {
+    K(x, t);
+    vcheb_one<R>(b, t, dinv, R(WB_OMEGA), x, true, n1, c.s);        // x += w D^-1 (b - K x)
+  }
+  K(x, t);
+  vsub<R>(b, t, r, n1, c.s);
+  launch_p1_restrict<R>(C.d, L.d, r, bc, c.s);
+  vcycle_p1<R>(c, l - 1, a2, bc, xc);
+  launch_p1_prolong<R>(C.d, L.d, xc, t, c.s);
+  vaxpy<R>(R(1), t, x, n1, c.s);
+  for (int k = 0; k < WB_SMOOTH; ++k) {
+    K(x, t);
+    vcheb_one<R>(b, t, dinv, R(WB_OMEGA), x, true, n1, c.s);
+  }
+}
+
+// K_{1/sqrt eta}^-1 b on the finest level: CG preconditioned by the P1
+// V-cycle, stopped at |r| <= tol_wbfbt |r0| or |r| <= tol_wbfbt (whichever
+// comes first, Table parametertable); b and x of arithmetic mean zero.
+template <class R>
+void solve_poisson(Ctx& c, double a2, const R* b, R* x) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long n1 = L.h.n1;
+  const LevelData::PoissonSet& P = poisson_set(c, l, a2);
+  Pool<R>& Q = L.ppool<R>();
+  R* r = Q.get(Q_PK_R, n1, c.s);
+  R* z = Q.get(Q_PK_Z, n1, c.s);
+  R* p = Q.get(Q_PK_P, n1, c.s);
+  R* q = Q.get(Q_PK_Q, n1, c.s);
+  vfill<R>(x, R(0), n1, c.s);
+  vcopy<R>(b, r, n1, c.s);
+  project_mean<R>(c, r);
+  const double nb = nrm2<R>(c, r, n1);
+  if (c.rep) c.rep->s_solves++;
+  if (nb == 0.0) return;
+  const double stop = std::max(c.par.tol_wbfbt * nb, c.par.tol_wbfbt);
+  vcycle_p1<R>(c, l, a2, r, z);
+  project_mean<R>(c, z);
+  vcopy<R>(z, p, n1, c.s);
+  double rz = dot<R>(c, r, z, n1);
+  for (int it = 1; it <= c.par.max_inner * 10; ++it) {
+    if (c.rep) c.rep->s_cg_its++;
+    apply_poisson<R>(c, l, P, p, q);
+    const double alpha = rz / dot<R>(c, p, q, n1);
+    cg_step_nrm<R>(c, alpha, p, x, q, r, n1);
+    // K p sums to zero only up to rounding: keep r free of the constant, or
+    // the recurrence stalls at the rounding level (FP32)
+    launch_remove_mean<R>(r, n1, c.meanbuf.p, c.s);
+    if (nrm2<R>(c, r, n1) <= stop) break;
+    vcycle_p1<R>(c, l, a2, r, z);
+    project_mean<R>(c, z);
+    const double rz2 = dot<R>(c, r, z, n1);
+    vaxpby<R>(R(1), z, R(rz2 / rz), p, n1, c.s);
+    rz = rz2;
+  }
+  project_mean<R>(c, x);
+}
+
+// The inverse diagonal of the vector mass M_{sqrt eta} for the factor a2
+Ctx::VmassDiag& vmass_diag(Ctx& c, double a2) {
+  for (auto& d : c.vmd)
+    if (d.a2 == a2 && d.gen == c.field_gen) return d;
+  Ctx::VmassDiag& D = c.vmd[0].gen != c.field_gen ? c.vmd[0] : c.vmd[1];
+  LevelData& L = c.at(c.L());
+  const long long N = 3 * L.h.n2;
+  D.d64.alloc(N);
+  D.d32.alloc(N);
+  launch_vmass<double>(L.d, c.vrule, L.eta.p, a2, nullptr, D.d64.p, true, 0, c.s);
+  vinvert<double>(D.d64.p, D.d64.p, N, c.s);
+  vconvert<double, float>(D.d64.p, D.d32.p, N, c.s);
+  D.a2 = a2;
+  D.gen = c.field_gen;
+  return D;
+}
+
+// y = P M_{sqrt eta} P u on the finest level
+template <class R>
+void apply_vmass(Ctx& c, double a2, const R* u, R* y) {
+  LevelData& L = c.at(c.L());
+  launch_vmass<R>(L.d, c.vrule, L.etap<R>(), R(a2), u, y, false, BCM_IN, c.s);
+  project<R>(c, c.L(), y);
+}
+
+// M_{sqrt eta}^-1 b on the admissible velocities: Jacobi-CG to tol_vmass
+template <class R>
+void solve_vmass(Ctx& c, double a2, const R* b, R* x) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2;
+  Ctx::VmassDiag& D = vmass_diag(c, a2);
+  const R* dinv = std::is_same<R, double>::value ? (const R*)D.d64.p : (const R*)D.d32.p;
+  Pool<R>& P = L.pool<R>();
+  R* r = P.get(W_VM_R, N, c.s);
+  R* z = P.get(W_VM_Z, N, c.s);
+  R* p = P.get(W_VM_P, N, c.s);
+  R* q = P.get(W_VM_Q, N, c.s);
+  const int its = dev_pcg<R>(
+      c, N, [&](const R* v, R* y) { apply_vmass<R>(c, a2, v, y); }, [&](R* v) { project<R>(c, l, v); }, dinv, b, x,
+      r, z, p, q, c.par.tol_vmass, c.par.max_inner * 10, 4);
+  if (c.rep) c.rep->mass_its += its;
+}
+
+// eq. schurWBFBT with the Poisson replacements and the scaled viscosities:
+// out = K_{1/sqrt eta_l}^-1 B M_{sqrt eta_l}^-1 A M_{sqrt eta_r}^-1 B^T K_{1/sqrt eta_r}^-1 rp
+template <class R>
+void schur_wbfbt(Ctx& c, const R* rp, R* out) {
+  const int l = c.L();
+  LevelData& L = c.at(l);
+  const long long N = 3 * L.h.n2, n1 = L.h.n1;
+  const double a2l = c.par.a_l * c.par.a_l, a2r = c.par.a_r * c.par.a_r;
+  R* y1 = L.ppool<R>().get(Q_WB1, n1, c.s);
+  R* y2 = L.ppool<R>().get(Q_WB2, n1, c.s);
+  R* t = L.pool<R>().get(W_VM_T, N, c.s);
+  R* z = L.pool<R>().get(W_VM_Z2, N, c.s);
+  solve_poisson<R>(c, a2r, rp, y1);
+  applyBt<R>(c, l, y1, t, false, BCM_OUT);
+  solve_vmass<R>(c, a2r, t, z);
+  applyA<R>(c, l, z, t, BCM_IN | BCM_OUT);
+  if (c.rot) rot_remove<R>(c, t);
+  solve_vmass<R>(c, a2l, t, z);
+  applyB<R>(c, l, z, y2, false, BCM_IN);
+  project_mean<R>(c, y2);
+  solve_poisson<R>(c, a2l, y2, out);
+}
+
 // S^-1 of the chosen approximation (Sec. 5.2.3) applied to a mean-zero rp
 template <class R>
 void schur_inv(Ctx& c, const R* rp, R* out) {
@@ -628,6 +847,8 @@ void schur_inv(Ctx& c, const R* rp, R* out) {
     solve_mass<R>(c, rp, out);   // eq. schurMass
     project_mean<R>(c, out);
     if (c.rep) c.rep->s_solves++;
+  } else if (c.par.schur == STK_SCHUR_WBFBT) {
+    schur_wbfbt<R>(c, rp, out);   // eq. schurWBFBT
   } else {
     schur_vbfbt<R>(c, rp, out);   // eq. schurV, or the diag(A)-BFBT
   }
@@ -1059,7 +1280,106 @@ void check_params(const stk_solver_params* p) {
   REQUIRE(p->cheb_lo > 0 && p->cheb_hi > p->cheb_lo, "bad Chebyshev interval factors");
   REQUIRE(p->max_inner >= 1 && p->max_outer >= 1 && p->power_its >= 1, "iteration caps must be >= 1");
   REQUIRE(p->uzawa >= STK_UZAWA_SYMMETRIC && p->uzawa <= STK_UZAWA_ADJOINT, "unknown Uzawa variant");
-  REQUIRE(p->schur >= STK_SCHUR_VBFBT && p->schur <= STK_SCHUR_DIAG_BFBT, "unknown Schur approximation");
+  REQUIRE(p->schur >= STK_SCHUR_VBFBT && p->schur <= STK_SCHUR_WBFBT, "unknown Schur approximation");
+  if (p->schur == STK_SCHUR_WBFBT)
+    REQUIRE(p->a_l > 0 && p->a_r > 0 && p->tol_wbfbt > 0 && p->tol_vmass > 0,
+            "w-BFBT needs a_l, a_r, tol_wbfbt, tol_vmass > 0");
+}
+
+// Gauss-Jacobi rule with k points for the weight (1 - x)^alpha on [-1, 1]
+// (Golub-Welsch: the nodes are the eigenvalues of the Jacobi matrix of the
+// three-term recurrence, the weights mu0 times the squared first eigenvector
+// components), eigenvalues by cyclic Jacobi rotations.
+void gauss_jacobi(int k, double alpha, double* x, double* w) {
+  const double beta = 0.0, ab = alpha + beta;
+  std::vector<double> J((size_t)k * k, 0.0), V((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    const double d = 2.0 * i + ab;
+    J[(size_t)i * k + i] = (i == 0) ? (beta - alpha) / (ab + 2.0) : (beta * beta - alpha * alpha) / (d * (d + 2.0));
+    if (i > 0) {
+      const double b = std::sqrt(4.0 * i * (i + alpha) * (i + beta) * (i + ab) / (d * d * (d + 1.0) * (d - 1.0)));
+      J[(size_t)i * k + i - 1] = J[(size_t)(i - 1) * k + i] = b;
+    }
+    V[(size_t)i * k + i] = 1.0;
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += J[(size_t)p * k + q] * J[(size_t)p * k + q];
+    if (off < 1e-32) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = J[(size_t)p * k + q];
+        if (apq == 0.0) continue;
+        const double theta = (J[(size_t)q * k + q] - J[(size_t)p * k + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int r = 0; r < k; ++r) {   // J <- J G (columns p, q)
+          const double jp = J[(size_t)r * k + p], jq = J[(size_t)r * k + q];
+          J[(size_t)r * k + p] = cs * jp - sn * jq;
+          J[(size_t)r * k + q] = sn * jp + cs * jq;
+        }
+        for (int r = 0; r < k; ++r) {   // J <- G^T J (rows p, q)
+          const double jp = J[(size_t)p * k + r], jq = J[(size_t)q * k + r];
+          J[(size_t)p * k + r] = cs * jp - sn * jq;
+          J[(size_t)q * k + r] = sn * jp + cs * jq;
+        }
+        for (int r = 0; r < k; ++r) {   // V <- V G
+          const double vp = V[(size_t)r * k + p], vq = V[(size_t)r * k + q];
+          V[(size_t)r * k + p] = cs * vp - sn * vq;
+          V[(size_t)r * k + q] = sn * vp + cs * vq;
+        }
+      }
+  }
+  const double mu0 = std::pow(2.0, ab + 1.0) * std::tgamma(alpha + 1.0) * std::tgamma(beta + 1.0) / std::tgamma(ab + 2.0);
+  for (int i = 0; i < k; ++i) {
+    x[i] = J[(size_t)i * k + i];
+    w[i] = mu0 * V[i] * V[i];   // first row of the eigenvector matrix
+  }
+}
+
+// The 27-point conical-product rule on the reference tetrahedron (3 Gauss-
+// Jacobi points with weights (1 - u)^2, (1 - u), 1 per collapsed direction;
+// exact to degree 5), as barycentric points; checked against the monomial
+// integrals a! b! c! / (a + b + c + 3)! up to degree 5.
+VmassRule make_vmass_rule() {
+  double u[3][3], wu[3][3];
+  const double alphas[3] = {2.0, 1.0, 0.0};
+  for (int d = 0; d < 3; ++d) {
+    double x[3], w[3];
+    gauss_jacobi(3, alphas[d], x, w);
+    for (int i = 0; i < 3; ++i) {
+      u[d][i] = 0.5 * (1.0 + x[i]);
+      wu[d][i] = w[i] / std::pow(2.0, alphas[d] + 1.0);
+    }
+  }
+  VmassRule r{};
+  int q = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k, ++q) {
+        const double x1 = u[0][i], x2 = (1.0 - u[0][i]) * u[1][j], x3 = (1.0 - u[0][i]) * (1.0 - u[1][j]) * u[2][k];
+        r.lam[q][0] = 1.0 - x1 - x2 - x3;
+        r.lam[q][1] = x1;
+        r.lam[q][2] = x2;
+        r.lam[q][3] = x3;
+        r.w[q] = wu[0][i] * wu[1][j] * wu[2][k];
+      }
+  auto fact = [](int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+  };
+  for (int a = 0; a <= 5; ++a)
+    for (int b = 0; a + b <= 5; ++b)
+      for (int c = 0; a + b + c <= 5; ++c) {
+        double sum = 0.0;
+        for (int p = 0; p < VMASS_NQ; ++p)
+          sum += r.w[p] * std::pow(r.lam[p][1], a) * std::pow(r.lam[p][2], b) * std::pow(r.lam[p][3], c);
+        const double exact = fact(a) * fact(b) * fact(c) / fact(a + b + c + 3);
+        REQUIRE(std::fabs(sum - exact) <= 1e-14, "vector-mass quadrature rule failed its exactness check");
+      }
+  return r;
 }
 
 // power iteration for lambda_max(D^-1 A) with projections, FP64
@@ -1097,6 +1417,7 @@ double power_lambda(Ctx& c, int l, int its) {
 void set_fields_internal(Ctx& c, const double* eta, const double* lnrho, const stk_solver_params* par) {
   check_params(par);
   c.par = *par;
+  ++c.field_gen;   // the weighted-BFBT operators of earlier fields are stale
   const int Lf = c.L();
   LevelData& F = c.at(Lf);
   const long long n1 = F.h.n1;
@@ -1277,6 +1598,10 @@ void stk_default_params(stk_solver_params* p) {
   p->power_its = 15;
   p->cheb_lo = 0.12;
   p->cheb_hi = 1.2;
+  p->a_l = 1.0;
+  p->a_r = 1.0;
+  p->tol_wbfbt = 1e-10;
+  p->tol_vmass = 1e-4;
 }
 
 int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
@@ -1306,6 +1631,7 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
     c->desc = *desc;
     c->s = (hipStream_t)hip_stream;
     HIPCHK(hipGetDevice(&c->device));
+    c->vrule = make_vmass_rule();
     HIPCHK(noalloc_scratch_init(c->device));   // address of this GPU's fixed scratch array
     c->mm = desc->kind == STK_MESH_CUBE ? make_cube() : make_shell(desc->n_tan, desc->n_rad, desc->r_in, desc->r_out);
     c->top = build_topology(c->mm);
@@ -1359,6 +1685,7 @@ int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
       c->rot = true;
     }
     c->dotbuf.alloc(2 * DOT_BLOCKS + 8);
+    c->meanbuf.alloc(DOT_BLOCKS);
     c->cgbuf.alloc(16);
     c->cgpart.alloc(5 * DOT_BLOCKS);
     HIPCHK(hipHostMalloc((void**)&c->hpin, 64, hipHostMallocDefault));
@@ -1520,6 +1847,52 @@ int stk_apply_mass(stk_ctx* ctx, int level, int prec, const void* p, void* q) {
     REQUIRE(p && q, "null vector");
     PREC_DISPATCH(prec, applyMass<double>(*ctx, level, (const double*)p, (double*)q),
                   applyMass<float>(*ctx, level, (const float*)p, (float*)q));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_vmass(stk_ctx* ctx, int prec, double a, const void* u, void* y, int bc) {
+  return guard([&] {
+    need_ready(ctx);
+    REQUIRE(u && y, "null vector");
+    REQUIRE(a > 0 && std::isfinite(a), "a must be positive");
+    LevelData& L = ctx->at(ctx->L());
+    PREC_DISPATCH(prec,
+                  (launch_vmass<double>(L.d, ctx->vrule, L.etap<double>(), a * a, (const double*)u, (double*)y, false,
+                                        bc & BCM_IN, ctx->s),
+                   (bc & BCM_OUT) ? launch_project<double>(L.bc, L.h.n2, (double*)y, ctx->s) : (void)0),
+                  (launch_vmass<float>(L.d, ctx->vrule, L.etap<float>(), (float)(a * a), (const float*)u, (float*)y,
+                                       false, bc & BCM_IN, ctx->s),
+                   (bc & BCM_OUT) ? launch_project<float>(L.bc, L.h.n2, (float*)y, ctx->s) : (void)0));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_apply_poisson(stk_ctx* ctx, int level, int prec, double a, const void* p, void* q) {
+  return guard([&] {
+    need_ready(ctx);
+    check_level(ctx, level);
+    REQUIRE(p && q, "null vector");
+    REQUIRE(a > 0 && std::isfinite(a), "a must be positive");
+    const LevelData::PoissonSet& P = poisson_set(*ctx, level, a * a);
+    PREC_DISPATCH(prec, apply_poisson<double>(*ctx, level, P, (const double*)p, (double*)q),
+                  apply_poisson<float>(*ctx, level, P, (const float*)p, (float*)q));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_p1_transfer(stk_ctx* ctx, int level, int prec, int restrict_, const void* in, void* out) {
+  return guard([&] {
+    REQUIRE(ctx && in && out, "null argument");
+    check_level(ctx, level);
+    REQUIRE(level > ctx->lmin(), "P1 transfer needs level > min_level");
+    LevelData &C = ctx->at(level - 1), &F = ctx->at(level);
+    if (restrict_)
+      PREC_DISPATCH(prec, launch_p1_restrict<double>(C.d, F.d, (const double*)in, (double*)out, ctx->s),
+                    launch_p1_restrict<float>(C.d, F.d, (const float*)in, (float*)out, ctx->s));
+    else
+      PREC_DISPATCH(prec, launch_p1_prolong<double>(C.d, F.d, (const double*)in, (double*)out, ctx->s),
+                    launch_p1_prolong<float>(C.d, F.d, (const float*)in, (float*)out, ctx->s));
     HIPCHK(hipGetLastError());
   });
 }

@@ -11,15 +11,17 @@ assembled system.
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
+import torch
 
 import inputs
-from oracle.fem import assemble_A, assemble_B, assemble_M_inv_eta, rhs_buoyancy
-from oracle.solvers import adjoint_uzawa, inexact_uzawa, symmetric_uzawa
+from oracle.fem import (assemble_A, assemble_B, assemble_M_inv_eta, assemble_poisson_p1, assemble_vector_mass,
+                        dirichlet_element_scale, rhs_buoyancy)
+from oracle.solvers import adjoint_uzawa, inexact_uzawa, prolongation_p1, symmetric_uzawa, wbfbt
 from oracle.system import solve_stokes
 from paper_2506_04157_amd import default_params
-from paper_2506_04157_amd._lib import (SCHUR_DIAG_BFBT, SCHUR_MASS, SCHUR_VBFBT, UZAWA_ADJOINT, UZAWA_INEXACT,
-                                       UZAWA_SYMMETRIC)
-from tests._util import Pair, relerr
+from paper_2506_04157_amd._lib import (SCHUR_DIAG_BFBT, SCHUR_MASS, SCHUR_VBFBT, SCHUR_WBFBT, UZAWA_ADJOINT,
+                                       UZAWA_INEXACT, UZAWA_SYMMETRIC)
+from tests._util import Pair, relerr, rowerr
 
 pytestmark = pytest.mark.gpu
 
@@ -81,13 +83,16 @@ def test_preconditioner_step_matches_oracle(shell, variant, transpose):
 
 
 @pytest.mark.parametrize("variant,schur", [(UZAWA_INEXACT, SCHUR_VBFBT), (UZAWA_ADJOINT, SCHUR_VBFBT),
-                                           (UZAWA_SYMMETRIC, SCHUR_MASS), (UZAWA_SYMMETRIC, SCHUR_DIAG_BFBT)])
+                                           (UZAWA_SYMMETRIC, SCHUR_MASS), (UZAWA_SYMMETRIC, SCHUR_DIAG_BFBT),
+                                           (UZAWA_SYMMETRIC, SCHUR_WBFBT), (UZAWA_ADJOINT, SCHUR_WBFBT)])
 def test_solve_with_variant_reaches_tolerance(shell, variant, schur):
     d = shell
     P, m = d["P"], d["m"]
     T = d["field"].temperature(m.X2)
     f = rhs_buoyancy(m, T)
-    params = default_params(tol_rel=1e-9, precision=32, uzawa=variant, schur=schur, max_outer=300)
+    # the weighted BFBT with the Uzawa weight the paper found best for it (Sec. 7.4)
+    extra = dict(omega=0.0125) if schur == SCHUR_WBFBT else {}
+    params = default_params(tol_rel=1e-9, precision=32, uzawa=variant, schur=schur, max_outer=300, **extra)
     P.ctx.set_fields(P.p_to_lib(d["eta"]), P.p_to_lib(d["lnrho"]), params=params)
     u, p, rep = P.ctx.solve(P.u_to_lib(f), params=params)
     print(variant, schur, rep["iterations"], rep["rel_residual"])
@@ -101,3 +106,76 @@ def test_solve_with_variant_reaches_tolerance(shell, variant, schur):
     assert np.hypot(np.linalg.norm(ru), np.linalg.norm(rp)) <= 2e-9 * np.linalg.norm(Pm @ f)
     uo, po, _ = solve_stokes(A, Bb, f, np.zeros(m.n1), Q, Bt=B.T)
     assert relerr(ug, uo) < 1e-5 and relerr(pg, po) < 1e-5
+
+
+def test_wbfbt_operators_match_oracle(shell):
+    """The weighted BFBT's operators (eq. schurWBFBT) against the oracle's
+    assembly: the sqrt(eta) vector mass (with and without the projections,
+    element factor a^2 = 9 on the micro-tets touching the no-slip sphere), the
+    1/sqrt(eta) Poisson operator on every level (eta injected), and the nested
+    P1 transfers; FP64 1e-12 and FP32 1e-5 in norm, 1e-13 / 1e-5 per entry."""
+    d = shell
+    P, m = d["P"], d["m"]
+    P.ctx.set_fields(P.p_to_lib(d["eta"]), P.p_to_lib(d["lnrho"]))
+    a = 3.0
+    Pu, _ = P.projector()
+    M = assemble_vector_mass(m, d["eta"], dirichlet_element_scale(m, P.dir_flags, a))
+    x = inputs.uniform(31, 3 * m.n2)
+    for dtype, tol, rt in [(torch.float64, 1e-12, 1e-13), (torch.float32, 1e-5, 1e-5)]:
+        y = P.u_to_or(P.ctx.apply_vmass(P.u_to_lib(x, dtype=dtype), a=a, bc=0))
+        assert relerr(y, M @ x) < tol and rowerr(y, M @ x, abs(M) @ abs(x)) < rt
+        y = P.u_to_or(P.ctx.apply_vmass(P.u_to_lib(x, dtype=dtype), a=a, bc=3))
+        ref = Pu @ (M @ (Pu @ x))
+        assert relerr(y, ref) < tol and rowerr(y, ref, abs(Pu) @ (abs(M) @ (abs(Pu) @ abs(x)))) < rt
+    from scipy.spatial import cKDTree
+    for l, ml in P.meshes.items():
+        eta_l = d["eta"][cKDTree(m.X1).query(ml.X1)[1]]     # nodal injection
+        K = assemble_poisson_p1(ml, eta_l, dirichlet_element_scale(ml, P.dir_flags, 2.0))
+        p = inputs.uniform(32 + l, ml.n1)
+        for dtype, tol, rt in [(torch.float64, 1e-12, 1e-13), (torch.float32, 1e-5, 1e-5)]:
+            q = P.p_to_or(P.ctx.apply_poisson(P.p_to_lib(p, l, dtype), level=l, a=2.0), l)
+            assert relerr(q, K @ p) < tol and rowerr(q, K @ p, abs(K) @ abs(p)) < rt, (l, dtype)
+        if l > min(P.meshes):
+            Pro = prolongation_p1(P.meshes[l - 1], ml)
+            ec = inputs.uniform(40 + l, P.meshes[l - 1].n1)
+            for dtype, tol in [(torch.float64, 4e-15), (torch.float32, 2e-7)]:
+                ef = P.p_to_or(P.ctx.p1_transfer(P.p_to_lib(ec, l - 1, dtype), l), l)
+                assert np.abs(ef - Pro @ ec).max() <= tol * np.abs(ec).max()
+                rf = inputs.uniform(50 + l, ml.n1)
+                rc = P.p_to_or(P.ctx.p1_transfer(P.p_to_lib(rf, l, dtype), l, restrict=True), l - 1)
+                assert relerr(rc, Pro.T @ rf) < 10 * tol
+
+
+def test_wbfbt_step_matches_oracle(shell):
+    """One adjoint Uzawa step with the weighted BFBT (a_l = 1, a_r = 10, as in
+    the paper's asymmetric test), all inner solves tight, against the oracle's
+    step with exact projected solves: the Poisson problems with the mean-zero
+    constraint, the vector masses on the admissible velocities."""
+    d = shell
+    P, m = d["P"], d["m"]
+    params = default_params(precision=64, tol_A=1e-12, tol_wbfbt=1e-13, tol_vmass=1e-13, max_inner=400,
+                            uzawa=UZAWA_ADJOINT, schur=SCHUR_WBFBT, a_l=1.0, a_r=10.0)
+    P.ctx.set_fields(P.p_to_lib(d["eta"]), P.p_to_lib(d["lnrho"]), params=params)
+    ru = inputs.uniform(23, 3 * m.n2)
+    rp = inputs.uniform(24, m.n1)
+    zu, zp = P.ctx.precondition(P.u_to_lib(ru), P.p_to_lib(rp), params=params)
+    zu, zp = P.u_to_or(zu), P.p_to_or(zp)
+    Q = d["Q"]
+    ops = {}
+    for side, a in (("l", 1.0), ("r", 10.0)):
+        sK = dirichlet_element_scale(m, P.dir_flags, a)
+        Mq = spla.splu((Q.T @ assemble_vector_mass(m, d["eta"], sK) @ Q).tocsc())
+        K = assemble_poisson_p1(m, d["eta"], sK)
+        n1 = m.n1
+        import scipy.sparse as sp
+        Kb = sp.bmat([[K, np.ones((n1, 1))], [np.ones((1, n1)), None]], format="csc")
+        Klu = spla.splu(Kb)
+        ops[side] = (lambda v, Mq=Mq: Q @ Mq.solve(Q.T @ v),
+                     lambda v, Klu=Klu: Klu.solve(np.concatenate([v - v.mean(), [0.0]]))[:-1])
+    Sinv = lambda r: wbfbt(r - r.mean(), d["B"], d["B"].T, d["A"], ops["l"][0], ops["r"][0], ops["l"][1], ops["r"][1])
+    rpm = rp - rp.mean()
+    uo, po = adjoint_uzawa(ru, rpm, d["B"].T, d["Ainv"], Sinv, params.sigma, params.omega)
+    po = po - po.mean()
+    print("w-BFBT step", relerr(zu, uo), relerr(zp, po))
+    assert relerr(zu, uo) < 1e-8
+    assert relerr(zp, po) < 1e-8

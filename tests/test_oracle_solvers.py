@@ -62,6 +62,23 @@ def _levels(mac, lmax, eta_fn):
     return levels, meshes
 
 
+def test_p1_prolongation_reproduces_linear_functions():
+    """The nested P1 embedding: a linear function of the reference
+    coordinates is interpolated exactly, rows sum to one, and on the shell
+    every fine P1 node is a coarse vertex (weight 1) or an edge midpoint
+    (weights 1/2, 1/2)."""
+    from oracle.solvers import prolongation_p1
+    for mac in (cube_macros(), shell_macros(1, 1, 0.55, 1.0)):
+        c, f = RefinedMesh(mac, 1), RefinedMesh(mac, 2)
+        P = prolongation_p1(c, f)
+        g = np.array([0.7, -1.3, 0.4])
+        assert np.abs(P @ (c.x1 @ g + 0.2) - (f.x1 @ g + 0.2)).max() < 1e-13
+        assert np.abs(np.asarray(P.sum(axis=1)).ravel() - 1.0).max() < 1e-14
+        nnz = np.diff(P.indptr)
+        assert set(np.unique(nnz)) == {1, 2}
+        assert np.allclose(P.data[np.repeat(nnz, nnz) == 2], 0.5)
+
+
 def test_vcycle_contracts_level_independently():
     eta = lambda X: 1.0 + 9.0 * (X[:, 0] > 0.5)
     factors = []
