@@ -1,0 +1,203 @@
+"""The temperature step (Sec. 3 and Sec. 6 of arXiv 2506.04157), FP64.
+
+Test infrastructure: plain assembled matrices and a brute-force method of
+characteristics that the GPU path is compared against.
+
+* ``bdf2``                 the variable-step BDF2 weights s^{n+1}, s^n, s^{n-1}
+                           of the difference quotient D[.] (Sec. 3).
+* ``temperature_system``   the matrix and right-hand side of the discrete
+                           advection-diffusion problem, eq. (WeakTemp), on the
+                           P2 space of the blended mesh; Dirichlet values on
+                           both spheres.
+* ``locate`` / ``evaluate_p2``   point location in the blended mesh (every
+                           element tried: the reference point of a physical
+                           x in macro m is |x~| = (|x| - s0_m) / (g_m . d) along
+                           d = x/|x|, the inverse of the blending map) and
+                           evaluation of a P2 function there.
+* ``mmoc``                 the modified method of characteristics (Sec. 3):
+                           nodes traced backwards over one step with the
+                           classical Runge-Kutta method along the velocity
+                           linearly interpolated in time, and the field
+                           evaluated at the departure points.
+
+Readings (the paper is terse or garbled here):
+* eq. (WeakTemp) prints the history terms int s^n T^n w - int s^{n-1} T^{n-1} w
+  inside the factor tau^{n+1}; the BDF2 quotient D[T^{n+1}, T^n, T^{n-1}] /
+  tau^{n+1} defined just before it puts them beside s^{n+1} T^{n+1}, without
+  tau.  The quotient is followed: after multiplying by tau^{n+1} the history
+  terms carry no tau.
+* the shear heating is tau(u) : eps(u) = 2 eta (eps : eps - (div u)^2 / 3), the
+  deviatoric stress of the Stokes blocks.
+* the second history value composes the two tracing steps so that the
+  characteristic through a node at t^{n+1} is followed back to t^n and then
+  to t^{n-1}: T^(n-1) = MMOC(MMOC(T^{n-1}, u^n, u^{n-1}, tau^n), u^{n+1}, u^n,
+  tau^{n+1}).
+* departure points outside the shell are moved radially onto it.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .fem import EDGES, _chunks, geometry, p2_values, strain_and_div
+from .quadrature import rule_stroud
+
+
+def bdf2(tau1, tau0):
+    """(s^{n+1}, s^n, s^{n-1}) for the step tau1 = tau^{n+1} after tau0 = tau^n."""
+    s1 = (2.0 * tau1 + tau0) / (tau1 + tau0)
+    s0 = (tau1 + tau0) / tau0
+    sm = tau1 * tau1 / (tau0 * (tau1 + tau0))
+    return s1, s0, sm
+
+
+def temperature_system(mesh, ustar, lnrho1, eta1, That_n, That_nm1, tau1, tau0, k=1.0, Pe=1.0, Cp=1.0, Di=0.0,
+                       alpha=0.0, H=0.0, Ra=1.0, rule=None):
+    """LHS matrix L (n2 x n2) and right-hand side b of eq. (WeakTemp), before
+    the Dirichlet rows are imposed:
+
+      L_ij = int s^{n+1} phi_j phi_i
+             + tau ( int (u* . grad phi_j) phi_i
+                     + int k / (Pe Cp) grad phi_j . grad (phi_i / rho)
+                     - int Di alpha / Cp phi_j (u* . g) phi_i ),      g = -r_hat
+      b_i  = int (s^n That^n - s^{n-1} That^{n-1}) phi_i
+             + tau ( int H / Cp phi_i + int Pe Di / (Ra rho Cp) tau(u*):eps(u*) phi_i )
+
+    with rho = exp(ln rho_h), ln rho_h and eta_h the P1 interpolants of the
+    nodal values, the P2 functions at the points of the 27-point rule."""
+    rule = rule if rule is not None else rule_stroud(3)
+    s1, s0, sm = bdf2(tau1, tau0)
+    n2 = mesh.n2
+    U = ustar.reshape(3, n2)
+    rows, cols, vals = [], [], []
+    b = np.zeros(n2)
+    kap = k / (Pe * Cp)
+    for sel in _chunks(mesh.ne, 4096):
+        W, G2, G1, X, N2, N1 = geometry(mesh, sel, rule)
+        e2 = mesh.e2[sel]
+        lr = np.einsum("qk,ek->eq", N1, lnrho1[mesh.e1[sel]])
+        glr = np.einsum("eqkd,ek->eqd", G1, lnrho1[mesh.e1[sel]])      # grad ln rho_h
+        rho = np.exp(lr)
+        etaq = np.einsum("qk,ek->eq", N1, eta1[mesh.e1[sel]])
+        uq = np.einsum("cea,qa->eqc", U[:, e2], N2)                      # u* at the points
+        rhat = X / np.linalg.norm(X, axis=-1, keepdims=True)
+        ug = -np.einsum("eqc,eqc->eq", uq, rhat)                         # u* . g
+        mass = np.einsum("eq,qi,qj->eij", W, N2, N2)
+        adv = np.einsum("eq,eqd,eqjd,qi->eij", W, uq, G2, N2)
+        # grad(phi_i / rho) = (grad phi_i - phi_i grad ln rho) / rho
+        dif = np.einsum("eq,eqid,eqjd->eij", W / rho, G2, G2) - np.einsum("eq,qi,eqd,eqjd->eij", W / rho, N2, glr, G2)
+        adi = np.einsum("eq,eq,qi,qj->eij", W, ug, N2, N2)
+        Le = s1 * mass + tau1 * (adv + kap * dif - (Di * alpha / Cp) * adi)
+        rows.append(np.repeat(e2, 10, axis=1).ravel())
+        cols.append(np.tile(e2, (1, 10)).ravel())
+        vals.append(Le.ravel())
+        hist = np.einsum("qa,ea->eq", N2, s0 * That_n[e2] - sm * That_nm1[e2])
+        # tau(u):eps(u) = 2 eta (eps:eps - (div u)^2 / 3) from the P2 velocity
+        gradu = np.einsum("cea,eqad->eqcd", U[:, e2], G2)
+        eps = 0.5 * (gradu + np.swapaxes(gradu, -1, -2))
+        divu = np.einsum("eqcc->eq", gradu)
+        shear = 2.0 * etaq * (np.einsum("eqcd,eqcd->eq", eps, eps) - divu ** 2 / 3.0)
+        src = hist + tau1 * (H / Cp + Pe * Di / (Ra * rho * Cp) * shear)
+        np.add.at(b, e2.ravel(), np.einsum("eq,eq,qi->ei", W, src, N2).ravel())
+    L = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n2, n2)).tocsr()
+    return L, b
+
+
+def solve_dirichlet(L, b, dmask, Tdir):
+    """T with T = Tdir on the Dirichlet nodes (dmask) and the other rows of
+    L T = b, by a direct solve."""
+    import scipy.sparse.linalg as spla
+    free = ~dmask
+    T = np.where(dmask, Tdir, 0.0)
+    rhs = (b - L @ T)[free]
+    T[free] = spla.spsolve(L[free][:, free].tocsc(), rhs)
+    return T
+
+
+# --- point location and evaluation in the blended mesh --------------------------
+
+def _macro_vertices(mesh):
+    tets = mesh.macro.tets
+    return mesh.macro.vertices[tets]                              # (nm, 4, 3)
+
+
+def locate(mesh, X):
+    """For physical points X (n, 3) inside the mesh: the element and the
+    element-local barycentric coordinates (of the reference point).  Every
+    element is tried: x~ = |x~| d with |x~| = (|x| - s0) / (g . d) for the
+    element's macro (x itself on the cube), then the barycentric coordinates
+    of x~ in the element's reference vertices; the element whose smallest
+    coordinate is largest wins."""
+    X = np.asarray(X, dtype=np.float64)
+    n = len(X)
+    ev = mesh.ev                                                  # (ne, 4, 3)
+    T = np.stack([ev[:, 1] - ev[:, 0], ev[:, 2] - ev[:, 0], ev[:, 3] - ev[:, 0]], axis=2)
+    Tinv = np.linalg.inv(T)
+    best_e = np.zeros(n, dtype=np.int64)
+    best_l = np.full((n, 4), -np.inf)
+    best_m = np.full(n, -np.inf)
+    if mesh.blend_g is not None:
+        r = np.linalg.norm(X, axis=1)
+        d = X / r[:, None]
+    for chunk in _chunks(mesh.ne, 512):
+        if mesh.blend_g is not None:
+            m = mesh.emacro[chunk]
+            g = mesh.blend_g[m]                                    # (c, 3)
+            s0 = mesh.blend_s0[m]
+            gd = d @ g.T                                           # (n, c)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                rt = (r[:, None] - s0[None, :]) / gd
+                xt = rt[:, :, None] * d[:, None, :]                # (n, c, 3)
+            # the inverse is along +d only: a negative |x~| is the antipode
+            away = ~(rt > 0.0)
+        else:
+            xt = np.broadcast_to(X[:, None, :], (n, len(chunk), 3))
+            away = np.zeros((n, len(chunk)), dtype=bool)
+        xi = np.einsum("cij,ncj->nci", Tinv[chunk], xt - ev[chunk][None, :, 0, :])
+        lam = np.concatenate([1.0 - xi.sum(-1, keepdims=True), xi], axis=-1)   # (n, c, 4)
+        mn = np.where(away, -np.inf, lam.min(-1))
+        j = np.argmax(mn, axis=1)
+        better = mn[np.arange(n), j] > best_m
+        best_m[better] = mn[np.arange(n), j][better]
+        best_e[better] = chunk[j[better]]
+        best_l[better] = lam[np.arange(n), j][better]
+    assert best_m.min() > -1e-8, "point outside the mesh"
+    return best_e, best_l
+
+
+def evaluate_p2(mesh, F, X):
+    """Values at physical points X of the P2 functions F (k, n2) (rows are
+    fields) as an array (k, n)."""
+    F = np.atleast_2d(F)
+    e, lam = locate(mesh, X)
+    N = p2_values(lam)                                            # (n, 10)
+    return np.einsum("na,kna->kn", N, F[:, mesh.e2[e]])
+
+
+def _clamp_to_shell(mesh, X):
+    if mesh.blend_g is None:
+        return np.clip(X, 0.0, 1.0)
+    r = np.linalg.norm(X, axis=1)
+    rc = np.clip(r, mesh.macro.r_in, mesh.macro.r_out)
+    return X * (rc / r)[:, None]
+
+
+def mmoc(mesh, F, u_new, u_old, tau):
+    """The field F (n2) evaluated at the departure points of the P2 nodes:
+    each node is traced backwards over [t - tau, t] with one step of the
+    classical Runge-Kutta method along u(s) linearly interpolated between
+    u_old at t - tau and u_new at t (Sec. 3), departure points moved onto the
+    shell if they leave it."""
+    n2 = mesh.n2
+
+    def vel(X, theta):
+        """u at the points X and time t - tau + theta tau."""
+        uv = evaluate_p2(mesh, np.concatenate([theta * u_new.reshape(3, n2) + (1.0 - theta) * u_old.reshape(3, n2)]),
+                         X)
+        return uv.T
+
+    X0 = mesh.X2
+    k1 = vel(X0, 1.0)
+    k2 = vel(_clamp_to_shell(mesh, X0 - 0.5 * tau * k1), 0.5)
+    k3 = vel(_clamp_to_shell(mesh, X0 - 0.5 * tau * k2), 0.5)
+    k4 = vel(_clamp_to_shell(mesh, X0 - tau * k3), 0.0)
+    Xd = _clamp_to_shell(mesh, X0 - tau / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4))
+    return evaluate_p2(mesh, F, Xd)[0]
