@@ -26,13 +26,28 @@ Readings (the paper is terse or garbled here):
   tau^{n+1} defined just before it puts them beside s^{n+1} T^{n+1}, without
   tau.  The quotient is followed: after multiplying by tau^{n+1} the history
   terms carry no tau.
+* eq. (WeakTemp) and the strong form before it both print the advection term
+  u* . grad T^{n+1} beside the BDF2 quotient of the traced values, while the
+  text says the splitting step solves the energy equation without advection
+  and the cost breakdown assigns the advection to the MMOC alone.  With the
+  traced values the quotient already approximates the material derivative,
+  so the printed term would count the advection twice; it is kept with a
+  weight ``adv``, 0 by default (the splitting), 1 for the printed equation.
+* the preconditioner's "symmetric mass and diffusion part" is
+  s^{n+1} M + tau k / (Pe Cp) int grad T . grad w / rho: the symmetric half of
+  the diffusion term (the term -w grad ln rho . grad T / rho is not symmetric).
 * the shear heating is tau(u) : eps(u) = 2 eta (eps : eps - (div u)^2 / 3), the
   deviatoric stress of the Stokes blocks.
 * the second history value composes the two tracing steps so that the
   characteristic through a node at t^{n+1} is followed back to t^n and then
-  to t^{n-1}: T^(n-1) = MMOC(MMOC(T^{n-1}, u^n, u^{n-1}, tau^n), u^{n+1}, u^n,
-  tau^{n+1}).
-* departure points outside the shell are moved radially onto it.
+  to t^{n-1}, as the definition T^(t^{n-1}, x) = T(t^{n-1}, X(t^{n+1}, t^{n-1}, x))
+  requires: T^(n-1) = MMOC(MMOC(T^{n-1}, u^n, u^{n-1}, tau^n), u*^{n+1}, u^n,
+  tau^{n+1}).  The printed formula nests the two steps the other way round,
+  which agrees with the definition only for a velocity constant in time.
+* departure points outside the shell are moved radially onto it (onto the
+  cube by clamping the coordinates).
+* Dirichlet values: T_in on the inner sphere (the whole boundary of the
+  cube), T_out on the outer sphere.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -50,12 +65,12 @@ def bdf2(tau1, tau0):
 
 
 def temperature_system(mesh, ustar, lnrho1, eta1, That_n, That_nm1, tau1, tau0, k=1.0, Pe=1.0, Cp=1.0, Di=0.0,
-                       alpha=0.0, H=0.0, Ra=1.0, rule=None):
+                       alpha=0.0, H=0.0, Ra=1.0, adv=0.0, rule=None):
     """LHS matrix L (n2 x n2) and right-hand side b of eq. (WeakTemp), before
     the Dirichlet rows are imposed:
 
       L_ij = int s^{n+1} phi_j phi_i
-             + tau ( int (u* . grad phi_j) phi_i
+             + tau ( adv int (u* . grad phi_j) phi_i
                      + int k / (Pe Cp) grad phi_j . grad (phi_i / rho)
                      - int Di alpha / Cp phi_j (u* . g) phi_i ),      g = -r_hat
       b_i  = int (s^n That^n - s^{n-1} That^{n-1}) phi_i
@@ -81,11 +96,11 @@ def temperature_system(mesh, ustar, lnrho1, eta1, That_n, That_nm1, tau1, tau0, 
         rhat = X / np.linalg.norm(X, axis=-1, keepdims=True)
         ug = -np.einsum("eqc,eqc->eq", uq, rhat)                         # u* . g
         mass = np.einsum("eq,qi,qj->eij", W, N2, N2)
-        adv = np.einsum("eq,eqd,eqjd,qi->eij", W, uq, G2, N2)
+        advm = np.einsum("eq,eqd,eqjd,qi->eij", W, uq, G2, N2)
         # grad(phi_i / rho) = (grad phi_i - phi_i grad ln rho) / rho
         dif = np.einsum("eq,eqid,eqjd->eij", W / rho, G2, G2) - np.einsum("eq,qi,eqd,eqjd->eij", W / rho, N2, glr, G2)
         adi = np.einsum("eq,eq,qi,qj->eij", W, ug, N2, N2)
-        Le = s1 * mass + tau1 * (adv + kap * dif - (Di * alpha / Cp) * adi)
+        Le = s1 * mass + tau1 * (adv * advm + kap * dif - (Di * alpha / Cp) * adi)
         rows.append(np.repeat(e2, 10, axis=1).ravel())
         cols.append(np.tile(e2, (1, 10)).ravel())
         vals.append(Le.ravel())
@@ -201,3 +216,43 @@ def mmoc(mesh, F, u_new, u_old, tau):
     k4 = vel(_clamp_to_shell(mesh, X0 - tau * k3), 0.0)
     Xd = _clamp_to_shell(mesh, X0 - tau / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4))
     return evaluate_p2(mesh, F, Xd)[0]
+
+
+def symmetric_part(mesh, lnrho1, tau1, tau0, k=1.0, Pe=1.0, Cp=1.0, rule=None):
+    """The matrix the CG preconditioner solves with: s^{n+1} M + tau k / (Pe Cp)
+    K_{1/rho}, K_{1/rho} the P2 stiffness matrix with weight 1/rho_h."""
+    rule = rule if rule is not None else rule_stroud(3)
+    s1, _, _ = bdf2(tau1, tau0)
+    kap = k / (Pe * Cp)
+    rows, cols, vals = [], [], []
+    for sel in _chunks(mesh.ne, 4096):
+        W, G2, G1, X, N2, N1 = geometry(mesh, sel, rule)
+        rho = np.exp(np.einsum("qk,ek->eq", N1, lnrho1[mesh.e1[sel]]))
+        Le = s1 * np.einsum("eq,qi,qj->eij", W, N2, N2) + tau1 * kap * np.einsum("eq,eqid,eqjd->eij", W / rho, G2, G2)
+        e2 = mesh.e2[sel]
+        rows.append(np.repeat(e2, 10, axis=1).ravel())
+        cols.append(np.tile(e2, (1, 10)).ravel())
+        vals.append(Le.ravel())
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(mesh.n2, mesh.n2)).tocsr()
+
+
+def dirichlet_values(mesh, T_in, T_out):
+    """Mask of the Dirichlet nodes and their values (T_in on flag 1, T_out on
+    flag 2)."""
+    dmask = mesh.flag2 > 0
+    return dmask, np.where(mesh.flag2 == 2, T_out, np.where(mesh.flag2 == 1, T_in, 0.0))
+
+
+def temperature_step(mesh, T_n, T_nm1, u_n, u_nm1, lnrho1, eta1, tau1, tau0, T_in=1.0, T_out=0.0, **coef):
+    """One step of the splitting scheme (Sec. 3): the extrapolated velocity
+    u*^{n+1} = u^n + (u^n - u^{n-1}) tau^{n+1} / tau^n (eq. Extrapolation), the
+    traced history values by the MMOC, and the Dirichlet solve of eq. (WeakTemp).
+    eta1 is the viscosity at the extrapolated temperature, given by the caller.
+    Returns T^{n+1}, That^n, That^{n-1} and u*."""
+    ustar = u_n + (u_n - u_nm1) * (tau1 / tau0)
+    That_n = mmoc(mesh, T_n, ustar, u_n, tau1)
+    That_nm1 = mmoc(mesh, mmoc(mesh, T_nm1, u_n, u_nm1, tau0), ustar, u_n, tau1)
+    L, b = temperature_system(mesh, ustar, lnrho1, eta1, That_n, That_nm1, tau1, tau0, **coef)
+    dmask, Tdir = dirichlet_values(mesh, T_in, T_out)
+    return solve_dirichlet(L, b, dmask, Tdir), That_n, That_nm1, ustar
