@@ -134,47 +134,59 @@ def _macro_vertices(mesh):
     return mesh.macro.vertices[tets]                              # (nm, 4, 3)
 
 
+def _reference_points(mesh, X, macros):
+    """Reference points x~ of the physical points X (n, 3) for each macro in
+    `macros` (n, c, 3): the inverse of the blending map of that macro, along
+    +X/|X| (NaN where that ray misses the macro's blending, i.e. |x~| <= 0);
+    X itself on the cube."""
+    if mesh.blend_g is None:
+        return np.broadcast_to(X[:, None, :], (len(X), len(macros), 3))
+    r = np.linalg.norm(X, axis=1)
+    d = X / r[:, None]
+    gd = d @ mesh.blend_g[macros].T                                 # (n, c)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rt = (r[:, None] - mesh.blend_s0[macros][None, :]) / gd
+        rt = np.where(rt > 0.0, rt, np.nan)
+        return rt[:, :, None] * d[:, None, :]
+
+
+def _barycentric(verts, xt):
+    """Barycentric coordinates (n, c, 4) of the points xt (n, c, 3) in the
+    tetrahedra verts (c, 4, 3)."""
+    T = np.stack([verts[:, 1] - verts[:, 0], verts[:, 2] - verts[:, 0], verts[:, 3] - verts[:, 0]], axis=2)
+    xi = np.einsum("cij,ncj->nci", np.linalg.inv(T), xt - verts[None, :, 0, :])
+    return np.concatenate([1.0 - xi.sum(-1, keepdims=True), xi], axis=-1)
+
+
 def locate(mesh, X):
     """For physical points X (n, 3) inside the mesh: the element and the
-    element-local barycentric coordinates (of the reference point).  Every
-    element is tried: x~ = |x~| d with |x~| = (|x| - s0) / (g . d) for the
-    element's macro (x itself on the cube), then the barycentric coordinates
-    of x~ in the element's reference vertices; the element whose smallest
-    coordinate is largest wins."""
+    element-local barycentric coordinates (of the reference point).  Brute
+    force in two stages: every macro-tet is tried, the reference point of x in
+    macro m being x~ = |x~| d with |x~| = (|x| - s0_m) / (g_m . d) > 0 along
+    d = x/|x| (x itself on the cube), and the macro whose smallest barycentric
+    coordinate of x~ is largest wins; then every element of that macro is
+    tried the same way."""
     X = np.asarray(X, dtype=np.float64)
     n = len(X)
-    ev = mesh.ev                                                  # (ne, 4, 3)
-    T = np.stack([ev[:, 1] - ev[:, 0], ev[:, 2] - ev[:, 0], ev[:, 3] - ev[:, 0]], axis=2)
-    Tinv = np.linalg.inv(T)
+    nm = mesh.macro.n_macros
+    mverts = mesh.macro.vertices[mesh.macro.tets]                     # (nm, 4, 3)
+    lam_m = _barycentric(mverts, _reference_points(mesh, X, np.arange(nm)))
+    mn = np.nan_to_num(lam_m.min(-1), nan=-np.inf)
+    best_mac = np.argmax(mn, axis=1)
+    assert mn[np.arange(n), best_mac].min() > -1e-8, "point outside the mesh"
+    ne_loc = mesh.ne // nm
     best_e = np.zeros(n, dtype=np.int64)
-    best_l = np.full((n, 4), -np.inf)
-    best_m = np.full(n, -np.inf)
-    if mesh.blend_g is not None:
-        r = np.linalg.norm(X, axis=1)
-        d = X / r[:, None]
-    for chunk in _chunks(mesh.ne, 512):
-        if mesh.blend_g is not None:
-            m = mesh.emacro[chunk]
-            g = mesh.blend_g[m]                                    # (c, 3)
-            s0 = mesh.blend_s0[m]
-            gd = d @ g.T                                           # (n, c)
-            with np.errstate(divide="ignore", invalid="ignore"):
-                rt = (r[:, None] - s0[None, :]) / gd
-                xt = rt[:, :, None] * d[:, None, :]                # (n, c, 3)
-            # the inverse is along +d only: a negative |x~| is the antipode
-            away = ~(rt > 0.0)
-        else:
-            xt = np.broadcast_to(X[:, None, :], (n, len(chunk), 3))
-            away = np.zeros((n, len(chunk)), dtype=bool)
-        xi = np.einsum("cij,ncj->nci", Tinv[chunk], xt - ev[chunk][None, :, 0, :])
-        lam = np.concatenate([1.0 - xi.sum(-1, keepdims=True), xi], axis=-1)   # (n, c, 4)
-        mn = np.where(away, -np.inf, lam.min(-1))
-        j = np.argmax(mn, axis=1)
-        better = mn[np.arange(n), j] > best_m
-        best_m[better] = mn[np.arange(n), j][better]
-        best_e[better] = chunk[j[better]]
-        best_l[better] = lam[np.arange(n), j][better]
-    assert best_m.min() > -1e-8, "point outside the mesh"
+    best_l = np.zeros((n, 4))
+    for mac in np.unique(best_mac):
+        elems = np.arange(mac * ne_loc, (mac + 1) * ne_loc)
+        allp = np.nonzero(best_mac == mac)[0]
+        for pts in np.array_split(allp, max(1, len(allp) * ne_loc // 2 ** 20)):
+            xt = _reference_points(mesh, X[pts], np.array([mac]))[:, 0, :]
+            lam = _barycentric(mesh.ev[elems], np.broadcast_to(xt[:, None, :], (len(pts), ne_loc, 3)))
+            j = np.argmax(lam.min(-1), axis=1)
+            best_e[pts] = elems[j]
+            best_l[pts] = lam[np.arange(len(pts)), j]
+    assert best_l.min() > -1e-8, "point outside the mesh"
     return best_e, best_l
 
 
