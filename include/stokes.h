@@ -312,6 +312,84 @@ int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, 
  * timed. */
 int stk_kernel_timer(stk_ctx* ctx, int enable, double* ms_total, int* launches);
 
+/* ---- temperature step (Sec. 3 splitting, Sec. 6 eq. WeakTemp) ------------------
+ * The advection-diffusion step of the energy equation on the P2 space of the
+ * finest level, FP64 throughout.  With s^{n+1}, s^n, s^{n-1} the variable-step
+ * BDF2 weights of Sec. 3 and tau = tau^{n+1}:
+ *   L T = s^{n+1} M T + tau [ adv int (u* . grad T) w + int k/(Pe Cp) grad T . grad(w/rho)
+ *                             - int Di alpha/Cp T (u* . g) w ],   g = -x/|x|
+ *   b   = int (s^n T^n - s^{n-1} T^{n-1}) w
+ *         + tau [ int H/Cp w + int Pe Di/(Ra rho Cp) 2 eta eps_d(u*):eps_d(u*) w ]
+ * with eps_d the deviatoric strain rate, rho = exp(ln rho_h), ln rho_h and
+ * eta_h P1 interpolants, integrals on the 27-point conical-product rule.
+ * `adv` weights the advection term that eq. (WeakTemp) prints beside the
+ * traced history values: 0 (default) solves the splitting's advection-free
+ * step, 1 the printed equation.  Dirichlet rows: T = T_in on the inner
+ * sphere (the whole cube boundary), T_out on the outer sphere.
+ * Vectors: device doubles; temperatures n_p2, velocities 3 n_p2
+ * (component-major), ln rho and eta n_p1.  ln rho may be NULL (rho = 1). */
+typedef struct {
+  double tau1, tau0;     /* tau^{n+1}, tau^n (> 0) */
+  double k, Pe, Cp, Di, alpha, H, Ra;   /* nondimensional coefficients (Sec. 2) */
+  double adv;            /* weight of the advection term in the linear system */
+  double T_in, T_out;    /* Dirichlet values */
+  double tol_abs;        /* FGMRES stop |b - L T| <= tol_abs on the free rows (tol_T) */
+  double tol_cg;         /* relative tolerance of the preconditioner's CG */
+  int restart, max_outer, max_cg;
+} stk_temp_params;
+typedef struct {
+  int iterations;           /* FGMRES iterations */
+  int cg_its;               /* CG iterations of the preconditioner, summed */
+  int converged;
+  double initial_residual, abs_residual;
+  double ms_mmoc, ms_rhs, ms_solve;   /* host clock, stream synchronised (step only) */
+} stk_temp_report;
+/* tau1 = tau0 = 1e-3, k = Pe = Cp = Ra = 1, Di = alpha = H = adv = 0,
+ * T_in = 1, T_out = 0, tol_abs = 1e-10 (table parametertable's tol_T),
+ * tol_cg = 1e-12 (the paper applies the preconditioner "exactly"),
+ * restart 30, max_outer 300, max_cg 5000. */
+void stk_temp_default_params(stk_temp_params* p);
+#define STK_TEMP_APPLY 0   /* y = L x (no Dirichlet rows) */
+#define STK_TEMP_SYM 1     /* y = S x, S = s^{n+1} M + tau k/(Pe Cp) K_{1/rho}: the
+                              symmetric mass and diffusion part the preconditioner's CG solves */
+#define STK_TEMP_DIAG 2    /* y = diag(S) (x ignored, may be NULL) */
+/* Operator applies for parity tests: y (n_p2) overwritten, no boundary rows;
+ * u_star may be NULL (no velocity). */
+int stk_temp_apply(stk_ctx* ctx, const stk_temp_params* p, int mode, const double* u_star, const double* lnrho,
+                   const double* x, double* y);
+/* b of eq. (WeakTemp) (n_p2, overwritten, no boundary rows) from the traced
+ * history values That_n, That_nm1 (n_p2), u_star (3 n_p2, nullable: no
+ * heating) and eta (n_p1, the viscosity at the extrapolated temperature;
+ * nullable when u_star is NULL). */
+int stk_temp_rhs(stk_ctx* ctx, const stk_temp_params* p, const double* u_star, const double* lnrho, const double* eta,
+                 const double* That_n, const double* That_nm1, double* b);
+/* The modified method of characteristics (Sec. 3): out[i] = F(X_d), X_d the
+ * departure point of P2 node i after one step of the classical Runge-Kutta
+ * method backwards over tau along u(t - tau + theta tau) = theta u_new +
+ * (1 - theta) u_old, the velocity at each stage point and F at X_d
+ * evaluated in the micro-tet that contains the point (analytic point
+ * location through the blending map).  Points that leave the domain are
+ * moved radially onto the shell (clamped onto the cube).  F, out: n_p2
+ * (distinct buffers); u_new, u_old: 3 n_p2. */
+int stk_mmoc(stk_ctx* ctx, const double* F, const double* u_new, const double* u_old, double tau, double* out);
+/* T (n_p2, overwritten): the solution of L T = b with the Dirichlet rows, by
+ * FGMRES right-preconditioned with a Jacobi-CG on S (Sec. 6); T_init
+ * (nullable) starts the free rows.  STK_ENOCONV if max_outer is reached (T
+ * holds the last iterate). */
+int stk_temp_solve(stk_ctx* ctx, const stk_temp_params* p, const double* u_star, const double* lnrho,
+                   const double* b, const double* T_init, double* T, stk_temp_report* rep);
+/* One step of the splitting scheme (Sec. 3): u* = u^n + (u^n - u^{n-1})
+ * tau^{n+1}/tau^n (eq. Extrapolation); That^n = MMOC(T^n, u*, u^n, tau^{n+1});
+ * That^{n-1} = MMOC(MMOC(T^{n-1}, u^n, u^{n-1}, tau^n), u*, u^n, tau^{n+1})
+ * (the characteristic through a node followed back to t^n, then to
+ * t^{n-1}); b of eq. (WeakTemp); the Dirichlet solve started from T^n.
+ * eta (n_p1) is the viscosity at the extrapolated temperature, supplied by
+ * the caller.  T_np1 overwritten; That_n, That_nm1 (nullable) receive the
+ * traced values. */
+int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T_n, const double* T_nm1,
+                         const double* u_n, const double* u_nm1, const double* lnrho, const double* eta,
+                         double* T_np1, double* That_n, double* That_nm1, stk_temp_report* rep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,11 +9,11 @@ from ._lib import (BC_DIRICHLET, BC_FREESLIP, MESH_CUBE, MESH_SHELL, STK_ENOCONV
                    load)
 
 __all__ = ["load", "StokesError", "BC_DIRICHLET", "BC_FREESLIP", "MESH_CUBE", "MESH_SHELL",
-           "STK_ENOCONV", "StokesContext", "default_params", "StokesSolve"]
+           "STK_ENOCONV", "StokesContext", "default_params", "temp_params", "StokesSolve"]
 
 
 def __getattr__(name):
-    if name in ("StokesContext", "default_params"):
+    if name in ("StokesContext", "default_params", "temp_params"):
         from . import context
         return getattr(context, name)
     if name == "StokesSolve":

@@ -44,6 +44,26 @@ class Report(ctypes.Structure):
         return d
 
 
+class TempParams(ctypes.Structure):
+    _fields_ = [("tau1", ctypes.c_double), ("tau0", ctypes.c_double), ("k", ctypes.c_double),
+                ("Pe", ctypes.c_double), ("Cp", ctypes.c_double), ("Di", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("H", ctypes.c_double), ("Ra", ctypes.c_double),
+                ("adv", ctypes.c_double), ("T_in", ctypes.c_double), ("T_out", ctypes.c_double),
+                ("tol_abs", ctypes.c_double), ("tol_cg", ctypes.c_double), ("restart", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("max_cg", ctypes.c_int)]
+
+
+class TempReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("cg_its", ctypes.c_int), ("converged", ctypes.c_int),
+                ("initial_residual", ctypes.c_double), ("abs_residual", ctypes.c_double),
+                ("ms_mmoc", ctypes.c_double), ("ms_rhs", ctypes.c_double), ("ms_solve", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+TEMP_APPLY, TEMP_SYM, TEMP_DIAG = 0, 1, 2
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
@@ -83,6 +103,13 @@ SIGNATURES = {
     "stk_gradient": [_CTX, _P, _P, _D, _P, _P],
     "stk_time_apply_A": [_CTX, _I, _I, _P, _P, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "stk_kernel_timer": [_CTX, _I, ctypes.POINTER(_D), ctypes.POINTER(_I)],
+    "stk_temp_default_params": [ctypes.POINTER(TempParams)],
+    "stk_temp_apply": [_CTX, ctypes.POINTER(TempParams), _I, _P, _P, _P, _P],
+    "stk_temp_rhs": [_CTX, ctypes.POINTER(TempParams), _P, _P, _P, _P, _P, _P],
+    "stk_mmoc": [_CTX, _P, _P, _P, _D, _P],
+    "stk_temp_solve": [_CTX, ctypes.POINTER(TempParams), _P, _P, _P, _P, _P, ctypes.POINTER(TempReport)],
+    "stk_temperature_step": [_CTX, ctypes.POINTER(TempParams), _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                             ctypes.POINTER(TempReport)],
 }
 
 _lib = None
@@ -99,7 +126,7 @@ def load():
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = ctypes.c_char_p if name == "stk_last_error" else (
-                None if name == "stk_default_params" else ctypes.c_int)
+                None if name in ("stk_default_params", "stk_temp_default_params") else ctypes.c_int)
         _lib = lib
     return _lib
 

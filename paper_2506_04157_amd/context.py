@@ -8,12 +8,23 @@ import torch
 
 from . import _lib
 from ._lib import (BC_DIRICHLET, BC_FREESLIP, MESH_CUBE, MESH_SHELL, MeshDesc, Report, SolverParams,
-                   check, load)
+                   TempParams, TempReport, check, load)
 
 
 def default_params(**kw):
     p = SolverParams()
     load().stk_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def temp_params(**kw):
+    """Parameters of the temperature step (stk_temp_params) with overrides."""
+    p = TempParams()
+    load().stk_temp_default_params(ctypes.byref(p))
     for k, v in kw.items():
         if not hasattr(p, k):
             raise AttributeError(k)
@@ -338,3 +349,53 @@ class StokesContext:
         ms, n = ctypes.c_double(), ctypes.c_int()
         check(self.lib.stk_kernel_timer(self.h, int(bool(enable)), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # -- temperature step (Sec. 3, eq. WeakTemp) --------------------------------------
+    def _s1(self, t, name):
+        return self._vec(t, self.sizes()[1], (torch.float64,), name)
+
+    def temp_apply(self, x, params, mode=0, u_star=None, lnrho=None, out=None):
+        """mode 0: L x; 1: the symmetric part S x; 2: diag(S) (x ignored)."""
+        n2 = self.sizes()[0]
+        out = torch.empty(n2, dtype=torch.float64, device=self.device) if out is None else out
+        check(self.lib.stk_temp_apply(self.h, ctypes.byref(params), int(mode), self._u(u_star, name="u_star"),
+                                      self._s1(lnrho, "lnrho"), self._s2(x, name="x"), self._s2(out, name="out")))
+        return out
+
+    def temp_rhs(self, That_n, That_nm1, params, u_star=None, lnrho=None, eta=None, out=None):
+        n2 = self.sizes()[0]
+        out = torch.empty(n2, dtype=torch.float64, device=self.device) if out is None else out
+        check(self.lib.stk_temp_rhs(self.h, ctypes.byref(params), self._u(u_star, name="u_star"),
+                                    self._s1(lnrho, "lnrho"), self._s1(eta, "eta"), self._s2(That_n, name="That_n"),
+                                    self._s2(That_nm1, name="That_nm1"), self._s2(out, name="out")))
+        return out
+
+    def mmoc(self, F, u_new, u_old, tau, out=None):
+        out = torch.empty_like(F) if out is None else out
+        check(self.lib.stk_mmoc(self.h, self._s2(F, name="F"), self._u(u_new, name="u_new"),
+                                self._u(u_old, name="u_old"), float(tau), self._s2(out, name="out")))
+        return out
+
+    def temp_solve(self, b, params, u_star=None, lnrho=None, T_init=None, allow_noconv=False):
+        T = torch.empty_like(b)
+        rep = TempReport()
+        rc = self.lib.stk_temp_solve(self.h, ctypes.byref(params), self._u(u_star, name="u_star"),
+                                     self._s1(lnrho, "lnrho"), self._s2(b, name="b"), self._s2(T_init, name="T_init"),
+                                     self._s2(T, name="T"), ctypes.byref(rep))
+        if not (allow_noconv and rc == _lib.STK_ENOCONV):
+            check(rc)
+        return T, rep.as_dict()
+
+    def temperature_step(self, T_n, T_nm1, u_n, u_nm1, eta, params, lnrho=None, traced=False, allow_noconv=False):
+        """T^{n+1} (and, with traced=True, the traced history values)."""
+        T = torch.empty_like(T_n)
+        thn = torch.empty_like(T_n) if traced else None
+        thm = torch.empty_like(T_n) if traced else None
+        rep = TempReport()
+        rc = self.lib.stk_temperature_step(
+            self.h, ctypes.byref(params), self._s2(T_n, name="T_n"), self._s2(T_nm1, name="T_nm1"),
+            self._u(u_n, name="u_n"), self._u(u_nm1, name="u_nm1"), self._s1(lnrho, "lnrho"), self._s1(eta, "eta"),
+            self._s2(T, name="T"), self._s2(thn, name="That_n"), self._s2(thm, name="That_nm1"), ctypes.byref(rep))
+        if not (allow_noconv and rc == _lib.STK_ENOCONV):
+            check(rc)
+        return (T, thn, thm, rep.as_dict()) if traced else (T, rep.as_dict())

@@ -196,6 +196,47 @@ struct VmassRule {
 template <typename R>
 void launch_vmass(const LevelDev& L, const VmassRule& qr, const R* eta, R a2, const R* u, R* y, bool diag, int bcmode,
                   hipStream_t s);
+// ---- temperature step (Sec. 3 and Sec. 6, eq. WeakTemp) -----------------------
+// Coefficients of the discrete advection-diffusion problem, with tau = tau^{n+1}:
+//   L = s1 M + tau (adv Adv(u*) + kap D_rho - cad Adi(u*)),   S = s1 M + tau kap K_{1/rho}
+//   b = M (s0 T^n - sm T^{n-1}) + tau (hsrc M 1 + heat W(u*, eta) / rho)
+// kap = k/(Pe Cp), cad = Di alpha/Cp, hsrc = H/Cp, heat = Pe Di/(Ra Cp).
+struct TempCoef {
+  double s1, s0, sm, tau, kap, adv, cad, hsrc, heat;
+};
+enum { TM_APPLY = 0, TM_SYM = 1, TM_DIAG = 2, TM_RHS = 3 };
+// Finest-level element kernel of the temperature problem, 27-point rule:
+// TM_APPLY y = L x, TM_SYM y = S x, TM_DIAG y = diag(S), TM_RHS y = b (from
+// Tn, Tm, u, eta); no boundary rows (y overwritten).  u (3 n2, component
+// major) and lnrho (P1) are nullable (zero velocity, rho = 1).
+void launch_temp(const LevelDev& L, const VmassRule& qr, const TempCoef& tc, int mode, const double* x,
+                 const double* u, const double* lnrho, const double* eta, const double* Tn, const double* Tm, double* y,
+                 hipStream_t s);
+// Point location in the blended mesh.  Shell: the icosahedral face whose cone
+// holds the direction (fmat: inverse of the face's vertex matrix), the
+// sub-triangle of its n_tan lattice, the radial layer, and among the prism's
+// three macro-tets the one containing the inverse-blended point; cube: the
+// best of the six macro-tets.  Then the lattice cube and micro-tet type.
+struct LocDev {
+  int kind;                  // 0 cube, 1 shell
+  int n_tan, n_rad;
+  double r_in, r_out;
+  double fmat[20][9];        // row-major inverse of [v_f0 v_f1 v_f2] (columns)
+  double tinv6[6][9];        // row-major inverse of the lattice offsets [o1-o0 o2-o0 o3-o0] of each type
+  const int* prism;          // shell: [20][2 n_tan^2][n_rad][3] macro ids
+  const double* minv;        // per macro: row-major inverse of E (reference x~ - v0 = E (a, b, c))
+};
+// out[i] = F(X_d(i)) for every P2 node i of the finest level: X_d the end
+// of one classical Runge-Kutta step backwards over tau along the velocity
+// linearly interpolated between un (at t) and uo (at t - tau); points that
+// leave the domain are moved back onto it (radially on the shell).
+void launch_mmoc(const LevelDev& L, const LocDev& loc, const double* F, const double* un, const double* uo, double tau,
+                 double* out, hipStream_t s);
+// Dirichlet rows of a scalar P2 field on the node list (kind 1 inner / cube, 2 outer):
+// set = 0: v = 0 there; set = 1: v = vin / vout there
+void launch_scalar_dirichlet(const uint32_t* node, const uint8_t* kind, int nb, double* v, int set, double vin,
+                             double vout, hipStream_t s);
+
 // coefficients per level: nmacro * NSTORE1 * (nloc1 + 1)
 void launch_rhs(const LevelDev& L, const double* T, double scale, double* f, hipStream_t s);
 void launch_gradient(const LevelDev& L, const double* eta, const double* u, const double* lam,

@@ -1274,6 +1274,425 @@ __global__ __launch_bounds__(256) void k_vmass(LevelDev L, VmassRule qr, const R
   }
 }
 
+// ---- temperature step (Sec. 3 and Sec. 6, eq. WeakTemp) -------------------------
+// One thread per micro-tet of the finest level, global atomics, the 27-point
+// conical-product rule of the vector mass: the P2 mass integrand has degree
+// 4, which the 4-point rule of the Stokes blocks would make singular.  Per
+// point: the barycentric coordinates, the P2 values N and physical gradients
+// dN (J_B^{-T} applied to the affine gradients), and 1/rho = exp(-ln rho_h).
+//   APPLY: y_i += W [N_i (s1 T + tau (adv u.grad T - kap/rho grad ln rho . grad T
+//                  - cad (u.g) T)) + tau kap/rho grad T . grad N_i],  g = -X/|X|
+//   SYM:   the s1 T N_i and tau kap/rho grad T . grad N_i parts
+//   DIAG:  W (s1 N_i^2 + tau kap/rho |grad N_i|^2)
+//   RHS:   W N_i (s0 T^n - sm T^{n-1} + tau (hsrc + heat/rho 2 eta eps_d:eps_d))
+template <int MODE, bool BLEND>
+__global__ __launch_bounds__(256) void k_temp(LevelDev L, VmassRule qr, TempCoef tc, const double* __restrict__ x,
+                                              const double* __restrict__ u, const double* __restrict__ lnrho,
+                                              const double* __restrict__ eta, const double* __restrict__ Tn,
+                                              const double* __restrict__ Tm, double* __restrict__ y) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int n = L.n, m2 = 2 * n;
+  const int ne = n * n * n;
+  if (gid >= (long long)ne * L.nmacro) return;
+  const int mac = (int)(gid / ne);
+  const int pk = L.eall[gid - (long long)mac * ne];
+  const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  const double* G = L.geo + (size_t)mac * 16;
+  const size_t N2 = (size_t)L.n2;
+  const bool hasU = u != nullptr && (MODE == TM_APPLY || MODE == TM_RHS);
+  int I2[10], J2[10], K2[10];
+  size_t g2[10];
+  double lr[4], et[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], K = pz + c_toff[type][v][2];
+    const uint32_t g1 = l1[lloc(I, J, K, n)];
+    lr[v] = lnrho ? lnrho[g1] : 0.0;
+    et[v] = (MODE == TM_RHS && eta) ? eta[g1] : 0.0;
+    I2[v] = 2 * I;
+    J2[v] = 2 * J;
+    K2[v] = 2 * K;
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    I2[4 + ed] = (I2[i] + I2[j]) >> 1;
+    J2[4 + ed] = (J2[i] + J2[j]) >> 1;
+    K2[4 + ed] = (K2[i] + K2[j]) >> 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+  double xv[4][3];
+  elem_vertices<double>(G, type, px, py, pz, n, xv);
+  const double* TI = L.tinv + ((size_t)mac * 6 + type) * 10;
+  double gl[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gl[r][k] = TI[3 * r + k];
+  const double detF = TI[9];
+  double xs[10];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) {
+    if (MODE == TM_APPLY || MODE == TM_SYM) xs[a] = x[g2[a]];
+    else if (MODE == TM_RHS) xs[a] = tc.s0 * Tn[g2[a]] - tc.sm * Tm[g2[a]];
+    else xs[a] = 0.0;
+  }
+  double U[3][10];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 10; ++a) U[c][a] = hasU ? u[g2[a] + c * N2] : 0.0;
+  double acc[10];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) acc[a] = 0.0;
+  for (int q = 0; q < VMASS_NQ; ++q) {
+    const double lam[4] = {qr.lam[q][0], qr.lam[q][1], qr.lam[q][2], qr.lam[q][3]};
+    double xq[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) xq[r] = lam[0] * xv[0][r] + lam[1] * xv[1][r] + lam[2] * xv[2][r] + lam[3] * xv[3][r];
+    QGeo<double, BLEND> geo;
+    geo.eval(G, xq, qr.w[q] * detF);
+    const double W = geo.W;
+    double gL[4][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gL[i + 1][k] = gl[i][k];
+      geo.JinvT(gL[i + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gL[0][k] = -(gL[1][k] + gL[2][k] + gL[3][k]);
+    double N[10], dN[10][3];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      N[v] = lam[v] * (2.0 * lam[v] - 1.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dN[v][k] = (4.0 * lam[v] - 1.0) * gL[v][k];
+    }
+#pragma unroll
+    for (int ed = 0; ed < 6; ++ed) {
+      const int i = EV0(ed), j = EV1(ed);
+      N[4 + ed] = 4.0 * lam[i] * lam[j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dN[4 + ed][k] = 4.0 * (lam[i] * gL[j][k] + lam[j] * gL[i][k]);
+    }
+    const double irho = exp(-(lam[0] * lr[0] + lam[1] * lr[1] + lam[2] * lr[2] + lam[3] * lr[3]));
+    const double tk = tc.tau * tc.kap * irho;
+    if (MODE == TM_DIAG) {
+#pragma unroll
+      for (int a = 0; a < 10; ++a)
+        acc[a] += W * (tc.s1 * N[a] * N[a] + tk * (dN[a][0] * dN[a][0] + dN[a][1] * dN[a][1] + dN[a][2] * dN[a][2]));
+      continue;
+    }
+    if (MODE == TM_RHS) {
+      double src = tc.tau * tc.hsrc;
+#pragma unroll
+      for (int a = 0; a < 10; ++a) src += N[a] * xs[a];
+      if (hasU) {
+        double Gm[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 10; ++a) s += U[c][a] * dN[a][k];
+            Gm[c][k] = s;
+          }
+        const double dv = Gm[0][0] + Gm[1][1] + Gm[2][2];
+        double ee = Gm[0][0] * Gm[0][0] + Gm[1][1] * Gm[1][1] + Gm[2][2] * Gm[2][2];
+        const double e01 = 0.5 * (Gm[0][1] + Gm[1][0]), e02 = 0.5 * (Gm[0][2] + Gm[2][0]),
+                     e12 = 0.5 * (Gm[1][2] + Gm[2][1]);
+        ee += 2.0 * (e01 * e01 + e02 * e02 + e12 * e12);
+        const double etq = lam[0] * et[0] + lam[1] * et[1] + lam[2] * et[2] + lam[3] * et[3];
+        src += tc.tau * tc.heat * irho * 2.0 * etq * (ee - dv * dv * (1.0 / 3.0));
+      }
+#pragma unroll
+      for (int a = 0; a < 10; ++a) acc[a] += W * src * N[a];
+      continue;
+    }
+    double Tq = 0.0, gT[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 10; ++a) {
+      Tq += N[a] * xs[a];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gT[k] += dN[a][k] * xs[a];
+    }
+    double sa = tc.s1 * Tq;
+    if (MODE == TM_APPLY) {
+      double glr[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) glr[k] = lr[0] * gL[0][k] + lr[1] * gL[1][k] + lr[2] * gL[2][k] + lr[3] * gL[3][k];
+      sa -= tk * (glr[0] * gT[0] + glr[1] * gT[1] + glr[2] * gT[2]);
+      if (hasU) {
+        double uq[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < 10; ++a) s += N[a] * U[c][a];
+          uq[c] = s;
+        }
+        // the physical point B(x~) lies on the ray of x~: g = -x~/|x~|
+        const double ri = rsq(xq[0] * xq[0] + xq[1] * xq[1] + xq[2] * xq[2]);
+        const double ug = -(uq[0] * xq[0] + uq[1] * xq[1] + uq[2] * xq[2]) * ri;
+        sa += tc.tau * (tc.adv * (uq[0] * gT[0] + uq[1] * gT[1] + uq[2] * gT[2]) - tc.cad * ug * Tq);
+      }
+    }
+    const double b0 = tk * gT[0], b1 = tk * gT[1], b2 = tk * gT[2];
+#pragma unroll
+    for (int a = 0; a < 10; ++a) acc[a] += W * (sa * N[a] + b0 * dN[a][0] + b1 * dN[a][1] + b2 * dN[a][2]);
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) gadd(y + g2[a], acc[a]);
+}
+
+// ---- point location and the method of characteristics (Sec. 3) ------------------
+struct PointLoc {
+  int mac, type, cx, cy, cz;
+  double lam[4];
+};
+
+__device__ __forceinline__ double min4(const double l[4]) { return fmin(fmin(l[0], l[1]), fmin(l[2], l[3])); }
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// barycentric coordinates (1 - a - b - c, a, b, c) of the reference point xt in macro mac
+__device__ __forceinline__ void macro_bary(const LevelDev& L, const LocDev& loc, int mac, const double xt[3],
+                                           double lam[4]) {
+  const double* G = L.geo + (size_t)mac * 16;
+  const double* Mi = loc.minv + (size_t)mac * 9;
+  const double r0 = xt[0] - G[0], r1 = xt[1] - G[1], r2 = xt[2] - G[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lam[k + 1] = Mi[3 * k] * r0 + Mi[3 * k + 1] * r1 + Mi[3 * k + 2] * r2;
+  lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+}
+
+// X: a physical point inside the domain (after clamping)
+__device__ void locate_point(const LevelDev& L, const LocDev& loc, const double X[3], PointLoc& o) {
+  double best = -1e300;
+  int bm = 0;
+  double bl[4] = {1.0, 0.0, 0.0, 0.0};
+  if (loc.kind == 1) {
+    const double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    const double d[3] = {X[0] / r, X[1] / r, X[2] / r};
+    int bf = 0;
+    double bc[3] = {1.0, 1.0, 1.0}, bmin = -1e300;
+    for (int f = 0; f < 20; ++f) {
+      const double* M = loc.fmat[f];
+      const double c0 = M[0] * d[0] + M[1] * d[1] + M[2] * d[2];
+      const double c1 = M[3] * d[0] + M[4] * d[1] + M[5] * d[2];
+      const double c2 = M[6] * d[0] + M[7] * d[1] + M[8] * d[2];
+      const double mn = fmin(c0, fmin(c1, c2));
+      if (mn > bmin) {
+        bmin = mn;
+        bf = f;
+        bc[0] = c0;
+        bc[1] = c1;
+        bc[2] = c2;
+      }
+    }
+    const int nt = loc.n_tan;
+    const double cs = bc[0] + bc[1] + bc[2];
+    const double xa = nt * bc[0] / cs, xb = nt * bc[1] / cs;
+    const int i = clampi((int)floor(fmin(fmax(xa, 0.0), (double)nt)), 0, nt - 1);
+    const int j = clampi((int)floor(fmin(fmax(xb, 0.0), (double)nt)), 0, nt - 1 - i);
+    const int down = ((xa - i) + (xb - j) > 1.0) && (i + j <= nt - 2);
+    const int tri = 2 * (i * nt + j) + down;
+    const double t = (r - loc.r_in) / (loc.r_out - loc.r_in) * loc.n_rad;
+    const int k = clampi((int)floor(fmin(fmax(t, 0.0), (double)loc.n_rad)), 0, loc.n_rad - 1);
+    const int* cand = loc.prism + (((size_t)bf * 2 * nt * nt + tri) * loc.n_rad + k) * 3;
+    for (int s = 0; s < 3; ++s) {
+      const int m = cand[s];
+      const double* G = L.geo + (size_t)m * 16;
+      const double gd = G[12] * d[0] + G[13] * d[1] + G[14] * d[2];
+      const double rt = (r - G[15]) / gd;
+      if (!(rt > 0.0)) continue;
+      const double xt[3] = {rt * d[0], rt * d[1], rt * d[2]};
+      double lam[4];
+      macro_bary(L, loc, m, xt, lam);
+      const double mn = min4(lam);
+      if (mn > best) {
+        best = mn;
+        bm = m;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bl[v] = lam[v];
+      }
+    }
+  } else {
+    for (int m = 0; m < L.nmacro; ++m) {
+      double lam[4];
+      macro_bary(L, loc, m, X, lam);
+      const double mn = min4(lam);
+      if (mn > best) {
+        best = mn;
+        bm = m;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bl[v] = lam[v];
+      }
+    }
+  }
+  // lattice cube and micro-tet type inside the macro (P1 lattice coordinates)
+  const int n = L.n;
+  double p[3];
+  int c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    p[k] = fmin(fmax(n * bl[k + 1], 0.0), (double)n);
+    c[k] = clampi((int)floor(p[k]), 0, n - 1);
+  }
+  // a point on the macro's far face may floor to a cube beyond it
+  while (c[0] + c[1] + c[2] > n - 1) {
+    const int k = (c[0] >= c[1] && c[0] >= c[2]) ? 0 : (c[1] >= c[2] ? 1 : 2);
+    --c[k];
+  }
+  const int sc = c[0] + c[1] + c[2];
+  double bt = -1e300;
+  o.mac = bm;
+  o.type = 0;
+  o.cx = c[0];
+  o.cy = c[1];
+  o.cz = c[2];
+  o.lam[0] = 1.0;
+  o.lam[1] = o.lam[2] = o.lam[3] = 0.0;
+  for (int ty = 0; ty < 6; ++ty) {
+    if (sc > type_limit(ty, n)) continue;
+    const double r0 = p[0] - c[0] - c_toff[ty][0][0], r1 = p[1] - c[1] - c_toff[ty][0][1],
+                 r2 = p[2] - c[2] - c_toff[ty][0][2];
+    const double* T = loc.tinv6[ty];
+    double lam[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lam[k + 1] = T[3 * k] * r0 + T[3 * k + 1] * r1 + T[3 * k + 2] * r2;
+    lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+    const double mn = min4(lam);
+    if (mn > bt) {
+      bt = mn;
+      o.type = ty;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o.lam[v] = lam[v];
+    }
+  }
+}
+
+// global P2 nodes and basis values of a located point
+__device__ __forceinline__ void point_basis(const LevelDev& L, const PointLoc& o, size_t g2[10], double N[10]) {
+  const int m2 = 2 * L.n;
+  const uint32_t* l2 = L.l2g2 + (size_t)o.mac * L.nloc2;
+  int I2[10], J2[10], K2[10];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    I2[v] = 2 * (o.cx + c_toff[o.type][v][0]);
+    J2[v] = 2 * (o.cy + c_toff[o.type][v][1]);
+    K2[v] = 2 * (o.cz + c_toff[o.type][v][2]);
+    N[v] = o.lam[v] * (2.0 * o.lam[v] - 1.0);
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    I2[4 + ed] = (I2[i] + I2[j]) >> 1;
+    J2[4 + ed] = (J2[i] + J2[j]) >> 1;
+    K2[4 + ed] = (K2[i] + K2[j]) >> 1;
+    N[4 + ed] = 4.0 * o.lam[i] * o.lam[j];
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+}
+
+// move a point that left the domain back onto it
+__device__ __forceinline__ void clamp_to_domain(const LocDev& loc, double X[3]) {
+  if (loc.kind == 1) {
+    const double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    const double rc = fmin(fmax(r, loc.r_in), loc.r_out);
+    if (rc != r) {
+      const double f = rc / r;
+      X[0] *= f;
+      X[1] *= f;
+      X[2] *= f;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) X[k] = fmin(fmax(X[k], 0.0), 1.0);
+  }
+}
+
+// velocity at X (clamped first) and time t - tau + theta tau
+__device__ __forceinline__ void mmoc_vel(const LevelDev& L, const LocDev& loc, const double* __restrict__ un,
+                                         const double* __restrict__ uo, double theta, double X[3], double v[3]) {
+  clamp_to_domain(loc, X);
+  PointLoc o;
+  locate_point(L, loc, X, o);
+  size_t g2[10];
+  double N[10];
+  point_basis(L, o, g2, N);
+  const size_t N2 = (size_t)L.n2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 10; ++a) s += N[a] * (theta * un[g2[a] + c * N2] + (1.0 - theta) * uo[g2[a] + c * N2]);
+    v[c] = s;
+  }
+}
+
+// One thread per (macro, P2 lattice point); the macro owning the node writes it.
+__global__ __launch_bounds__(256) void k_mmoc(LevelDev L, LocDev loc, const double* __restrict__ F,
+                                              const double* __restrict__ un, const double* __restrict__ uo, double tau,
+                                              double* __restrict__ out) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int m2 = 2 * L.n, nl = L.nloc2;
+  if (gid >= (long long)nl * L.nmacro) return;
+  const int mac = (int)(gid / nl);
+  const int t = (int)(gid - (long long)mac * nl);
+  int I, J, K;
+  lattice_of(t, m2, I, J, K);
+  if (!L.own[(size_t)mac * 16 + wmask(I, J, K, m2)]) return;
+  const size_t g = L.l2g2[(size_t)mac * nl + t];
+  const double* G = L.geo + (size_t)mac * 16;
+  double X0[3];
+  lattice_x<double>(G, I, J, K, m2, X0);
+  if (L.blend) {
+    const double s = G[12] * X0[0] + G[13] * X0[1] + G[14] * X0[2] + G[15];
+    const double f = s / sqrt(X0[0] * X0[0] + X0[1] * X0[1] + X0[2] * X0[2]);
+    X0[0] *= f;
+    X0[1] *= f;
+    X0[2] *= f;
+  }
+  const size_t N2 = (size_t)L.n2;
+  // classical Runge-Kutta backwards: stage velocities at t, t - tau/2 (twice), t - tau
+  const double k1[3] = {un[g], un[g + N2], un[g + 2 * N2]};
+  double P[3], k2[3], k3[3], k4[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) P[c] = X0[c] - 0.5 * tau * k1[c];
+  mmoc_vel(L, loc, un, uo, 0.5, P, k2);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) P[c] = X0[c] - 0.5 * tau * k2[c];
+  mmoc_vel(L, loc, un, uo, 0.5, P, k3);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) P[c] = X0[c] - tau * k3[c];
+  mmoc_vel(L, loc, un, uo, 0.0, P, k4);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) P[c] = X0[c] - tau / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+  clamp_to_domain(loc, P);
+  PointLoc o;
+  locate_point(L, loc, P, o);
+  size_t g2[10];
+  double N[10];
+  point_basis(L, o, g2, N);
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 10; ++a) s += N[a] * F[g2[a]];
+  out[g] = s;
+}
+
+__global__ void k_scalar_dirichlet(const uint32_t* __restrict__ node, const uint8_t* __restrict__ kind, int nb,
+                                   double* v, int set, double vin, double vout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  v[node[i]] = set ? (kind[i] == 2 ? vout : vin) : 0.0;
+}
+
 // ---- diag(A) (no free-slip projection, Sec. 5.2.2) ---------------------------
 template <typename R, bool BLEND>
 __global__ __launch_bounds__(384) void k_diag(LevelDev L, const R* __restrict__ eta, R* __restrict__ dout) {
@@ -2927,6 +3346,38 @@ void launch_vmass(const LevelDev& L, const VmassRule& qr, const R* eta, R a2, co
 }
 template void launch_vmass<double>(const LevelDev&, const VmassRule&, const double*, double, const double*, double*,
                                    bool, int, hipStream_t);
+
+void launch_temp(const LevelDev& L, const VmassRule& qr, const TempCoef& tc, int mode, const double* x,
+                 const double* u, const double* lnrho, const double* eta, const double* Tn, const double* Tm, double* y,
+                 hipStream_t s) {
+  const long long tot = (long long)L.n * L.n * L.n * L.nmacro;
+  dim3 grid((unsigned)((tot + 255) / 256));
+  vfill<double>(y, 0.0, L.n2, s);
+#define TEMP_LAUNCH(M)                                                                                         \
+  do {                                                                                                         \
+    if (L.blend) hipLaunchKernelGGL((k_temp<M, true>), grid, dim3(256), 0, s, L, qr, tc, x, u, lnrho, eta, Tn, Tm, y); \
+    else hipLaunchKernelGGL((k_temp<M, false>), grid, dim3(256), 0, s, L, qr, tc, x, u, lnrho, eta, Tn, Tm, y);        \
+  } while (0)
+  switch (mode) {
+    case TM_APPLY: TEMP_LAUNCH(TM_APPLY); break;
+    case TM_SYM: TEMP_LAUNCH(TM_SYM); break;
+    case TM_DIAG: TEMP_LAUNCH(TM_DIAG); break;
+    default: TEMP_LAUNCH(TM_RHS); break;
+  }
+#undef TEMP_LAUNCH
+}
+
+void launch_mmoc(const LevelDev& L, const LocDev& loc, const double* F, const double* un, const double* uo, double tau,
+                 double* out, hipStream_t s) {
+  const long long tot = (long long)L.nloc2 * L.nmacro;
+  hipLaunchKernelGGL(k_mmoc, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, loc, F, un, uo, tau, out);
+}
+
+void launch_scalar_dirichlet(const uint32_t* node, const uint8_t* kind, int nb, double* v, int set, double vin,
+                             double vout, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_scalar_dirichlet, dim3((nb + 255) / 256), dim3(256), 0, s, node, kind, nb, v, set, vin, vout);
+}
 template void launch_vmass<float>(const LevelDev&, const VmassRule&, const float*, float, const float*, float*, bool,
                                   int, hipStream_t);
 

@@ -49,12 +49,11 @@ MacroMesh make_cube() {
   return mm;
 }
 
-MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out) {
+void icosahedron(double ico[12][3], std::vector<std::array<int, 3>>& faces) {
   const double phi = (1.0 + std::sqrt(5.0)) / 2.0;
   const double raw[12][3] = {{0, 1, phi},  {0, -1, phi},  {0, 1, -phi},  {0, -1, -phi},
                              {1, phi, 0},  {-1, phi, 0},  {1, -phi, 0},  {-1, -phi, 0},
                              {phi, 0, 1},  {-phi, 0, 1},  {phi, 0, -1},  {-phi, 0, -1}};
-  double ico[12][3];
   for (int i = 0; i < 12; ++i) {
     double n = std::sqrt(raw[i][0] * raw[i][0] + raw[i][1] * raw[i][1] + raw[i][2] * raw[i][2]);
     for (int d = 0; d < 3; ++d) ico[i][d] = raw[i][d] / n;
@@ -67,7 +66,7 @@ MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out) {
   double emin = 10;
   for (int i = 0; i < 12; ++i)
     for (int j = i + 1; j < 12; ++j) emin = std::min(emin, dist(i, j));
-  std::vector<std::array<int, 3>> faces;
+  faces.clear();
   for (int i = 0; i < 12; ++i)
     for (int j = i + 1; j < 12; ++j)
       for (int k = j + 1; k < 12; ++k)
@@ -75,6 +74,12 @@ MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out) {
             std::fabs(dist(i, k) - emin) < 1e-9)
           faces.push_back({i, j, k});
   if (faces.size() != 20) throw std::runtime_error("icosahedron faces");
+}
+
+MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out) {
+  double ico[12][3];
+  std::vector<std::array<int, 3>> faces;
+  icosahedron(ico, faces);
 
   // sphere points keyed by their integer weights over the 12 icosahedron vertices
   using Key = std::array<int, 12>;

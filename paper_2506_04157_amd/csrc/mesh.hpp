@@ -36,6 +36,10 @@ struct MacroMesh {
 
 MacroMesh make_cube();
 MacroMesh make_shell(int n_tan, int n_rad, double r_in, double r_out);
+// The unit icosahedron of the shell: 12 vertices and the 20 faces (vertex
+// ids ascending, in the order make_shell refines them; face f's lattice
+// point (i, j) has the weights i, j, n_tan - i - j on its vertices 0, 1, 2).
+void icosahedron(double ico[12][3], std::vector<std::array<int, 3>>& faces);
 
 // Number of lattice points with i+j+k <= s.
 inline int64_t tet_count(int64_t s) { return s < 0 ? 0 : (s + 1) * (s + 2) * (s + 3) / 6; }

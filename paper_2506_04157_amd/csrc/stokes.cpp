@@ -238,6 +238,18 @@ struct stk_ctx {
   DBuf<double> rotX, rotbuf;
   DBuf<double> meanbuf;    // partial sums of the device-side mean removal
   RotDev rotd{};
+  // temperature step: Dirichlet node list of the finest level, the point
+  // locator of the MMOC, work vectors and FGMRES storage
+  struct TempData {
+    bool ready = false;
+    DBuf<uint32_t> bnode;
+    DBuf<uint8_t> bkind;
+    int nb = 0;
+    DBuf<int> prism;
+    DBuf<double> minv;
+    LocDev loc{};
+    DBuf<double> w, fg;
+  } temp;
   DBuf<double> lnrho;
   DBuf<float> lnrhof;
   DBuf<double> vbase;      // radial base viscosity samples (quadrature-point viscosity)
@@ -1048,6 +1060,294 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
   project<double>(c, l, xu);
   project_mean<double>(c, xp);
   return out;
+}
+
+// ---- temperature step (Sec. 3 and Sec. 6, eq. WeakTemp) -----------------------------
+// row-major inverse of a 3x3 matrix given row-major
+void inv3(const double* A, double* B) {
+  const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+  REQUIRE(std::fabs(det) > 0.0, "singular 3x3 matrix in the point locator");
+  B[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+  B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+  B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+  B[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+  B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+  B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+  B[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+  B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+  B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+// Finest-level data of the temperature problem: the Dirichlet node list (both
+// spheres, or the cube's boundary) and the point locator of the MMOC.  The
+// shell's prism table is built geometrically: each macro-tet's centroid
+// direction is classified with the same face / sub-triangle formulas as the
+// device locator, its layer is the lowest of its vertices'.
+void setup_temp(Ctx& c) {
+  if (c.temp.ready) return;
+  const Level& h = c.at(c.L()).h;
+  std::vector<uint32_t> bn(h.bnode.begin(), h.bnode.end());
+  std::vector<uint8_t> bk(h.bkind.begin(), h.bkind.end());
+  c.temp.bnode.upload(bn);
+  c.temp.bkind.upload(bk);
+  c.temp.nb = (int)bn.size();
+  LocDev& loc = c.temp.loc;
+  loc = LocDev{};
+  loc.kind = c.mm.kind;
+  for (int t = 0; t < 6; ++t) {
+    double A[9];
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) A[3 * r + k] = TYPE_OFF[t][k + 1][r] - TYPE_OFF[t][0][r];
+    inv3(A, loc.tinv6[t]);
+  }
+  const int nm = c.mm.nm();
+  std::vector<double> geo = macro_geometry(c.mm);
+  std::vector<double> minv((size_t)nm * 9);
+  for (int m = 0; m < nm; ++m) inv3(&geo[(size_t)m * 16 + 3], &minv[(size_t)m * 9]);
+  c.temp.minv.upload(minv);
+  loc.minv = c.temp.minv.p;
+  if (c.mm.kind == 1) {
+    const int nt = c.desc.n_tan, nr = c.desc.n_rad;
+    loc.n_tan = nt;
+    loc.n_rad = nr;
+    loc.r_in = c.desc.r_in;
+    loc.r_out = c.desc.r_out;
+    double ico[12][3];
+    std::vector<std::array<int, 3>> faces;
+    icosahedron(ico, faces);
+    for (int f = 0; f < 20; ++f) {
+      double A[9];
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) A[3 * r + k] = ico[faces[f][k]][r];
+      inv3(A, loc.fmat[f]);
+    }
+    std::vector<int> prism((size_t)20 * 2 * nt * nt * nr * 3, -1);
+    for (int m = 0; m < nm; ++m) {
+      double cen[3] = {0, 0, 0};
+      int lay = 1 << 30;
+      for (int v = 0; v < 4; ++v) {
+        const int id = c.mm.tets[m][v];
+        for (int d = 0; d < 3; ++d) cen[d] += 0.25 * c.mm.V[3 * id + d];
+        lay = std::min(lay, c.mm.layer[id]);
+      }
+      const double r = std::sqrt(cen[0] * cen[0] + cen[1] * cen[1] + cen[2] * cen[2]);
+      const double d[3] = {cen[0] / r, cen[1] / r, cen[2] / r};
+      int bf = 0;
+      double bc[3] = {0, 0, 0}, bmin = -1e300;
+      for (int f = 0; f < 20; ++f) {
+        const double* M = loc.fmat[f];
+        double cc[3];
+        for (int k = 0; k < 3; ++k) cc[k] = M[3 * k] * d[0] + M[3 * k + 1] * d[1] + M[3 * k + 2] * d[2];
+        const double mn = std::min(cc[0], std::min(cc[1], cc[2]));
+        if (mn > bmin) {
+          bmin = mn;
+          bf = f;
+          for (int k = 0; k < 3; ++k) bc[k] = cc[k];
+        }
+      }
+      const double cs = bc[0] + bc[1] + bc[2];
+      const double xa = nt * bc[0] / cs, xb = nt * bc[1] / cs;
+      const int i = std::min(std::max((int)std::floor(xa), 0), nt - 1);
+      const int j = std::min(std::max((int)std::floor(xb), 0), nt - 1 - i);
+      const int down = ((xa - i) + (xb - j) > 1.0) && (i + j <= nt - 2);
+      const int tri = 2 * (i * nt + j) + down;
+      REQUIRE(lay >= 0 && lay < nr, "macro layer out of range");
+      int* slot = &prism[(((size_t)bf * 2 * nt * nt + tri) * nr + lay) * 3];
+      int s = 0;
+      while (s < 3 && slot[s] >= 0) ++s;
+      REQUIRE(s < 3, "point locator: more than three macro-tets in one prism");
+      slot[s] = m;
+    }
+    for (int f = 0; f < 20; ++f)
+      for (int i = 0; i < nt; ++i)
+        for (int j = 0; i + j < nt; ++j)
+          for (int down = 0; down < 2; ++down) {
+            if (down && i + j > nt - 2) continue;
+            for (int k = 0; k < nr; ++k) {
+              const int* slot = &prism[(((size_t)f * 2 * nt * nt + 2 * (i * nt + j) + down) * nr + k) * 3];
+              REQUIRE(slot[0] >= 0 && slot[1] >= 0 && slot[2] >= 0, "point locator: incomplete prism table");
+            }
+          }
+    c.temp.prism.upload(prism);
+    loc.prism = c.temp.prism.p;
+  }
+  c.temp.ready = true;
+}
+
+TempCoef temp_coef(const stk_temp_params& p) {
+  TempCoef t{};
+  const double t1 = p.tau1, t0 = p.tau0;
+  t.s1 = (2.0 * t1 + t0) / (t1 + t0);
+  t.s0 = (t1 + t0) / t0;
+  t.sm = t1 * t1 / (t0 * (t1 + t0));
+  t.tau = t1;
+  t.kap = p.k / (p.Pe * p.Cp);
+  t.adv = p.adv;
+  t.cad = p.Di * p.alpha / p.Cp;
+  t.hsrc = p.H / p.Cp;
+  t.heat = p.Pe * p.Di / (p.Ra * p.Cp);
+  return t;
+}
+
+void check_temp_params(const stk_temp_params* p) {
+  REQUIRE(p, "null parameters");
+  REQUIRE(p->tau1 > 0 && p->tau0 > 0 && std::isfinite(p->tau1) && std::isfinite(p->tau0),
+          "time steps tau1, tau0 must be positive");
+  REQUIRE(p->Pe != 0 && p->Cp != 0 && p->Ra != 0 && std::isfinite(p->Pe) && std::isfinite(p->Cp) &&
+              std::isfinite(p->Ra),
+          "Pe, Cp and Ra must be finite and nonzero");
+  REQUIRE(p->k >= 0 && std::isfinite(p->k), "k must be finite and >= 0");
+  REQUIRE(std::isfinite(p->Di) && std::isfinite(p->alpha) && std::isfinite(p->H) && std::isfinite(p->adv) &&
+              std::isfinite(p->T_in) && std::isfinite(p->T_out),
+          "non-finite coefficient");
+  REQUIRE(p->tol_abs >= 0 && p->tol_cg > 0 && p->tol_cg < 1, "bad tolerances");
+  REQUIRE(p->restart >= 1 && p->max_outer >= 1 && p->max_cg >= 1, "restart, max_outer and max_cg must be >= 1");
+}
+
+// temperature work vectors of the finest level (n2 each)
+enum { T_US = 0, T_M1, T_M2, T_M3, T_B, T_R, T_D, T_X, T_CR, T_CZ, T_CP, T_CQ, T_TMP, T_NVEC };
+double* twork(Ctx& c, int k) {
+  const long long n2 = n2of(c, c.L());
+  const size_t need = (size_t)(T_NVEC + 2) * n2;   // u* takes 3 n2
+  if (c.temp.w.n < need) c.temp.w.alloc(need);
+  return c.temp.w.p + (k == T_US ? 0 : (size_t)(k + 2) * n2);
+}
+
+void temp_apply(Ctx& c, const TempCoef& tc, int mode, const double* x, const double* u, const double* lnrho,
+                double* y) {
+  LevelData& L = c.at(c.L());
+  launch_temp(L.d, c.vrule, tc, mode, x, u, lnrho, nullptr, nullptr, nullptr, y, c.s);
+}
+void temp_zero_bc(Ctx& c, double* v) {
+  launch_scalar_dirichlet(c.temp.bnode.p, c.temp.bkind.p, c.temp.nb, v, 0, 0.0, 0.0, c.s);
+}
+
+// FGMRES (Saad 1993), right preconditioned, for the scalar temperature system
+// on the vectors with zero Dirichlet rows; x enters as zero.
+template <class Apply, class Prec>
+FgmresOut fgmres_scalar(Ctx& c, long long N, Apply apply, Prec prec, const double* b, double* x, double tol_abs,
+                        int m, int max_outer) {
+  c.temp.fg.alloc((size_t)(2 * m + 1) * N);
+  auto V = [&](int j) { return c.temp.fg.p + (size_t)j * N; };
+  auto Z = [&](int j) { return c.temp.fg.p + (size_t)(m + 1 + j) * N; };
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  auto Hs = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  FgmresOut out;
+  vfill<double>(x, 0.0, N, c.s);
+  const double nb = nrm2<double>(c, b, N);
+  out.r0 = out.rfin = nb;
+  if (nb <= tol_abs || nb == 0.0) {
+    out.converged = true;
+    return out;
+  }
+  double beta = nb;
+  vcopy<double>(b, V(0), N, c.s);
+  int total = 0;
+  while (total < max_outer) {
+    vscale<double>(1.0 / beta, V(0), N, c.s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j_used = 0;
+    for (int j = 0; j < m && total < max_outer; ++j) {
+      prec(V(j), Z(j));
+      apply(Z(j), V(j + 1));
+      for (int i = 0; i <= j; ++i) {
+        Hs(i, j) = dot<double>(c, V(j + 1), V(i), N);
+        vaxpy<double>(-Hs(i, j), V(i), V(j + 1), N, c.s);
+      }
+      Hs(j + 1, j) = nrm2<double>(c, V(j + 1), N);
+      if (Hs(j + 1, j) > 0) vscale<double>(1.0 / Hs(j + 1, j), V(j + 1), N, c.s);
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * Hs(i, j) + sn[i] * Hs(i + 1, j);
+        Hs(i + 1, j) = -sn[i] * Hs(i, j) + cs[i] * Hs(i + 1, j);
+        Hs(i, j) = t;
+      }
+      double den = std::hypot(Hs(j, j), Hs(j + 1, j));
+      cs[j] = Hs(j, j) / den;
+      sn[j] = Hs(j + 1, j) / den;
+      Hs(j, j) = den;
+      Hs(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      j_used = j + 1;
+      if (c.verbose) {
+        std::fprintf(stderr, "[stk] temperature fgmres it %d abs %.3e\n", total, std::fabs(g[j + 1]));
+        std::fflush(stderr);
+      }
+      if (std::fabs(g[j + 1]) <= tol_abs) break;
+    }
+    std::vector<double> yv(j_used);
+    for (int i = j_used - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < j_used; ++k) s -= Hs(i, k) * yv[k];
+      yv[i] = s / Hs(i, i);
+    }
+    for (int i = 0; i < j_used; ++i) vaxpy<double>(yv[i], Z(i), x, N, c.s);
+    // true residual b - A x into V(0)
+    apply(x, V(0));
+    vaxpby<double>(1.0, b, -1.0, V(0), N, c.s);
+    beta = nrm2<double>(c, V(0), N);
+    out.rfin = beta;
+    out.its = total;
+    if (beta <= tol_abs) {
+      out.converged = true;
+      break;
+    }
+  }
+  return out;
+}
+
+// T = solution of the Dirichlet problem L T = b, T = T_in / T_out on the
+// boundary; T_init (nullable) is the starting guess of the free rows.
+void temp_solve(Ctx& c, const stk_temp_params& p, const double* ustar, const double* lnrho, const double* b,
+                const double* T_init, double* T, stk_temp_report* rep) {
+  setup_temp(c);
+  const long long N = n2of(c, c.L());
+  const TempCoef tc = temp_coef(p);
+  double* dinv = twork(c, T_D);
+  double* r = twork(c, T_R);
+  double* dx = twork(c, T_X);
+  double* tmp = twork(c, T_TMP);
+  temp_apply(c, tc, TM_DIAG, nullptr, nullptr, lnrho, tmp);
+  vinvert<double>(tmp, dinv, N, c.s);
+  if (T_init) vcopy<double>(T_init, T, N, c.s);
+  else vfill<double>(T, 0.0, N, c.s);
+  launch_scalar_dirichlet(c.temp.bnode.p, c.temp.bkind.p, c.temp.nb, T, 1, p.T_in, p.T_out, c.s);
+  temp_apply(c, tc, TM_APPLY, T, ustar, lnrho, tmp);
+  vcopy<double>(b, r, N, c.s);
+  vaxpy<double>(-1.0, tmp, r, N, c.s);
+  temp_zero_bc(c, r);
+  int cg_total = 0;
+  auto apply = [&](const double* v, double* y) {
+    temp_apply(c, tc, TM_APPLY, v, ustar, lnrho, y);
+    temp_zero_bc(c, y);
+  };
+  auto prec = [&](const double* v, double* z) {
+    cg_total += dev_pcg<double>(
+        c, N, [&](const double* pp, double* q) {
+          temp_apply(c, tc, TM_SYM, pp, nullptr, lnrho, q);
+          temp_zero_bc(c, q);
+        },
+        [&](double* w) { temp_zero_bc(c, w); }, dinv, v, z, twork(c, T_CR), twork(c, T_CZ), twork(c, T_CP),
+        twork(c, T_CQ), p.tol_cg, p.max_cg, 8);
+  };
+  FgmresOut fo = fgmres_scalar(c, N, apply, prec, r, dx, p.tol_abs, p.restart, p.max_outer);
+  vaxpy<double>(1.0, dx, T, N, c.s);
+  HIPCHK(hipStreamSynchronize(c.s));
+  if (rep) {
+    rep->iterations = fo.its;
+    rep->cg_its = cg_total;
+    rep->converged = fo.converged ? 1 : 0;
+    rep->initial_residual = fo.r0;
+    rep->abs_residual = fo.rfin;
+  }
+  if (!fo.converged) throw StkError(STK_ENOCONV, "temperature FGMRES reached max_outer before tol_abs");
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ---- setup --------------------------------------------------------------------------
@@ -2138,6 +2438,129 @@ int stk_time_apply_A(stk_ctx* ctx, int level, int prec, const void* x, void* y, 
     (void)hipEventDestroy(e2);
     *ms_apply = a / reps;
     if (ms_kernel) *ms_kernel = b / reps;
+  });
+}
+
+// ---- temperature step ---------------------------------------------------------------
+void stk_temp_default_params(stk_temp_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tau1 = 1e-3;
+  p->tau0 = 1e-3;
+  p->k = 1.0;
+  p->Pe = 1.0;
+  p->Cp = 1.0;
+  p->Ra = 1.0;
+  p->T_in = 1.0;
+  p->T_out = 0.0;
+  p->tol_abs = 1e-10;
+  p->tol_cg = 1e-12;
+  p->restart = 30;
+  p->max_outer = 300;
+  p->max_cg = 5000;
+}
+
+int stk_temp_apply(stk_ctx* ctx, const stk_temp_params* p, int mode, const double* u_star, const double* lnrho,
+                   const double* x, double* y) {
+  return guard([&] {
+    REQUIRE(ctx && ctx->lv.size() > 0, "null context");
+    check_temp_params(p);
+    REQUIRE(mode == STK_TEMP_APPLY || mode == STK_TEMP_SYM || mode == STK_TEMP_DIAG, "unknown mode");
+    REQUIRE(y && (x || mode == STK_TEMP_DIAG), "null vector");
+    const int m = mode == STK_TEMP_APPLY ? TM_APPLY : (mode == STK_TEMP_SYM ? TM_SYM : TM_DIAG);
+    temp_apply(*ctx, temp_coef(*p), m, x, mode == STK_TEMP_APPLY ? u_star : nullptr, lnrho, y);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_temp_rhs(stk_ctx* ctx, const stk_temp_params* p, const double* u_star, const double* lnrho, const double* eta,
+                 const double* That_n, const double* That_nm1, double* b) {
+  return guard([&] {
+    REQUIRE(ctx && ctx->lv.size() > 0, "null context");
+    check_temp_params(p);
+    REQUIRE(That_n && That_nm1 && b, "null vector");
+    REQUIRE(!u_star || eta, "eta is needed with a velocity");
+    LevelData& L = ctx->at(ctx->L());
+    launch_temp(L.d, ctx->vrule, temp_coef(*p), TM_RHS, nullptr, u_star, lnrho, eta, That_n, That_nm1, b, ctx->s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_mmoc(stk_ctx* ctx, const double* F, const double* u_new, const double* u_old, double tau, double* out) {
+  return guard([&] {
+    REQUIRE(ctx && ctx->lv.size() > 0, "null context");
+    REQUIRE(F && u_new && u_old && out, "null vector");
+    REQUIRE(F != out, "F and out must be distinct buffers");
+    REQUIRE(std::isfinite(tau) && tau >= 0, "tau must be finite and >= 0");
+    setup_temp(*ctx);
+    launch_mmoc(ctx->at(ctx->L()).d, ctx->temp.loc, F, u_new, u_old, tau, out, ctx->s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int stk_temp_solve(stk_ctx* ctx, const stk_temp_params* p, const double* u_star, const double* lnrho,
+                   const double* b, const double* T_init, double* T, stk_temp_report* rep) {
+  return guard([&] {
+    REQUIRE(ctx && ctx->lv.size() > 0, "null context");
+    check_temp_params(p);
+    REQUIRE(b && T, "null vector");
+    REQUIRE(T != b && T_init != b, "T must not alias b");
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    const auto t0 = std::chrono::steady_clock::now();
+    temp_solve(*ctx, *p, u_star, lnrho, b, T_init, T, rep);
+    if (rep) rep->ms_solve = ms_since(t0);
+  });
+}
+
+int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T_n, const double* T_nm1,
+                         const double* u_n, const double* u_nm1, const double* lnrho, const double* eta,
+                         double* T_np1, double* That_n, double* That_nm1, stk_temp_report* rep) {
+  return guard([&] {
+    REQUIRE(ctx && ctx->lv.size() > 0, "null context");
+    check_temp_params(p);
+    REQUIRE(T_n && T_nm1 && u_n && u_nm1 && eta && T_np1, "null vector");
+    REQUIRE(T_np1 != T_n && T_np1 != T_nm1, "T_np1 must not alias T_n or T_nm1");
+    for (const double* o : {That_n, That_nm1})
+      REQUIRE(!o || (o != T_n && o != T_nm1 && o != T_np1), "traced outputs must not alias the temperatures");
+    REQUIRE(!That_n || That_n != That_nm1, "That_n and That_nm1 must be distinct");
+    Ctx& c = *ctx;
+    setup_temp(c);
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    const long long n2 = n2of(c, c.L());
+    LevelData& L = c.at(c.L());
+    double* us = twork(c, T_US);
+    double* thn = That_n ? That_n : twork(c, T_M1);
+    double* thm = That_nm1 ? That_nm1 : twork(c, T_M2);
+    double* mid = twork(c, T_M3);
+    double* b = twork(c, T_B);
+    auto t0 = std::chrono::steady_clock::now();
+    const double q = p->tau1 / p->tau0;
+    vcopy<double>(u_n, us, 3 * n2, c.s);
+    vaxpby<double>(-q, u_nm1, 1.0 + q, us, 3 * n2, c.s);
+    launch_mmoc(L.d, c.temp.loc, T_n, us, u_n, p->tau1, thn, c.s);
+    launch_mmoc(L.d, c.temp.loc, T_nm1, u_n, u_nm1, p->tau0, mid, c.s);
+    launch_mmoc(L.d, c.temp.loc, mid, us, u_n, p->tau1, thm, c.s);
+    HIPCHK(hipStreamSynchronize(c.s));
+    const double ms_mmoc = ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
+    launch_temp(L.d, c.vrule, temp_coef(*p), TM_RHS, nullptr, us, lnrho, eta, thn, thm, b, c.s);
+    HIPCHK(hipStreamSynchronize(c.s));
+    const double ms_rhs = ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
+    stk_temp_report local{};
+    try {
+      temp_solve(c, *p, us, lnrho, b, T_n, T_np1, &local);
+    } catch (...) {
+      local.ms_mmoc = ms_mmoc;
+      local.ms_rhs = ms_rhs;
+      local.ms_solve = ms_since(t0);
+      if (rep) *rep = local;
+      throw;
+    }
+    local.ms_mmoc = ms_mmoc;
+    local.ms_rhs = ms_rhs;
+    local.ms_solve = ms_since(t0);
+    if (rep) *rep = local;
   });
 }
 
