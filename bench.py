@@ -320,6 +320,9 @@ def main():
                          "setting): every Uzawa variant with the V-cycle BFBT, mass, and symmetric and "
                          "asymmetric weighted BFBT, stopped at an absolute residual of 1e-8; use with "
                          "--n-tan 2 --n-rad 1")
+    ap.add_argument("--temp-study", action="store_true",
+                    help="only the temperature step (Sec. 3 splitting, eq. WeakTemp) on the shell and level "
+                         "given: MMOC, right-hand side and FGMRES solve timings, kernel times")
     ap.add_argument("--l-eta-study", action="store_true",
                     help="only the coarse-viscosity study: A-block CG iterations and time of 10 FGMRES "
                          "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
@@ -329,7 +332,7 @@ def main():
               "part of this build", file=sys.stderr)
         sys.exit(2)
     if (args.apply_only or args.transfer_only or args.l_eta_study or args.contrast_study or args.large_apply
-            or args.schur_study):
+            or args.schur_study or args.temp_study):
         return studies(args)
 
     n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
@@ -532,6 +535,8 @@ def studies(args):
             return contrast_study(args, sc, dev, Nu, Np)
         if args.schur_study:
             return schur_study(args, sc, dev, Nu, Np)
+        if args.temp_study:
+            return temp_study(args, sc, dev, Nu, Np)
         X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
         X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
         field = inputs.SHField(2)
@@ -684,6 +689,73 @@ def contrast_study(args, sc, dev, Nu, Np):
                             "u_rel_diff": (torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)).item(),
                             "p_rel_diff": (torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)).item()}
     print(json.dumps({"contrast_study": out}), flush=True)
+
+
+def temp_study(args, sc, dev, Nu, Np):
+    """The temperature step at the given size with the paper's nondimensional
+    numbers (Ra = 1.692e7, Pe = 2.822e4, Di = 0.4538, alpha = k = Cp = H = 1,
+    T_in = 4200/3900, T_out = 300/3900, tol_T = 1e-10): a seeded SH
+    temperature, a smooth seeded velocity of magnitude about 1, viscosity
+    contrast 1e4 at the temperature, rho = exp(0.5 (1 - r)), tau = 2e-3
+    (displacements of about a sixth of a micro-tet).  Three steps (the first
+    builds the point locator), then single launches of the MMOC and of the
+    operator timed with HIP events on the library's stream."""
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2506_04157_amd import temp_params
+    n2 = Nu // 3
+    field = inputs.SHField(2)
+    X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
+    T2 = field.temperature_torch(X2).contiguous()
+    u_n = inputs.smooth_vector_field_torch(11, X2).contiguous()
+    u_nm1 = (0.9 * u_n).contiguous()
+    del X2
+    X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
+    eta = torch.exp(float(np.log(1e4)) * (0.5 - field.temperature_torch(X1))).contiguous()
+    lnrho = (0.5 * (1.0 - torch.linalg.norm(X1, dim=1))).contiguous()
+    del X1
+    log("temperature inputs ready")
+    prm = temp_params(tau1=2e-3, tau0=2e-3, k=1.0, Pe=2.822e4, Cp=1.0, Di=0.4538, alpha=1.0, H=1.0, Ra=1.692e7,
+                      T_in=4200.0 / 3900.0, T_out=300.0 / 3900.0, tol_abs=1e-10)
+    T_nm1 = T2.clone()
+    T_n = T2
+    steps = []
+    for it in range(3):
+        T_np1, rep = sc.temperature_step(T_n, T_nm1, u_n, u_nm1, eta, prm, lnrho=lnrho)
+        torch.cuda.synchronize()
+        steps.append(rep)
+        log(f"step {it}: mmoc {rep['ms_mmoc']:.1f} ms, rhs {rep['ms_rhs']:.1f} ms, solve {rep['ms_solve']:.1f} ms, "
+            f"{rep['iterations']} FGMRES its, {rep['cg_its']} CG its, residual {rep['abs_residual']:.2e}")
+        T_nm1, T_n = T_n, T_np1
+    st = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps=5):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+    out_buf = torch.empty_like(T2)
+    ms_mmoc = timed(lambda: sc.mmoc(T_n, u_n, u_nm1, 2e-3, out=out_buf))
+    ms_apply = timed(lambda: sc.temp_apply(T_n, prm, 0, u_star=u_n, lnrho=lnrho, out=out_buf))
+    ms_sym = timed(lambda: sc.temp_apply(T_n, prm, 1, lnrho=lnrho, out=out_buf))
+    n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
+    last = steps[-1]
+    out = {"workload": f"shell {args.n_tan}x{args.n_rad} level {args.level}, temperature nodes {n2}, "
+                       f"micro-tets {n_tets}",
+           "params": {k: getattr(prm, k) for k, _ in prm._fields_},
+           "steps": steps,
+           "mmoc_launch_ms": ms_mmoc, "mmoc_gnodes_per_s": n2 / ms_mmoc * 1e-6,
+           "apply_L_ms": ms_apply, "apply_L_gdof_per_s": n2 / ms_apply * 1e-6,
+           "apply_S_ms": ms_sym, "apply_S_gdof_per_s": n2 / ms_sym * 1e-6,
+           "step_ms": last["ms_mmoc"] + last["ms_rhs"] + last["ms_solve"],
+           "mmoc_share": last["ms_mmoc"] / (last["ms_mmoc"] + last["ms_rhs"] + last["ms_solve"])}
+    print(json.dumps({"temp_study": out}), flush=True)
 
 
 def schur_study(args, sc, dev, Nu, Np):

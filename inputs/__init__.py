@@ -134,6 +134,23 @@ def smooth_vector_field(seed, xyz, k=3):
     return out
 
 
+def smooth_vector_field_torch(seed, xyz, k=3):
+    """smooth_vector_field for an (n, 3) float64 torch tensor, evaluated where
+    the tensor lives; returned component-major (3 n), as the solver stores
+    velocities."""
+    import torch
+    rng = np.random.default_rng(seed)
+    out = torch.zeros(3, xyz.shape[0], dtype=torch.float64, device=xyz.device)
+    for _ in range(k):
+        w = rng.normal(0.0, 3.0, 3)
+        ph = rng.uniform(0, 2 * np.pi)
+        a = rng.uniform(-1, 1, 3)
+        s = torch.sin(float(w[0]) * xyz[:, 0] + float(w[1]) * xyz[:, 1] + float(w[2]) * xyz[:, 2] + ph)
+        for c in range(3):
+            out[c] += float(a[c]) * s
+    return out.reshape(-1)
+
+
 def plate_velocity(seed, xyz, n_plates=6, scale=0.5):
     """Synthetic tangential surface velocity: the sphere split into
     ``n_plates`` Voronoi plates around seeded centres, each rotating rigidly

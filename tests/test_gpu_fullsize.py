@@ -208,3 +208,31 @@ def test_sampled_fp32_chebyshev_step_at_full_size(full, mac_id):
     e = np.abs(xg - ref).max() / np.abs(ref).max()
     print(mac_id, "chebyshev", int(deep.sum()), "nodes", e)
     assert e <= 1e-5
+
+
+def test_mmoc_rigid_rotation_at_full_size(full):
+    """The method of characteristics at full size (66.6 million P2 nodes):
+    without velocity every node is its own departure point; for a
+    rigid rotation about z the departure point of X is R(-w tau) X, and a
+    function linear in the physical coordinates is evaluated there up to the
+    blended P2 interpolation error (order h^3) of the velocity and of the
+    function: a point located in a wrong micro-tet would be off by order h."""
+    sc, X2, _ = full
+    Xt = torch.tensor(X2, device="cuda")
+    # elementwise (torch's matrix-vector product is not used at this size)
+    lin = lambda Y: (0.7 * Y[:, 0] - 0.4 * Y[:, 1] + 1.1 * Y[:, 2] + 0.3).contiguous()
+    F = lin(Xt)
+    z = torch.zeros(3 * len(X2), dtype=torch.float64, device="cuda")
+    got = sc.mmoc(F, z, z, 0.05)
+    # exact up to the rounding of the inverse blending and of the barycentric
+    # coordinates (node values about 2)
+    assert (got - F).abs().max().item() < 2e-12
+    w, tau = 1.0, 0.05
+    u = torch.cat([-w * Xt[:, 1], w * Xt[:, 0], torch.zeros_like(Xt[:, 0])]).contiguous()
+    got = sc.mmoc(F, u, u, tau)
+    c, s = np.cos(-w * tau), np.sin(-w * tau)
+    Xd = torch.stack([c * Xt[:, 0] - s * Xt[:, 1], s * Xt[:, 0] + c * Xt[:, 1], Xt[:, 2]], dim=1)
+    err = (got - lin(Xd)).abs().max().item()
+    moved = (F - lin(Xd)).abs().max().item()
+    print(f"rotation: max error {err:.2e}, displacement effect {moved:.2e}")
+    assert err < 2e-5 and moved > 1e-2
