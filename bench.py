@@ -43,7 +43,10 @@ sys.path.insert(0, ROOT)
 # points): the FP32 sweep's element loop counted from its gfx950 assembly
 # (fma/fmac/fmamk = 2 flops, mul/add/sub = 1, rsq/rcp = 1).  The FP64 kernel
 # executes about 100 more per micro-tet, the Newton steps of its rsq/rcp; they
-# are not counted as algorithmic work.
+# are not counted as algorithmic work.  The committed counter summary
+# (FLOPS_FILE) holds this figure with the sweep-source hash it was checked on
+# and the executed flops the VALU counters report per micro-tet; a figure whose
+# hash no longer matches is reported as unverified.
 A_FLOPS_PER_TET = 1194
 PEAK_FP64_TFLOPS = 78.6           # MI355X published FP64 vector peak
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak (packed)
@@ -52,7 +55,9 @@ PEAK_HBM_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILES = {64: os.path.join(PROFILES, "traffic_k_sweep_A_fp64_shell10x2_L4.txt"),
                  32: os.path.join(PROFILES, "traffic_k_sweep_A_fp32_shell10x2_L4.txt")}
+FLOPS_FILE = os.path.join(PROFILES, "flops_k_sweep_A_shell10x2_L4.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_04157_amd", "csrc", "kernels.hip")
+DEVICE_HDR = os.path.join(ROOT, "paper_2506_04157_amd", "csrc", "device.hpp")
 ROOF_KERNELS = {64: "k_sweep<double, true, 1>", 32: "k_sweep<float, true, 1>"}
 METRIC = "A-apply GDoF/s + time-to-1e-8 Stokes solve, FP32-MG vs FP64, 1 MI355X"
 
@@ -61,9 +66,43 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _between(text, start, end):
+    i = text.index(start) if start else 0
+    return text[i:text.index(end, i)]
+
+
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the source the roofline kernel is built from: kernels.hip up to
+    the end of the plane sweep (its helpers, the element arithmetic and the
+    kernel), the sweep's launch wrapper, and device.hpp up to the sweep's LDS
+    layout.  Kernels elsewhere in the files do not change it."""
+    with open(KERNEL_SRC) as fh:
+        k = fh.read()
+    with open(DEVICE_HDR) as fh:
+        d = fh.read()
+    parts = [_between(k, None, "// Element-parallel variant for coarse levels"),
+             _between(k, "void launch_stokes(", "\n}\n"),
+             _between(d, None, "size_t sweep_lds_bytes")]
+    return hashlib.sha256("\0".join(parts).encode()).hexdigest()[:16]
+
+
+def _kv(path):
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
+def read_flops():
+    """(algorithmic flops per micro-tet, verified): verified when the counter
+    summary was taken on the current sweep source."""
+    if not os.path.exists(FLOPS_FILE):
+        return A_FLOPS_PER_TET, False
+    kv = _kv(FLOPS_FILE)
+    return A_FLOPS_PER_TET, kv.get("kernel_source_sha256_16") == kernel_sha()
 
 
 def read_traffic(prec=64):
@@ -72,12 +111,7 @@ def read_traffic(prec=64):
     path = TRAFFIC_FILES[prec]
     if not os.path.exists(path):
         return None
-    kv = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
+    kv = _kv(path)
     if kv.get("kernel_source_sha256_16") != kernel_sha():
         return None
     try:
@@ -236,6 +270,31 @@ def summarize_traffic(dfetch, dwrite, n_u, out, cmd, kernel=ROOF_KERNEL):
     print("\n".join(lines))
 
 
+def summarize_flops(d, n_tets, out, cmd):
+    """Executed VALU flops per micro-tet of the two finest-level sweep kernels
+    (the largest grid of each) from a rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP64
+    SQ_INSTS_VALU_FLOPS_FP32 run, next to the algorithmic count, with the hash
+    of the sweep source they were taken on."""
+    acc = {}
+    for r in _rows(os.path.join(d, "run_counter_collection.csv")):
+        key = (r["Kernel_Name"], int(r["Grid_Size"]), r["Counter_Name"])
+        acc.setdefault(key, []).append(float(r["Counter_Value"]))
+    lines = ["# VALU flops of the A-apply sweep kernels (finest level, largest grid)", f"# command: {cmd}",
+             f"kernel_source_sha256_16: {kernel_sha()}", f"micro_tets: {n_tets}",
+             f"algorithmic_flops_per_micro_tet: {A_FLOPS_PER_TET}"]
+    for prec, counter in ((64, "SQ_INSTS_VALU_FLOPS_FP64"), (32, "SQ_INSTS_VALU_FLOPS_FP32")):
+        name = ROOF_KERNELS[prec]
+        cands = [(g, sum(v) / len(v)) for (k, g, c), v in acc.items() if name in k and c == counter]
+        if not cands:
+            lines.append(f"executed_flops_per_micro_tet_fp{prec}: n/a")
+            continue
+        g, val = max(cands)
+        lines.append(f"executed_flops_per_micro_tet_fp{prec}: {val / n_tets:.1f}  ({counter}, grid {g})")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_counters(d, out, cmd, match):
     """Per-kernel averages of every counter of a rocprofv3 --pmc run over the
     dispatches whose kernel name contains `match`, grouped by grid size."""
@@ -261,13 +320,15 @@ def _roofline(prec, n_tets, nu, np_, ms_kernel, traffic):
     HBM."""
     peak = PEAK_FP64_TFLOPS if prec == 64 else PEAK_FP32_TFLOPS
     wb = 8 if prec == 64 else 4
-    flops = A_FLOPS_PER_TET * n_tets
+    fpt, verified = read_flops()
+    flops = fpt * n_tets
     achieved = flops / (ms_kernel * 1e-3) / 1e12
     algo_bytes = (2 * nu + np_) * wb
     r = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
          "traffic": traffic,
          "kernel": f"{ROOF_KERNELS[prec]} (A-apply plane sweep, finest level)",
-         "ms_per_launch": ms_kernel, "flops_per_launch": flops, "flops_per_micro_tet": A_FLOPS_PER_TET,
+         "ms_per_launch": ms_kernel, "flops_per_launch": flops, "flops_per_micro_tet": fpt,
+         "flops_checked_on_current_source": verified,
          "hbm_gbs_algorithmic": algo_bytes / (ms_kernel * 1e-3) / 1e9,
          "hbm_frac_algorithmic": algo_bytes / (ms_kernel * 1e-3) / 1e9 / PEAK_HBM_GBS,
          "algorithmic_bytes_per_launch": algo_bytes}
@@ -283,6 +344,10 @@ def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         # bench.py --summarize-counters DIR OUT "COMMAND" KERNEL_SUBSTRING
         summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-flops":
+        # bench.py --summarize-flops DIR MICRO_TETS OUT "COMMAND"
+        summarize_flops(sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
         # bench.py --summarize-profile DIR OUT "COMMAND" [KERNEL]

@@ -121,3 +121,43 @@ def test_roofline_fields():
     assert r["hbm_gbs_algorithmic"] == pytest.approx((2 * 300 + 20) * 8 / 2e-3 / 1e9)
     r32 = bench._roofline(32, 1000, 300, 20, 2.0, 4960.0)
     assert r32["peak"] == bench.PEAK_FP32_TFLOPS and r32["traffic_over_algorithmic"] == pytest.approx(2.0)
+
+
+def test_flop_figure_is_checked_against_the_sweep_source(tmp_path, monkeypatch):
+    """The flop count per micro-tet is reported as checked only when the
+    counter summary was taken on the current sweep source; the summariser
+    divides the executed-flop counters of the largest grid by the micro-tets."""
+    f = tmp_path / "flops.txt"
+    monkeypatch.setattr(bench, "FLOPS_FILE", str(f))
+    assert bench.read_flops() == (bench.A_FLOPS_PER_TET, False)
+    d = tmp_path / "pmc"
+    d.mkdir()
+    k64 = f"void stk::{bench.ROOF_KERNELS[64]}(stk::LevelDev, ...)"
+    k32 = f"void stk::{bench.ROOF_KERNELS[32]}(stk::LevelDev, ...)"
+    _write_csv(d / "run_counter_collection.csv", ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"], [
+        [k64, 6144, "SQ_INSTS_VALU_FLOPS_FP64", 130000.0],
+        [k64, 6144, "SQ_INSTS_VALU_FLOPS_FP64", 132000.0],
+        [k64, 1536, "SQ_INSTS_VALU_FLOPS_FP64", 99.0],
+        [k32, 6144, "SQ_INSTS_VALU_FLOPS_FP32", 120000.0],
+    ])
+    bench.summarize_flops(str(d), 100, str(f), "cmd")
+    kv = bench._kv(str(f))
+    assert kv["executed_flops_per_micro_tet_fp64"].startswith("1310.0")
+    assert kv["executed_flops_per_micro_tet_fp32"].startswith("1200.0")
+    assert bench.read_flops() == (bench.A_FLOPS_PER_TET, True)
+    f.write_text("kernel_source_sha256_16: 0000000000000000\n")
+    assert bench.read_flops() == (bench.A_FLOPS_PER_TET, False)
+
+
+def test_sweep_hash_ignores_kernels_outside_the_sweep(tmp_path, monkeypatch):
+    """A change after the sweep (another kernel) keeps the hash; a change in
+    the sweep's source changes it."""
+    src = open(bench.KERNEL_SRC).read()
+    base = bench.kernel_sha()
+    k = tmp_path / "k.hip"
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(k))
+    k.write_text(src + "\n// another kernel\n")
+    assert bench.kernel_sha() == base
+    i = src.index("k_sweep(")
+    k.write_text(src[:i] + " " + src[i:])
+    assert bench.kernel_sha() != base
