@@ -163,6 +163,51 @@ def test_vcycle_matches_assembled_vcycle(kind, L, lmin):
         assert relerr(P.u_to_or(x32), ref) < 1e-4
 
 
+def test_vcycle_bfbt_step_matches_oracle():
+    """The V-cycle BFBT of eq. (schurV) as a component: one symmetric Uzawa
+    step whose Schur inverse is (B C^-1 B^T)^-1 (B C^-1 A C^-1 B^T)
+    (B C^-1 B^T)^-1 with C^-1 one V-cycle (Chebyshev degree 1, one step,
+    exact coarse solve), the two outer solves by CG preconditioned with
+    M_{1/eta} to 1e-13, the A-block solve to 1e-12; against the oracle's
+    `bfbt` with its assembled V-cycle, a CG to 1e-14 for B C^-1 B^T and exact
+    projected solves elsewhere (1×1 shell, level 2, variable eta)."""
+    from oracle.fem import assemble_M_inv_eta
+    from oracle.solvers import bfbt, pcg, symmetric_uzawa
+    from paper_2506_04157_amd._lib import SCHUR_VBFBT, UZAWA_SYMMETRIC
+    print("\n[V-cycle BFBT shell L2]", flush=True)
+    P = Pair("shell", 2, min_level=0)
+    m = P.meshes[2]
+    eta = _eta(m)
+    levels = _oracle_levels(P, eta, {})
+    for l, (lo, hi) in _power_bounds(levels, 0).items():
+        levels[l]["lo"], levels[l]["hi"] = lo, hi
+        P.ctx.set_cheb_bounds(l, lo, hi)
+    params = default_params(precision=64, tol_A=1e-12, tol_vbfbt=1e-13, tol_invmass=1e-14, tol_coarse=1e-15,
+                            max_inner=2000, uzawa=UZAWA_SYMMETRIC, schur=SCHUR_VBFBT)
+    P.ctx.set_fields(P.p_to_lib(eta), params=params)
+    ru = inputs.uniform(61, 3 * m.n2)
+    rp = inputs.uniform(62, m.n1)
+    zu, zp = P.ctx.precondition(P.u_to_lib(ru), P.p_to_lib(rp), params=params)
+    zu, zp = P.u_to_or(zu), P.p_to_or(zp)
+    A, Pm, Q = levels[-1]["A"], levels[-1]["P"], levels[-1]["Q"]
+    B = assemble_B(m)
+    Q0 = levels[0]["Q"]
+    lu0 = spla.splu((Q0.T @ levels[0]["A"] @ Q0).tocsc())
+    cs = lambda r: Q0 @ lu0.solve(Q0.T @ r)
+    V = lambda b: vcycle(levels, 2, Pm @ b, cs, params.deg_V, params.m_V)
+    Alu = spla.splu((Q.T @ A @ Q).tocsc())
+    Ainv = lambda r: Q @ Alu.solve(Q.T @ r)
+    Mlu = spla.splu(assemble_M_inv_eta(m, eta).tocsc())
+    mean0 = lambda v: v - v.mean()
+    SC = lambda p: mean0(B @ (Pm @ V(Pm @ (B.T @ p))))
+    solve_BAB = lambda r: mean0(pcg(SC, mean0(r), lambda v: mean0(Mlu.solve(v)), 1e-14, maxit=2000)[0])
+    Sinv = lambda r: bfbt(mean0(r), (B @ Pm).tocsr(), (Pm @ B.T).tocsr(), (Pm @ A @ Pm).tocsr(), V, solve_BAB)
+    uo, po = symmetric_uzawa(ru, mean0(rp), A, B.T, B, Ainv, Sinv, params.sigma, params.omega)
+    eu, ep = relerr(zu, uo), relerr(zp, mean0(po))
+    print(f"V-cycle BFBT step: u {eu:.2e}, p {ep:.2e}")
+    assert eu < 1e-8 and ep < 1e-8
+
+
 def _oracle_solution(P, eta, lnrho, f, uD=None, transpose=False):
     m = P.meshes[P.L]
     A = assemble_A(m, eta)
