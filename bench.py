@@ -786,14 +786,18 @@ def temp_study(args, sc, dev, Nu, Np):
                       T_in=4200.0 / 3900.0, T_out=300.0 / 3900.0, tol_abs=1e-10)
     T_nm1 = T2.clone()
     T_n = T2
-    steps = []
-    for it in range(3):
+    steps, steps_mf = [], []
+    for it in range(4):
+        # the last step with the matrix-free S in the preconditioner's CG
+        prm.stored_S = 1 if it < 3 else 0
         T_np1, rep = sc.temperature_step(T_n, T_nm1, u_n, u_nm1, eta, prm, lnrho=lnrho)
         torch.cuda.synchronize()
-        steps.append(rep)
+        (steps if it < 3 else steps_mf).append(rep)
         log(f"step {it}: mmoc {rep['ms_mmoc']:.1f} ms, rhs {rep['ms_rhs']:.1f} ms, solve {rep['ms_solve']:.1f} ms, "
-            f"{rep['iterations']} FGMRES its, {rep['cg_its']} CG its, residual {rep['abs_residual']:.2e}")
+            f"{rep['iterations']} FGMRES its, {rep['cg_its']} CG its, residual {rep['abs_residual']:.2e}, "
+            f"stored S {rep['stored_S']}")
         T_nm1, T_n = T_n, T_np1
+    prm.stored_S = 1
     st = torch.cuda.current_stream(dev)
 
     def timed(fn, reps=5):
@@ -814,7 +818,9 @@ def temp_study(args, sc, dev, Nu, Np):
     out = {"workload": f"shell {args.n_tan}x{args.n_rad} level {args.level}, temperature nodes {n2}, "
                        f"micro-tets {n_tets}",
            "params": {k: getattr(prm, k) for k, _ in prm._fields_},
-           "steps": steps,
+           "steps": steps, "step_matrix_free_S": steps_mf,
+           "solve_ms_per_cg_iteration": steps[-1]["ms_solve"] / max(steps[-1]["cg_its"], 1),
+           "solve_ms_per_cg_iteration_matrix_free": steps_mf[-1]["ms_solve"] / max(steps_mf[-1]["cg_its"], 1),
            "mmoc_launch_ms": ms_mmoc, "mmoc_gnodes_per_s": n2 / ms_mmoc * 1e-6,
            "apply_L_ms": ms_apply, "apply_L_gdof_per_s": n2 / ms_apply * 1e-6,
            "apply_S_ms": ms_sym, "apply_S_gdof_per_s": n2 / ms_sym * 1e-6,

@@ -336,6 +336,10 @@ typedef struct {
   double tol_abs;        /* FGMRES stop |b - L T| <= tol_abs on the free rows (tol_T) */
   double tol_cg;         /* relative tolerance of the preconditioner's CG */
   int restart, max_outer, max_cg;
+  int stored_S;          /* 1: the CG applies S through element matrices stored for the
+                            solve (55 doubles per slot of the finest level's 4^3-cube
+                            bricks, about 1.9 slots per micro-tet; used only if that memory
+                            is free); 0: matrix-free */
 } stk_temp_params;
 typedef struct {
   int iterations;           /* FGMRES iterations */
@@ -343,16 +347,18 @@ typedef struct {
   int converged;
   double initial_residual, abs_residual;
   double ms_mmoc, ms_rhs, ms_solve;   /* host clock, stream synchronised (step only) */
+  int stored_S;             /* 1 if the solve used stored element matrices of S */
 } stk_temp_report;
 /* tau1 = tau0 = 1e-3, k = Pe = Cp = Ra = 1, Di = alpha = H = adv = 0,
  * T_in = 1, T_out = 0, tol_abs = 1e-10 (table parametertable's tol_T),
- * tol_cg = 1e-12 (the paper applies the preconditioner "exactly"),
- * restart 30, max_outer 300, max_cg 5000. */
+ * tol_cg = 1e-12 (the paper applies the preconditioner exactly),
+ * restart 30, max_outer 300, max_cg 5000, stored_S = 1. */
 void stk_temp_default_params(stk_temp_params* p);
 #define STK_TEMP_APPLY 0   /* y = L x (no Dirichlet rows) */
 #define STK_TEMP_SYM 1     /* y = S x, S = s^{n+1} M + tau k/(Pe Cp) K_{1/rho}: the
                               symmetric mass and diffusion part the preconditioner's CG solves */
 #define STK_TEMP_DIAG 2    /* y = diag(S) (x ignored, may be NULL) */
+#define STK_TEMP_SYM_STORED 3  /* y = S x through stored element matrices (built by the call) */
 /* Operator applies for parity tests: y (n_p2) overwritten, no boundary rows;
  * u_star may be NULL (no velocity). */
 int stk_temp_apply(stk_ctx* ctx, const stk_temp_params* p, int mode, const double* u_star, const double* lnrho,

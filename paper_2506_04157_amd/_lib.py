@@ -50,19 +50,20 @@ class TempParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("H", ctypes.c_double), ("Ra", ctypes.c_double),
                 ("adv", ctypes.c_double), ("T_in", ctypes.c_double), ("T_out", ctypes.c_double),
                 ("tol_abs", ctypes.c_double), ("tol_cg", ctypes.c_double), ("restart", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("max_cg", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("max_cg", ctypes.c_int), ("stored_S", ctypes.c_int)]
 
 
 class TempReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("cg_its", ctypes.c_int), ("converged", ctypes.c_int),
                 ("initial_residual", ctypes.c_double), ("abs_residual", ctypes.c_double),
-                ("ms_mmoc", ctypes.c_double), ("ms_rhs", ctypes.c_double), ("ms_solve", ctypes.c_double)]
+                ("ms_mmoc", ctypes.c_double), ("ms_rhs", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("stored_S", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-TEMP_APPLY, TEMP_SYM, TEMP_DIAG = 0, 1, 2
+TEMP_APPLY, TEMP_SYM, TEMP_DIAG, TEMP_SYM_STORED = 0, 1, 2, 3
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int

@@ -212,6 +212,14 @@ enum { TM_APPLY = 0, TM_SYM = 1, TM_DIAG = 2, TM_RHS = 3 };
 void launch_temp(const LevelDev& L, const VmassRule& qr, const TempCoef& tc, int mode, const double* x,
                  const double* u, const double* lnrho, const double* eta, const double* Tn, const double* Tm, double* y,
                  hipStream_t s);
+// S = s1 M + tk K_{1/rho} as stored element matrices (55 doubles per brick
+// slot: nmacro * ntiles * 384 slots of the finest level's bricks, entry-major),
+// and y = S x with them (y overwritten).
+constexpr int TEMP_SMAT_ENTRIES = 55;
+size_t temp_smat_slots(const LevelDev& L);
+void launch_temp_smat(const LevelDev& L, const VmassRule& qr, double s1, double tk, const double* lnrho, double* S,
+                      hipStream_t s);
+void launch_temp_sapply(const LevelDev& L, const double* S, const double* x, double* y, hipStream_t s);
 // Point location in the blended mesh.  Shell: the icosahedral face whose cone
 // holds the direction (fmat: inverse of the face's vertex matrix), the
 // sub-triangle of its n_tan lattice, the radial layer, and among the prism's

@@ -1275,6 +1275,84 @@ __global__ __launch_bounds__(256) void k_vmass(LevelDev L, VmassRule qr, const R
 }
 
 // ---- temperature step (Sec. 3 and Sec. 6, eq. WeakTemp) -------------------------
+// P2 basis at one point of a micro-tet: the reference point xq, the weight W
+// (rule weight times |det J_F| |det J_B|), the physical gradients gL of the
+// barycentric coordinates (J_B^{-T} applied to the affine ones), the values N
+// and the physical gradients dN of the ten basis functions.
+template <bool BLEND>
+__device__ __forceinline__ void temp_point(const double* G, const double xv[4][3], const double gl[3][3],
+                                           const double lam[4], double wdet, double xq[3], double& W,
+                                           double gL[4][3], double N[10], double dN[10][3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) xq[r] = lam[0] * xv[0][r] + lam[1] * xv[1][r] + lam[2] * xv[2][r] + lam[3] * xv[3][r];
+  QGeo<double, BLEND> geo;
+  geo.eval(G, xq, wdet);
+  W = geo.W;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gL[i + 1][k] = gl[i][k];
+    geo.JinvT(gL[i + 1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gL[0][k] = -(gL[1][k] + gL[2][k] + gL[3][k]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    N[v] = lam[v] * (2.0 * lam[v] - 1.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dN[v][k] = (4.0 * lam[v] - 1.0) * gL[v][k];
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    N[4 + ed] = 4.0 * lam[i] * lam[j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dN[4 + ed][k] = 4.0 * (lam[i] * gL[j][k] + lam[j] * gL[i][k]);
+  }
+}
+
+// Element data of the temperature kernels: the ten global P2 nodes, the four
+// P1 nodes' ln rho (0 without), the reference vertices and the affine
+// gradients of the barycentric coordinates 1..3 with |det J_F|.
+struct TempElem {
+  size_t g2[10];
+  uint32_t g1[4];
+  double xv[4][3], gl[3][3], detF;
+  const double* G;
+};
+__device__ __forceinline__ void temp_elem(const LevelDev& L, int mac, int pk, TempElem& e) {
+  const int type = pk & 7, px = (pk >> 3) & 1023, py = (pk >> 13) & 1023, pz = pk >> 23;
+  const int n = L.n, m2 = 2 * n;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
+  e.G = L.geo + (size_t)mac * 16;
+  int I2[10], J2[10], K2[10];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int I = px + c_toff[type][v][0], J = py + c_toff[type][v][1], K = pz + c_toff[type][v][2];
+    e.g1[v] = l1[lloc(I, J, K, n)];
+    I2[v] = 2 * I;
+    J2[v] = 2 * J;
+    K2[v] = 2 * K;
+  }
+#pragma unroll
+  for (int ed = 0; ed < 6; ++ed) {
+    const int i = EV0(ed), j = EV1(ed);
+    I2[4 + ed] = (I2[i] + I2[j]) >> 1;
+    J2[4 + ed] = (J2[i] + J2[j]) >> 1;
+    K2[4 + ed] = (K2[i] + K2[j]) >> 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) e.g2[a] = l2[lloc(I2[a], J2[a], K2[a], m2)];
+  elem_vertices<double>(e.G, type, px, py, pz, n, e.xv);
+  const double* TI = L.tinv + ((size_t)mac * 6 + type) * 10;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e.gl[r][k] = TI[3 * r + k];
+  e.detF = TI[9];
+}
+
 // One thread per micro-tet of the finest level, global atomics, the 27-point
 // conical-product rule of the vector mass: the P2 mass integrand has degree
 // 4, which the 4-point rule of the Stokes blocks would make singular.  Per
@@ -1350,35 +1428,8 @@ __global__ __launch_bounds__(256) void k_temp(LevelDev L, VmassRule qr, TempCoef
   for (int a = 0; a < 10; ++a) acc[a] = 0.0;
   for (int q = 0; q < VMASS_NQ; ++q) {
     const double lam[4] = {qr.lam[q][0], qr.lam[q][1], qr.lam[q][2], qr.lam[q][3]};
-    double xq[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) xq[r] = lam[0] * xv[0][r] + lam[1] * xv[1][r] + lam[2] * xv[2][r] + lam[3] * xv[3][r];
-    QGeo<double, BLEND> geo;
-    geo.eval(G, xq, qr.w[q] * detF);
-    const double W = geo.W;
-    double gL[4][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gL[i + 1][k] = gl[i][k];
-      geo.JinvT(gL[i + 1]);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gL[0][k] = -(gL[1][k] + gL[2][k] + gL[3][k]);
-    double N[10], dN[10][3];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      N[v] = lam[v] * (2.0 * lam[v] - 1.0);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dN[v][k] = (4.0 * lam[v] - 1.0) * gL[v][k];
-    }
-#pragma unroll
-    for (int ed = 0; ed < 6; ++ed) {
-      const int i = EV0(ed), j = EV1(ed);
-      N[4 + ed] = 4.0 * lam[i] * lam[j];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dN[4 + ed][k] = 4.0 * (lam[i] * gL[j][k] + lam[j] * gL[i][k]);
-    }
+    double xq[3], W, gL[4][3], N[10], dN[10][3];
+    temp_point<BLEND>(G, xv, gl, lam, qr.w[q] * detF, xq, W, gL, N, dN);
     const double irho = exp(-(lam[0] * lr[0] + lam[1] * lr[1] + lam[2] * lr[2] + lam[3] * lr[3]));
     const double tk = tc.tau * tc.kap * irho;
     if (MODE == TM_DIAG) {
@@ -1448,6 +1499,106 @@ __global__ __launch_bounds__(256) void k_temp(LevelDev L, VmassRule qr, TempCoef
   }
 #pragma unroll
   for (int a = 0; a < 10; ++a) gadd(y + g2[a], acc[a]);
+}
+
+// Stored element matrices of S = s1 M + tau kap K_{1/rho} (the preconditioner's
+// operator), built once per solve: the 55 entries i <= j of each micro-tet's
+// symmetric 10 x 10 matrix.  Both kernels work on bricks of 4^3 lattice cubes
+// (one workgroup per (macro, brick), one wave per micro-tet type, one lane per
+// cube), so a micro-tet's slot is ((mac * ntiles + tile) * 6 + type) * 64 + lane
+// and the matrices are stored entry-major over these slots (entry e of slot s
+// at e * nslots + s): a wave reads each entry coalesced.  Slots of cubes
+// outside the macro are left unused.
+template <bool BLEND>
+__global__ __launch_bounds__(384) void k_temp_smat(LevelDev L, VmassRule qr, double s1, double tk,
+                                                   const double* __restrict__ lnrho, double* __restrict__ S) {
+  const int tile = blockIdx.x % L.ntiles;
+  const int mac = blockIdx.x / L.ntiles;
+  const int type = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = L.tiles[3 * tile] + (lane & 3), py = L.tiles[3 * tile + 1] + ((lane >> 2) & 3),
+            pz = L.tiles[3 * tile + 2] + (lane >> 4);
+  if (px + py + pz > type_limit(type, L.n)) return;
+  const size_t nslots = (size_t)L.nmacro * L.ntiles * 384;
+  const size_t slot = (size_t)blockIdx.x * 384 + threadIdx.x;
+  TempElem e;
+  temp_elem(L, mac, type | (px << 3) | (py << 13) | (pz << 23), e);
+  double lr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) lr[v] = lnrho ? lnrho[e.g1[v]] : 0.0;
+  double acc[TEMP_SMAT_ENTRIES];
+#pragma unroll
+  for (int k = 0; k < TEMP_SMAT_ENTRIES; ++k) acc[k] = 0.0;
+  for (int q = 0; q < VMASS_NQ; ++q) {
+    const double lam[4] = {qr.lam[q][0], qr.lam[q][1], qr.lam[q][2], qr.lam[q][3]};
+    double xq[3], W, gL[4][3], N[10], dN[10][3];
+    temp_point<BLEND>(e.G, e.xv, e.gl, lam, qr.w[q] * e.detF, xq, W, gL, N, dN);
+    const double wm = W * s1;
+    const double wk = W * tk * exp(-(lam[0] * lr[0] + lam[1] * lr[1] + lam[2] * lr[2] + lam[3] * lr[3]));
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 10; ++i)
+#pragma unroll
+      for (int j = i; j < 10; ++j, ++k)
+        acc[k] += wm * N[i] * N[j] + wk * (dN[i][0] * dN[j][0] + dN[i][1] * dN[j][1] + dN[i][2] * dN[j][2]);
+  }
+#pragma unroll
+  for (int k = 0; k < TEMP_SMAT_ENTRIES; ++k) S[(size_t)k * nslots + slot] = acc[k];
+}
+
+// y += S x with the stored element matrices (y zero-filled by the caller): the
+// brick's P2 values of x are staged in LDS, each lane adds its micro-tet's
+// product into an LDS box of the brick's nodes, and the box is written out
+// (plain stores for nodes inside both the brick and the macro, atomic adds
+// for the others).
+__global__ __launch_bounds__(384) void k_temp_sapply(LevelDev L, const double* __restrict__ S,
+                                                     const double* __restrict__ x, double* __restrict__ y) {
+  __shared__ double sx[NB2], sy[NB2];
+  const int tile = blockIdx.x % L.ntiles;
+  const int mac = blockIdx.x / L.ntiles;
+  const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
+  const int n = L.n, m2 = 2 * n;
+  const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int I = 2 * ox + i % B2, J = 2 * oy + (i / B2) % B2, K = 2 * oz + i / (B2 * B2);
+    sx[i] = (I + J + K <= m2) ? x[l2[lloc(I, J, K, m2)]] : 0.0;
+    sy[i] = 0.0;
+  }
+  __syncthreads();
+  const int type = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+  if (ox + cx + oy + cy + oz + cz <= type_limit(type, n)) {
+    const size_t nslots = (size_t)L.nmacro * L.ntiles * 384;
+    const size_t slot = (size_t)blockIdx.x * 384 + threadIdx.x;
+    ElemIdx e;
+    elem_indices(type, cx, cy, cz, e);
+    double xs[10], acc[10];
+#pragma unroll
+    for (int a = 0; a < 10; ++a) {
+      xs[a] = sx[e.n2i[a]];
+      acc[a] = 0.0;
+    }
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 10; ++i)
+#pragma unroll
+      for (int j = i; j < 10; ++j, ++k) {
+        const double sij = S[(size_t)k * nslots + slot];
+        acc[i] += sij * xs[j];
+        if (j != i) acc[j] += sij * xs[i];
+      }
+#pragma unroll
+    for (int a = 0; a < 10; ++a) ldsadd(sy + e.n2i[a], acc[a]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NB2; i += blockDim.x) {
+    const int lx = i % B2, ly = (i / B2) % B2, lz = i / (B2 * B2);
+    const int I = 2 * ox + lx, J = 2 * oy + ly, K = 2 * oz + lz;
+    if (I + J + K > m2) continue;
+    const size_t g = l2[lloc(I, J, K, m2)];
+    const bool excl = wmask(I, J, K, m2) == 15 && lx > 0 && lx < B2 - 1 && ly > 0 && ly < B2 - 1 && lz > 0 && lz < B2 - 1;
+    if (excl) y[g] = sy[i];
+    else gadd(y + g, sy[i]);
+  }
 }
 
 // ---- point location and the method of characteristics (Sec. 3) ------------------
@@ -3365,6 +3516,20 @@ void launch_temp(const LevelDev& L, const VmassRule& qr, const TempCoef& tc, int
     default: TEMP_LAUNCH(TM_RHS); break;
   }
 #undef TEMP_LAUNCH
+}
+
+size_t temp_smat_slots(const LevelDev& L) { return (size_t)L.nmacro * L.ntiles * 384; }
+
+void launch_temp_smat(const LevelDev& L, const VmassRule& qr, double s1, double tk, const double* lnrho, double* S,
+                      hipStream_t s) {
+  dim3 grid((unsigned)(L.nmacro * L.ntiles));
+  if (L.blend) hipLaunchKernelGGL((k_temp_smat<true>), grid, dim3(384), 0, s, L, qr, s1, tk, lnrho, S);
+  else hipLaunchKernelGGL((k_temp_smat<false>), grid, dim3(384), 0, s, L, qr, s1, tk, lnrho, S);
+}
+
+void launch_temp_sapply(const LevelDev& L, const double* S, const double* x, double* y, hipStream_t s) {
+  vfill<double>(y, 0.0, L.n2, s);
+  hipLaunchKernelGGL(k_temp_sapply, dim3((unsigned)(L.nmacro * L.ntiles)), dim3(384), 0, s, L, S, x, y);
 }
 
 void launch_mmoc(const LevelDev& L, const LocDev& loc, const double* F, const double* un, const double* uo, double tau,

@@ -249,6 +249,7 @@ struct stk_ctx {
     DBuf<double> minv;
     LocDev loc{};
     DBuf<double> w, fg;
+    DBuf<double> smat;     // stored element matrices of S (STK_TEMP_SYM_STORED, stored_S)
   } temp;
   DBuf<double> lnrho;
   DBuf<float> lnrhof;
@@ -1203,6 +1204,25 @@ void check_temp_params(const stk_temp_params* p) {
           "non-finite coefficient");
   REQUIRE(p->tol_abs >= 0 && p->tol_cg > 0 && p->tol_cg < 1, "bad tolerances");
   REQUIRE(p->restart >= 1 && p->max_outer >= 1 && p->max_cg >= 1, "restart, max_outer and max_cg must be >= 1");
+  REQUIRE(p->stored_S == 0 || p->stored_S == 1, "stored_S must be 0 or 1");
+}
+
+// Builds the stored element matrices of S for these coefficients when asked
+// for and when their memory (55 doubles per brick slot, about 1.9 slots per
+// micro-tet) is free with 2 GiB to spare; returns whether they are in place.
+bool temp_build_smat(Ctx& c, const TempCoef& tc, const double* lnrho, bool want) {
+  LevelData& L = c.at(c.L());
+  const size_t cnt = (size_t)TEMP_SMAT_ENTRIES * temp_smat_slots(L.d);
+  if (!want) return false;
+  if (c.temp.smat.n != cnt) {
+    c.temp.smat.release();
+    size_t fr = 0, total = 0;
+    HIPCHK(hipMemGetInfo(&fr, &total));
+    if (cnt * sizeof(double) + ((size_t)2 << 30) > fr) return false;
+    c.temp.smat.alloc(cnt);
+  }
+  launch_temp_smat(L.d, c.vrule, tc.s1, tc.tau * tc.kap, lnrho, c.temp.smat.p, c.s);
+  return true;
 }
 
 // temperature work vectors of the finest level (n2 each)
@@ -1312,6 +1332,8 @@ void temp_solve(Ctx& c, const stk_temp_params& p, const double* ustar, const dou
   double* tmp = twork(c, T_TMP);
   temp_apply(c, tc, TM_DIAG, nullptr, nullptr, lnrho, tmp);
   vinvert<double>(tmp, dinv, N, c.s);
+  const bool stored = temp_build_smat(c, tc, lnrho, p.stored_S == 1);
+  LevelData& LF = c.at(c.L());
   if (T_init) vcopy<double>(T_init, T, N, c.s);
   else vfill<double>(T, 0.0, N, c.s);
   launch_scalar_dirichlet(c.temp.bnode.p, c.temp.bkind.p, c.temp.nb, T, 1, p.T_in, p.T_out, c.s);
@@ -1327,7 +1349,8 @@ void temp_solve(Ctx& c, const stk_temp_params& p, const double* ustar, const dou
   auto prec = [&](const double* v, double* z) {
     cg_total += dev_pcg<double>(
         c, N, [&](const double* pp, double* q) {
-          temp_apply(c, tc, TM_SYM, pp, nullptr, lnrho, q);
+          if (stored) launch_temp_sapply(LF.d, c.temp.smat.p, pp, q, c.s);
+          else temp_apply(c, tc, TM_SYM, pp, nullptr, lnrho, q);
           temp_zero_bc(c, q);
         },
         [&](double* w) { temp_zero_bc(c, w); }, dinv, v, z, twork(c, T_CR), twork(c, T_CZ), twork(c, T_CP),
@@ -1342,6 +1365,7 @@ void temp_solve(Ctx& c, const stk_temp_params& p, const double* ustar, const dou
     rep->converged = fo.converged ? 1 : 0;
     rep->initial_residual = fo.r0;
     rep->abs_residual = fo.rfin;
+    rep->stored_S = stored ? 1 : 0;
   }
   if (!fo.converged) throw StkError(STK_ENOCONV, "temperature FGMRES reached max_outer before tol_abs");
 }
@@ -2458,6 +2482,7 @@ void stk_temp_default_params(stk_temp_params* p) {
   p->restart = 30;
   p->max_outer = 300;
   p->max_cg = 5000;
+  p->stored_S = 1;
 }
 
 int stk_temp_apply(stk_ctx* ctx, const stk_temp_params* p, int mode, const double* u_star, const double* lnrho,
@@ -2465,10 +2490,18 @@ int stk_temp_apply(stk_ctx* ctx, const stk_temp_params* p, int mode, const doubl
   return guard([&] {
     REQUIRE(ctx && ctx->lv.size() > 0, "null context");
     check_temp_params(p);
-    REQUIRE(mode == STK_TEMP_APPLY || mode == STK_TEMP_SYM || mode == STK_TEMP_DIAG, "unknown mode");
+    REQUIRE(mode == STK_TEMP_APPLY || mode == STK_TEMP_SYM || mode == STK_TEMP_DIAG || mode == STK_TEMP_SYM_STORED,
+            "unknown mode");
     REQUIRE(y && (x || mode == STK_TEMP_DIAG), "null vector");
-    const int m = mode == STK_TEMP_APPLY ? TM_APPLY : (mode == STK_TEMP_SYM ? TM_SYM : TM_DIAG);
-    temp_apply(*ctx, temp_coef(*p), m, x, mode == STK_TEMP_APPLY ? u_star : nullptr, lnrho, y);
+    REQUIRE(x != y, "x and y must be distinct buffers");
+    const TempCoef tc = temp_coef(*p);
+    if (mode == STK_TEMP_SYM_STORED) {
+      REQUIRE(temp_build_smat(*ctx, tc, lnrho, true), "not enough free device memory for the stored matrices");
+      launch_temp_sapply(ctx->at(ctx->L()).d, ctx->temp.smat.p, x, y, ctx->s);
+    } else {
+      const int m = mode == STK_TEMP_APPLY ? TM_APPLY : (mode == STK_TEMP_SYM ? TM_SYM : TM_DIAG);
+      temp_apply(*ctx, tc, m, x, mode == STK_TEMP_APPLY ? u_star : nullptr, lnrho, y);
+    }
     HIPCHK(hipGetLastError());
   });
 }

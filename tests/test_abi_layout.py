@@ -14,7 +14,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-STRUCTS = {"stk_mesh_desc": "MeshDesc", "stk_solver_params": "SolverParams", "stk_report": "Report"}
+STRUCTS = {"stk_mesh_desc": "MeshDesc", "stk_solver_params": "SolverParams", "stk_report": "Report",
+           "stk_temp_params": "TempParams", "stk_temp_report": "TempReport"}
 
 
 def _c_layout(tmp_path):

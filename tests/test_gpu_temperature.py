@@ -55,11 +55,13 @@ def test_temperature_operators_match_oracle(shell, adv):
     y = P.s2_to_or(P.ctx.temp_apply(P.s2_to_lib(x), prm, 0, u_star=ul, lnrho=lr))
     ys = P.s2_to_or(P.ctx.temp_apply(P.s2_to_lib(x), prm, 1, lnrho=lr))
     yd = P.s2_to_or(P.ctx.temp_apply(P.s2_to_lib(x), prm, 2, lnrho=lr))
+    yst = P.s2_to_or(P.ctx.temp_apply(P.s2_to_lib(x), prm, 3, lnrho=lr))   # stored element matrices
     eL = rowerr(y, Lo @ x, abs(Lo) @ np.abs(x))
     eS = rowerr(ys, So @ x, abs(So) @ np.abs(x))
     eD = rowerr(yd, So.diagonal(), np.abs(So.diagonal()))
-    print(f"adv {adv}: L {eL:.2e}  S {eS:.2e}  diag {eD:.2e}")
-    assert eL < 1e-12 and eS < 1e-12 and eD < 1e-13
+    eSt = rowerr(yst, So @ x, abs(So) @ np.abs(x))
+    print(f"adv {adv}: L {eL:.2e}  S {eS:.2e}  diag {eD:.2e}  stored S {eSt:.2e}")
+    assert eL < 1e-12 and eS < 1e-12 and eD < 1e-13 and eSt < 1e-12
 
 
 def test_temperature_rhs_matches_oracle(shell):
@@ -124,11 +126,11 @@ def test_mmoc_on_the_cube_matches_oracle_and_is_exact_for_constant_velocity():
     P.ctx.close()
 
 
-@pytest.mark.parametrize("adv", [0.0, 1.0])
-def test_temperature_solve_matches_oracle(shell, adv):
+@pytest.mark.parametrize("adv,stored", [(0.0, 1), (1.0, 1), (1.0, 0)])
+def test_temperature_solve_matches_oracle(shell, adv, stored):
     d = shell
     P, m = d["P"], d["m"]
-    prm = _params(adv, T_in=1.0, T_out=0.1, tol_abs=1e-15)
+    prm = _params(adv, T_in=1.0, T_out=0.1, tol_abs=1e-15, stored_S=stored)
     Tn = d["T2"]
     Lo, bo = temperature_system(m, d["u"], d["lnrho"], d["eta"], Tn, Tn, TAU1, TAU0, adv=adv, **COEF)
     To = solve_dirichlet(Lo, bo, m.flag2 > 0, np.where(m.flag2 == 2, 0.1, 1.0))
@@ -138,7 +140,7 @@ def test_temperature_solve_matches_oracle(shell, adv):
     e = np.abs(T - To).max() / np.abs(To).max()
     print(f"adv {adv}: {rep['iterations']} FGMRES its, {rep['cg_its']} CG its, residual {rep['abs_residual']:.2e}, "
           f"max rel diff {e:.2e}")
-    assert rep["converged"] == 1 and e < 1e-9
+    assert rep["converged"] == 1 and e < 1e-9 and rep["stored_S"] == stored
     assert np.array_equal(T[m.flag2 == 1], np.ones((m.flag2 == 1).sum()))
     assert np.array_equal(T[m.flag2 == 2], np.full((m.flag2 == 2).sum(), 0.1))
 
