@@ -181,3 +181,55 @@ def test_temperature_errors_and_no_convergence(shell):
     T, rep = P.ctx.temp_solve(b, prm, u_star=u, allow_noconv=True)
     assert rep["converged"] == 0 and rep["iterations"] == 2
     assert torch.isfinite(T).all()
+
+
+def test_two_coupled_steps_match_oracle(shell):
+    """Two steps of the Gauss-Seidel-like alternation (Sec. 3): the Stokes
+    solve with the buoyancy of T^n (no-slip inner, free-slip outer,
+    compressible; buoyancy scaled by 500 so that the velocity is of order
+    one), then the temperature step from T^n, T^{n-1}, u^n, u^{n-1} with a
+    step of about a third of a micro-tet's height over max |u|; the library
+    (FGMRES to 1e-11, the step's FGMRES to an absolute 1e-14) against the
+    oracle's direct solves, starting from T^{-1} = T^0, u^{-1} = u^0.  Bars:
+    the velocity within the solve's condition x residual (1e-6), T^{n+1}
+    within 1e-7."""
+    from oracle.fem import assemble_A, assemble_B, rhs_buoyancy
+    from oracle.system import solve_stokes
+    from paper_2506_04157_amd import default_params
+    d = shell
+    P, m = d["P"], d["m"]
+    eta, lnrho = d["eta"], d["lnrho"]
+    A = assemble_A(m, eta)
+    B = assemble_B(m)
+    Bb = B + assemble_B(m, lnrho, only_C=True)
+    _, Q = P.projector()
+    sp_ = default_params(tol_rel=1e-11, precision=64)
+    P.ctx.set_fields(P.p_to_lib(eta), P.p_to_lib(lnrho), params=sp_)
+    T_o = [d["T2"].copy(), d["T2"].copy()]          # T^{n-1}, T^n
+    T_g = [P.s2_to_lib(d["T2"]), P.s2_to_lib(d["T2"])]
+    u_o, u_g = [], []
+    tau = None
+    for step in range(2):
+        f = rhs_buoyancy(m, T_o[-1], scale=500.0)
+        uo, _, _ = solve_stokes(A, Bb, f, np.zeros(m.n1), Q, Bt=B.T)
+        ug, _, rep = P.ctx.solve(P.ctx.rhs_buoyancy(T_g[-1], scale=500.0), params=sp_)
+        assert rep["rel_residual"] <= 1e-11
+        e_u = relerr(P.u_to_or(ug), uo)
+        u_o.append(uo)
+        u_g.append(ug)
+        if tau is None:
+            tau = 0.3 * 0.45 / 8 / np.abs(uo).max()     # a third of a micro-tet height per step
+        prm = temp_params(tau1=tau, tau0=tau, adv=0.0, T_in=1.0, T_out=0.0, tol_abs=1e-14, **COEF)
+        un_o, unm1_o = u_o[-1], u_o[-2] if step > 0 else u_o[-1]
+        un_g, unm1_g = u_g[-1], u_g[-2] if step > 0 else u_g[-1]
+        Tn1_o, _, _, _ = temperature_step(m, T_o[-1], T_o[-2], un_o, unm1_o, lnrho, eta, tau, tau, T_in=1.0,
+                                          T_out=0.0, **COEF)
+        Tn1_g, rep_t = P.ctx.temperature_step(T_g[-1], T_g[-2], un_g, unm1_g, P.p_to_lib(eta), prm,
+                                              lnrho=P.p_to_lib(lnrho))
+        e_T = np.abs(P.s2_to_or(Tn1_g) - Tn1_o).max() / np.abs(Tn1_o).max()
+        moved = np.abs(Tn1_o - T_o[-1]).max()
+        print(f"step {step}: u {e_u:.2e} (max|u| {np.abs(uo).max():.2e}, tau {tau:.2e}), T {e_T:.2e}, "
+              f"T changed by {moved:.2e}, {rep_t['iterations']} its")
+        assert e_u < 1e-6 and e_T < 1e-7 and moved > 1e-4
+        T_o.append(Tn1_o)
+        T_g.append(Tn1_g)
