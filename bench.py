@@ -393,8 +393,8 @@ def main():
                          "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not "
-              "part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU "
+              "path", file=sys.stderr)
         sys.exit(2)
     if (args.apply_only or args.transfer_only or args.l_eta_study or args.contrast_study or args.large_apply
             or args.schur_study or args.temp_study):
