@@ -161,6 +161,24 @@ def cpu_baseline(nt=10, nr=2, level=1, solve_nt=3, solve_nr=1, solve_level=1):
             ts.append(time.perf_counter() - s)
         t_spmv = float(np.median(ts))
         nu = A.shape[0]
+    # the same product on all host cores (the oracle's OpenMP CSR product)
+    omp = None
+    try:
+        from oracle import cspmv
+        if not os.path.exists(cspmv.LIB):
+            cspmv.build()
+        yo = cspmv.spmv(A, x)
+        tso = []
+        for _ in range(20):
+            s = time.perf_counter()
+            cspmv.spmv(A, x, yo)
+            tso.append(time.perf_counter() - s)
+        t_omp = float(np.median(tso))
+        omp = {"threads": cspmv.threads(), "ms": t_omp * 1e3, "gdof_s": nu / t_omp / 1e9,
+               "max_rel_diff_vs_scipy": float(np.abs(yo - y).max() / np.abs(y).max())}
+    except Exception as exc:   # a missing gcc/OpenMP only loses this secondary figure
+        omp = {"error": str(exc)[:200]}
+    with threadpool_limits(1):
         del A, y
         # secondary: the direct-solve pipeline on a small shell
         t1 = time.perf_counter()
@@ -184,6 +202,7 @@ def cpu_baseline(nt=10, nr=2, level=1, solve_nt=3, solve_nr=1, solve_level=1):
                        f"{nt}x{nr} shell ({60 * nt * nt * nr} macro-tets) at level {level}: N_u={nu}; "
                        f"{t_spmv * 1e3:.1f} ms per SpMV; mesh + assembly {t_asm:.1f} s"),
             "spmv_ms": t_spmv * 1e3, "assembly_s": t_asm,
+            "openmp_spmv_all_host_cores": omp,
             "direct_solve_pipeline": {
                 "sample": (f"{solve_nt}x{solve_nr} shell level {solve_level} (N_u={3 * ms.n2}, N_p={ms.n1}): "
                            "mesh, assembly, constrained direct forward and adjoint solves, gradient, FP64, 1 thread"),
@@ -527,7 +546,7 @@ def run_bench(args, line, fits, n_tets):
             cpu = cpu_baseline()
             line["cpu_baseline"] = {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")}
             line["cpu_baseline_detail"] = {k: cpu[k] for k in ("spmv_ms", "assembly_s", "direct_solve_pipeline",
-                                                               "host")}
+                                                               "openmp_spmv_all_host_cores", "host")}
             log(f"oracle: {cpu['sample']}")
 
         if args.no_solves:

@@ -1,4 +1,5 @@
 """Pins of the oracle's element integrals and assembled operators (CPU only)."""
+import os
 from math import factorial
 
 import numpy as np
@@ -411,3 +412,16 @@ def test_dirichlet_element_scale_marks_the_elements_touching_the_dirichlet_spher
     touch = (np.abs(r - 0.55) < 1e-12).any(axis=1)
     assert np.array_equal(s == 100.0, touch) and np.all(s[~touch] == 1.0) and touch.any() and (~touch).any()
     assert np.all(dirichlet_element_scale(m, {1}, 1.0) == 1.0)
+
+
+def test_multicore_spmv_equals_scipy():
+    """The oracle's OpenMP CSR product (host timing) sums each row in storage
+    order, as scipy does: equal to A @ x up to rounding on an assembled A."""
+    from oracle import cspmv
+    if not os.path.exists(cspmv.LIB):
+        cspmv.build()
+    m = RefinedMesh(shell_macros(1, 1, 0.55, 1.0), 1)
+    A = assemble_A(m, np.exp(np.linspace(-1.0, 1.0, m.n1)))
+    x = np.random.default_rng(7).standard_normal(A.shape[0])
+    ref = A @ x
+    assert np.abs(cspmv.spmv(A, x) - ref).max() <= 1e-14 * np.abs(ref).max()
