@@ -236,3 +236,59 @@ def test_mmoc_rigid_rotation_at_full_size(full):
     moved = (F - lin(Xd)).abs().max().item()
     print(f"rotation: max error {err:.2e}, displacement effect {moved:.2e}")
     assert err < 2e-5 and moved > 1e-2
+
+
+@pytest.mark.parametrize("mac_id", [0, 11999])
+def test_sampled_rows_of_the_temperature_operators_at_full_size(full, mac_id):
+    """The temperature step's operators at full size (66.6 million P2 nodes,
+    the launch shape of the temperature study): the rows of L (advection in
+    the system), of S (matrix-free and through the stored element matrices)
+    and of the right-hand side at the nodes inside one macro-tet depend only
+    on that macro's micro-tets, so the oracle's one-macro assembly
+    reproduces them; smooth inputs evaluated by each side at its own nodes,
+    errors per entry against the entry's scale."""
+    from oracle.temperature import symmetric_part, temperature_system
+    from paper_2506_04157_amd import temp_params
+    sc, X2, X1 = full
+    m = _one_macro(mac_id)
+    in2 = (m.keys2[:, 4:] > 0).all(axis=1)
+    g2 = _block_match(X2, int(in2.sum()), m.X2[in2])
+    coef = dict(k=0.8, Pe=3.0, Cp=1.1, Di=0.4, alpha=1.3, H=0.7, Ra=30.0)
+    tau1, tau0 = 0.02, 0.026
+    f = lambda X: np.sin(2.0 * X[:, 0]) + X[:, 1] * X[:, 2]
+    h = lambda X: np.cos(X[:, 0] + 2.0 * X[:, 2]) - 0.5 * X[:, 1]
+    u_or = inputs.smooth_vector_field(7, m.X2).T.ravel()
+    lnrho_or = inputs.ln_density(m.X1)
+    eta_or = _eta(m.X1)
+    Lo, bo = temperature_system(m, u_or, lnrho_or, eta_or, f(m.X2), h(m.X2), tau1, tau0, adv=1.0, **coef)
+    So = symmetric_part(m, lnrho_or, tau1, tau0, k=coef["k"], Pe=coef["Pe"], Cp=coef["Cp"])
+    x_or = f(m.X2)
+    dev = "cuda"
+    Xt = torch.tensor(X2, device=dev)
+    X1t = torch.tensor(X1, device=dev)
+    ft = lambda X: (torch.sin(2.0 * X[:, 0]) + X[:, 1] * X[:, 2]).contiguous()
+    ht = lambda X: (torch.cos(X[:, 0] + 2.0 * X[:, 2]) - 0.5 * X[:, 1]).contiguous()
+    u = torch.tensor(inputs.smooth_vector_field(7, X2).T.ravel(), device=dev)
+    lnrho = torch.tensor(inputs.ln_density(X1), device=dev)
+    eta = torch.tensor(_eta(X1), device=dev)
+    prm = temp_params(tau1=tau1, tau0=tau0, adv=1.0, **coef)
+    x = ft(Xt)
+    checks = [("L", sc.temp_apply(x, prm, 0, u_star=u, lnrho=lnrho), Lo @ x_or, abs(Lo) @ np.abs(x_or)),
+              ("S", sc.temp_apply(x, prm, 1, lnrho=lnrho), So @ x_or, abs(So) @ np.abs(x_or)),
+              ("S stored", sc.temp_apply(x, prm, 3, lnrho=lnrho), So @ x_or, abs(So) @ np.abs(x_or))]
+    for name, y, ref, scale in checks:
+        err = np.abs(y.cpu().numpy()[g2] - ref[in2]) / scale[in2]
+        print(mac_id, name, err.max())
+        assert err.max() <= 1e-12, (mac_id, name)
+    b = sc.temp_rhs(ft(Xt), ht(Xt), prm, u_star=u, lnrho=lnrho, eta=eta).cpu().numpy()[g2]
+    z = np.zeros(m.n2)
+    _, src = temperature_system(m, u_or, lnrho_or, eta_or, z, z, tau1, tau0, **coef)
+    from oracle.fem import assemble_vector_mass
+    from oracle.temperature import bdf2
+    _, s0, sm = bdf2(tau1, tau0)
+    Ma = abs(assemble_vector_mass(m, np.ones(m.n1))[:m.n2, :m.n2])
+    scale = Ma @ (s0 * np.abs(f(m.X2)) + sm * np.abs(h(m.X2)) + np.max(np.abs(src) / (Ma @ np.ones(m.n2))))
+    err = np.abs(b - bo[in2]) / scale[in2]
+    print(mac_id, "rhs", err.max())
+    assert err.max() <= 1e-12
+    del Xt, X1t
