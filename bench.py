@@ -18,12 +18,13 @@ After the timed steps, each once, within a wall-clock budget (STK_BENCH_BUDGET_S
 default 420 s from the start; legs that would not fit are listed as skipped):
   the FP32 A-apply (events, 20 applies);
   the CPU oracle: scipy FP64 SpMV of the assembled A on the 10x2 shell at
-    level 1 (1 core, median of 20), and the oracle's direct solve pipeline on
-    a 3x1 level-1 shell;
+    level 1 (1 core, median of 20; the same product on all host cores beside
+    it), and the oracle's direct solve pipeline on a 3x1 level-1 shell;
   the mixed-precision forward solve to 1e-8 (FP32 multigrid / Schur inner
     solves inside FP64 FGMRES) and the all-FP64 forward solve, with times,
     iterations, residuals and their difference;
-  the mixed adjoint solve (J = |u|^2 / 2) and the gradient kernel.
+  the mixed adjoint solve (J = |u|^2 / 2) and the gradient kernel;
+  two temperature steps of the splitting scheme driven by the solved velocity.
 The JSON line is printed once at the end, also when a leg fails or the
 process receives SIGTERM.
 """
@@ -588,6 +589,33 @@ def run_bench(args, line, fits, n_tets):
             solves["adjoint"]["gradient_finite"] = bool(torch.isfinite(gm).all().item()
                                                         and torch.isfinite(gT).all().item())
             log(f"adjoint {ra['seconds']:.2f}s ({ra['iterations']} its)")
+        if u is not None and fits("temperature_step", 30):
+            # the splitting's temperature step driven by the solved velocity
+            # (Sec. 3): two steps from T^n = T^{n-1} = T, u^n = u^{n-1} = u, with
+            # the paper's Ra, Pe, Di and a step of a third of a micro-tet's
+            # radial height over max |u|; the second is reported
+            from paper_2506_04157_amd import temp_params
+            umax = float(u.abs().max().item())
+            tau = (1.0 / 3.0) * (0.45 / args.n_rad / 2 ** args.level) / max(umax, 1e-30)
+            prm = temp_params(tau1=tau, tau0=tau, k=1.0, Pe=2.822e4, Cp=1.0, Di=0.4538, alpha=1.0, H=1.0,
+                              Ra=1.692e7, T_in=4200.0 / 3900.0, T_out=300.0 / 3900.0, tol_abs=1e-10)
+            eta1 = torch.exp(mlog).contiguous()
+            T_prev, T_cur = T2, T2
+            reps = []
+            for _ in range(2):
+                T_new, rt = sc.temperature_step(T_cur, T_prev, u, u, eta1, prm, lnrho=lnrho)
+                torch.cuda.synchronize()
+                reps.append(rt)
+                T_prev, T_cur = T_cur, T_new
+            rt = reps[-1]
+            line["temperature_step"] = {
+                "workload": f"P2 temperature nodes {Nu // 3}, the velocity of the mixed forward solve, tau {tau:.3e}",
+                "ms_mmoc": rt["ms_mmoc"], "ms_rhs": rt["ms_rhs"], "ms_solve": rt["ms_solve"],
+                "fgmres_iterations": rt["iterations"], "cg_iterations": rt["cg_its"],
+                "abs_residual": rt["abs_residual"], "stored_S": rt["stored_S"],
+                "T_finite": bool(torch.isfinite(T_cur).all().item())}
+            log(f"temperature step: mmoc {rt['ms_mmoc']:.1f} ms, rhs {rt['ms_rhs']:.1f} ms, solve "
+                f"{rt['ms_solve']:.1f} ms ({rt['iterations']} FGMRES its, {rt['cg_its']} CG its)")
 
 
 def _rep(rep):
