@@ -396,6 +396,25 @@ int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T
                          const double* u_n, const double* u_nm1, const double* lnrho, const double* eta,
                          double* T_np1, double* That_n, double* That_nm1, stk_temp_report* rep);
 
+/* One step of the coupled scheme (Sec. 3: the temperature first, then the
+ * Stokes problem of eq. StokesSub at the new temperature), on a shell:
+ *  1. T* = T^n + (T^n - T^{n-1}) tau^{n+1}/tau^n (eq. Extrapolation) and the
+ *     viscosity eta(x, T*) of the model of eq. ViscosityDef (arguments as in
+ *     stk_set_temperature_viscosity), used in the shear heating;
+ *  2. T^{n+1} as stk_temperature_step does it (tp);
+ *  3. the Stokes fields set to eta(x, T^{n+1}) and ln rho, and u^{n+1},
+ *     p^{n+1} from stk_solve (sp) with f = buoyancy_scale * int T^{n+1} r_hat
+ *     . phi (stk_rhs_buoyancy), g = 0 and no Dirichlet data.
+ * Device vectors: T_n, T_nm1, T_np1 (n_p2), u_n, u_nm1, u_np1 (3 n_p2),
+ * p_np1 and lnrho (n_p1, lnrho nullable).  The context's fields are left at
+ * eta(x, T^{n+1}).  Returns the temperature solve's STK_ENOCONV without
+ * solving the Stokes problem, else the Stokes solve's code; trep, srep
+ * (nullable) receive both reports. */
+int stk_coupled_step(stk_ctx* ctx, const stk_solver_params* sp, const stk_temp_params* tp, const double* eta_base,
+                     int n_base, double E_A, double V_A, int l_eta, double buoyancy_scale, const double* lnrho,
+                     const double* T_n, const double* T_nm1, const double* u_n, const double* u_nm1, double* T_np1,
+                     double* u_np1, double* p_np1, stk_temp_report* trep, stk_report* srep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -111,6 +111,8 @@ SIGNATURES = {
     "stk_temp_solve": [_CTX, ctypes.POINTER(TempParams), _P, _P, _P, _P, _P, ctypes.POINTER(TempReport)],
     "stk_temperature_step": [_CTX, ctypes.POINTER(TempParams), _P, _P, _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(TempReport)],
+    "stk_coupled_step": [_CTX, ctypes.POINTER(SolverParams), ctypes.POINTER(TempParams), _P, _I, _D, _D, _I, _D,
+                         _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(TempReport), ctypes.POINTER(Report)],
 }
 
 _lib = None

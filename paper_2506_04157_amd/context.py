@@ -399,3 +399,24 @@ class StokesContext:
         if not (allow_noconv and rc == _lib.STK_ENOCONV):
             check(rc)
         return (T, thn, thm, rep.as_dict()) if traced else (T, rep.as_dict())
+
+    def coupled_step(self, T_n, T_nm1, u_n, u_nm1, eta_base, tparams, params=None, E_A=4.610, V_A=2.996,
+                     l_eta=-1, buoyancy_scale=1.0, lnrho=None, allow_noconv=False):
+        """One step of the coupled scheme (temperature, then Stokes at the new
+        temperature): (T^{n+1}, u^{n+1}, p^{n+1}, temperature report, Stokes report)."""
+        params = params or self.params or default_params()
+        base = np.ascontiguousarray(eta_base, dtype=np.float64)
+        T = torch.empty_like(T_n)
+        u, p = self.zeros_u(), self.zeros_p()
+        trep, srep = TempReport(), Report()
+        rc = self.lib.stk_coupled_step(
+            self.h, ctypes.byref(params), ctypes.byref(tparams), base.ctypes.data_as(ctypes.c_void_p), len(base),
+            float(E_A), float(V_A), int(l_eta), float(buoyancy_scale), self._s1(lnrho, "lnrho"),
+            self._s2(T_n, name="T_n"), self._s2(T_nm1, name="T_nm1"), self._u(u_n, name="u_n"),
+            self._u(u_nm1, name="u_nm1"), self._s2(T, name="T_np1"), self._u(u, name="u_np1"),
+            self._p(p, name="p_np1"), ctypes.byref(trep), ctypes.byref(srep))
+        if not (allow_noconv and rc == _lib.STK_ENOCONV):
+            check(rc)
+        self.params = params
+        self.generation += 1
+        return T, u, p, trep.as_dict(), srep.as_dict()

@@ -250,6 +250,7 @@ struct stk_ctx {
     LocDev loc{};
     DBuf<double> w, fg;
     DBuf<double> smat;     // stored element matrices of S (STK_TEMP_SYM_STORED, stored_S)
+    DBuf<double> tstar, fbuf;   // stk_coupled_step: extrapolated temperature, buoyancy
   } temp;
   DBuf<double> lnrho;
   DBuf<float> lnrhof;
@@ -1372,6 +1373,54 @@ void temp_solve(Ctx& c, const stk_temp_params& p, const double* ustar, const dou
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void temperature_step_internal(Ctx& c, const stk_temp_params* p, const double* T_n, const double* T_nm1,
+                               const double* u_n, const double* u_nm1, const double* lnrho, const double* eta,
+                               double* T_np1, double* That_n, double* That_nm1, stk_temp_report* rep) {
+  check_temp_params(p);
+  REQUIRE(T_n && T_nm1 && u_n && u_nm1 && eta && T_np1, "null vector");
+  REQUIRE(T_np1 != T_n && T_np1 != T_nm1, "T_np1 must not alias T_n or T_nm1");
+  for (const double* o : {That_n, That_nm1})
+    REQUIRE(!o || (o != T_n && o != T_nm1 && o != T_np1), "traced outputs must not alias the temperatures");
+  REQUIRE(!That_n || That_n != That_nm1, "That_n and That_nm1 must be distinct");
+  setup_temp(c);
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  const long long n2 = n2of(c, c.L());
+  LevelData& L = c.at(c.L());
+  double* us = twork(c, T_US);
+  double* thn = That_n ? That_n : twork(c, T_M1);
+  double* thm = That_nm1 ? That_nm1 : twork(c, T_M2);
+  double* mid = twork(c, T_M3);
+  double* b = twork(c, T_B);
+  auto t0 = std::chrono::steady_clock::now();
+  const double q = p->tau1 / p->tau0;
+  vcopy<double>(u_n, us, 3 * n2, c.s);
+  vaxpby<double>(-q, u_nm1, 1.0 + q, us, 3 * n2, c.s);
+  launch_mmoc(L.d, c.temp.loc, T_n, us, u_n, p->tau1, thn, c.s);
+  launch_mmoc(L.d, c.temp.loc, T_nm1, u_n, u_nm1, p->tau0, mid, c.s);
+  launch_mmoc(L.d, c.temp.loc, mid, us, u_n, p->tau1, thm, c.s);
+  HIPCHK(hipStreamSynchronize(c.s));
+  const double ms_mmoc = ms_since(t0);
+  t0 = std::chrono::steady_clock::now();
+  launch_temp(L.d, c.vrule, temp_coef(*p), TM_RHS, nullptr, us, lnrho, eta, thn, thm, b, c.s);
+  HIPCHK(hipStreamSynchronize(c.s));
+  const double ms_rhs = ms_since(t0);
+  t0 = std::chrono::steady_clock::now();
+  stk_temp_report local{};
+  try {
+    temp_solve(c, *p, us, lnrho, b, T_n, T_np1, &local);
+  } catch (...) {
+    local.ms_mmoc = ms_mmoc;
+    local.ms_rhs = ms_rhs;
+    local.ms_solve = ms_since(t0);
+    if (rep) *rep = local;
+    throw;
+  }
+  local.ms_mmoc = ms_mmoc;
+  local.ms_rhs = ms_rhs;
+  local.ms_solve = ms_since(t0);
+  if (rep) *rep = local;
 }
 
 // ---- setup --------------------------------------------------------------------------
@@ -2550,51 +2599,40 @@ int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T
                          double* T_np1, double* That_n, double* That_nm1, stk_temp_report* rep) {
   return guard([&] {
     REQUIRE(ctx && ctx->lv.size() > 0, "null context");
-    check_temp_params(p);
-    REQUIRE(T_n && T_nm1 && u_n && u_nm1 && eta && T_np1, "null vector");
-    REQUIRE(T_np1 != T_n && T_np1 != T_nm1, "T_np1 must not alias T_n or T_nm1");
-    for (const double* o : {That_n, That_nm1})
-      REQUIRE(!o || (o != T_n && o != T_nm1 && o != T_np1), "traced outputs must not alias the temperatures");
-    REQUIRE(!That_n || That_n != That_nm1, "That_n and That_nm1 must be distinct");
-    Ctx& c = *ctx;
-    setup_temp(c);
-    if (rep) std::memset(rep, 0, sizeof(*rep));
-    const long long n2 = n2of(c, c.L());
-    LevelData& L = c.at(c.L());
-    double* us = twork(c, T_US);
-    double* thn = That_n ? That_n : twork(c, T_M1);
-    double* thm = That_nm1 ? That_nm1 : twork(c, T_M2);
-    double* mid = twork(c, T_M3);
-    double* b = twork(c, T_B);
-    auto t0 = std::chrono::steady_clock::now();
-    const double q = p->tau1 / p->tau0;
-    vcopy<double>(u_n, us, 3 * n2, c.s);
-    vaxpby<double>(-q, u_nm1, 1.0 + q, us, 3 * n2, c.s);
-    launch_mmoc(L.d, c.temp.loc, T_n, us, u_n, p->tau1, thn, c.s);
-    launch_mmoc(L.d, c.temp.loc, T_nm1, u_n, u_nm1, p->tau0, mid, c.s);
-    launch_mmoc(L.d, c.temp.loc, mid, us, u_n, p->tau1, thm, c.s);
-    HIPCHK(hipStreamSynchronize(c.s));
-    const double ms_mmoc = ms_since(t0);
-    t0 = std::chrono::steady_clock::now();
-    launch_temp(L.d, c.vrule, temp_coef(*p), TM_RHS, nullptr, us, lnrho, eta, thn, thm, b, c.s);
-    HIPCHK(hipStreamSynchronize(c.s));
-    const double ms_rhs = ms_since(t0);
-    t0 = std::chrono::steady_clock::now();
-    stk_temp_report local{};
-    try {
-      temp_solve(c, *p, us, lnrho, b, T_n, T_np1, &local);
-    } catch (...) {
-      local.ms_mmoc = ms_mmoc;
-      local.ms_rhs = ms_rhs;
-      local.ms_solve = ms_since(t0);
-      if (rep) *rep = local;
-      throw;
-    }
-    local.ms_mmoc = ms_mmoc;
-    local.ms_rhs = ms_rhs;
-    local.ms_solve = ms_since(t0);
-    if (rep) *rep = local;
+    temperature_step_internal(*ctx, p, T_n, T_nm1, u_n, u_nm1, lnrho, eta, T_np1, That_n, That_nm1, rep);
   });
+}
+
+int stk_coupled_step(stk_ctx* ctx, const stk_solver_params* sp, const stk_temp_params* tp, const double* eta_base,
+                     int n_base, double E_A, double V_A, int l_eta, double buoyancy_scale, const double* lnrho,
+                     const double* T_n, const double* T_nm1, const double* u_n, const double* u_nm1, double* T_np1,
+                     double* u_np1, double* p_np1, stk_temp_report* trep, stk_report* srep) {
+  const int rc = guard([&] {
+    REQUIRE(ctx && ctx->lv.size() > 0, "null context");
+    REQUIRE(sp && eta_base && u_np1 && p_np1, "null argument");
+    REQUIRE(std::isfinite(buoyancy_scale), "buoyancy_scale must be finite");
+    check_temp_params(tp);
+    REQUIRE(T_n && T_nm1, "null vector");
+    Ctx& c = *ctx;
+    const long long n2 = n2of(c, c.L());
+    // T* = T^n + (T^n - T^{n-1}) tau^{n+1} / tau^n and the viscosity at it
+    c.temp.tstar.alloc((size_t)n2);
+    const double q = tp->tau1 / tp->tau0;
+    vcopy<double>(T_n, c.temp.tstar.p, n2, c.s);
+    vaxpby<double>(-q, T_nm1, 1.0 + q, c.temp.tstar.p, n2, c.s);
+    set_temperature_viscosity_internal(c, c.temp.tstar.p, lnrho, eta_base, n_base, E_A, V_A, l_eta, sp);
+    temperature_step_internal(c, tp, T_n, T_nm1, u_n, u_nm1, lnrho, c.at(c.L()).eta.p, T_np1, nullptr, nullptr,
+                              trep);
+    // the Stokes fields at T^{n+1} and the buoyancy of T^{n+1}
+    set_temperature_viscosity_internal(c, T_np1, lnrho, eta_base, n_base, E_A, V_A, l_eta, sp);
+    LevelData& F = c.at(c.L());
+    c.temp.fbuf.alloc((size_t)3 * n2);
+    vfill<double>(c.temp.fbuf.p, 0.0, 3 * n2, c.s);
+    launch_rhs(F.d, T_np1, buoyancy_scale, c.temp.fbuf.p, c.s);
+    HIPCHK(hipGetLastError());
+  });
+  if (rc != STK_OK) return rc;
+  return solve_common(ctx, sp, ctx->temp.fbuf.p, nullptr, nullptr, u_np1, p_np1, srep, false);
 }
 
 int stk_kernel_timer(stk_ctx* ctx, int enable, double* ms_total, int* launches) {

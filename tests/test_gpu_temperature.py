@@ -233,3 +233,52 @@ def test_two_coupled_steps_match_oracle(shell):
         assert e_u < 1e-6 and e_T < 1e-7 and moved > 1e-4
         T_o.append(Tn1_o)
         T_g.append(Tn1_g)
+
+
+def test_coupled_step_entry_point_matches_oracle(shell):
+    """stk_coupled_step twice (the temperature step with the viscosity of the
+    model at the extrapolated temperature, then the Stokes solve with the
+    viscosity and buoyancy of the new temperature) against the same sequence
+    in the oracle: the model's eta(x_V, T(x_V)) at the vertices, the oracle's
+    temperature step and its direct Stokes solve."""
+    from oracle.fem import assemble_A, assemble_B, rhs_buoyancy, vertex_p2_nodes, viscosity_model
+    from oracle.system import solve_stokes
+    from paper_2506_04157_amd import default_params
+    d = shell
+    P, m = d["P"], d["m"]
+    lnrho = d["lnrho"]
+    base = inputs.base_viscosity_profile()
+    E_A, V_A, scale = 4.610, 2.996, 500.0
+    v2 = vertex_p2_nodes(m)
+    model = lambda T2: viscosity_model(m.X1, T2[v2], base, E_A, V_A, 0.55, 1.0)
+    B = assemble_B(m)
+    Bb = B + assemble_B(m, lnrho, only_C=True)
+    _, Q = P.projector()
+    sp_ = default_params(tol_rel=1e-11, precision=64, max_outer=400)
+    # start: T^{-1} = T^0 and the velocity of T^0
+    T0 = d["T2"]
+    u0, _, _ = solve_stokes(assemble_A(m, model(T0)), Bb, rhs_buoyancy(m, T0, scale=scale), np.zeros(m.n1), Q,
+                            Bt=B.T)
+    tau = 0.3 * 0.45 / 8 / np.abs(u0).max()
+    tp = temp_params(tau1=tau, tau0=tau, T_in=1.0, T_out=0.0, tol_abs=1e-14, **COEF)
+    To = [T0, T0]
+    uo = [u0, u0]
+    Tg = [P.s2_to_lib(T0), P.s2_to_lib(T0)]
+    ug = [P.u_to_lib(u0), P.u_to_lib(u0)]
+    for step in range(2):
+        Ts = 2.0 * To[-1] - To[-2]
+        Tn1, _, _, _ = temperature_step(m, To[-1], To[-2], uo[-1], uo[-2], lnrho, model(Ts), tau, tau, T_in=1.0,
+                                        T_out=0.0, **COEF)
+        un1, pn1, _ = solve_stokes(assemble_A(m, model(Tn1)), Bb, rhs_buoyancy(m, Tn1, scale=scale),
+                                   np.zeros(m.n1), Q, Bt=B.T)
+        T, u, p, trep, srep = P.ctx.coupled_step(Tg[-1], Tg[-2], ug[-1], ug[-2], base, tp, params=sp_, E_A=E_A,
+                                                 V_A=V_A, buoyancy_scale=scale, lnrho=P.p_to_lib(lnrho))
+        e_T = np.abs(P.s2_to_or(T) - Tn1).max() / np.abs(Tn1).max()
+        e_u = relerr(P.u_to_or(u), un1)
+        print(f"coupled step {step}: T {e_T:.2e}, u {e_u:.2e}, {trep['iterations']} temperature its, "
+              f"{srep['iterations']} Stokes its, rel {srep['rel_residual']:.1e}")
+        assert e_T < 1e-7 and e_u < 1e-6 and srep["rel_residual"] <= 1e-11
+        To.append(Tn1)
+        uo.append(un1)
+        Tg.append(T)
+        ug.append(u)
