@@ -408,6 +408,10 @@ def main():
     ap.add_argument("--temp-study", action="store_true",
                     help="only the temperature step (Sec. 3 splitting, eq. WeakTemp) on the shell and level "
                          "given: MMOC, right-hand side and FGMRES solve timings, kernel times")
+    ap.add_argument("--time-loop-study", action="store_true",
+                    help="only the coupled time loop: STEPS steps of temperature then Stokes (from the previous "
+                         "solution, absolute tolerance 1e-5) with the viscosity model, per-step times")
+    ap.add_argument("--loop-steps", type=int, default=5)
     ap.add_argument("--l-eta-study", action="store_true",
                     help="only the coarse-viscosity study: A-block CG iterations and time of 10 FGMRES "
                          "iterations with the viscosity model of eq. ViscosityDef for l_eta = -1, 0, 1")
@@ -417,7 +421,7 @@ def main():
               "path", file=sys.stderr)
         sys.exit(2)
     if (args.apply_only or args.transfer_only or args.l_eta_study or args.contrast_study or args.large_apply
-            or args.schur_study or args.temp_study):
+            or args.schur_study or args.temp_study or args.time_loop_study):
         return studies(args)
 
     n_tets = 60 * args.n_tan ** 2 * args.n_rad * 8 ** args.level
@@ -649,6 +653,8 @@ def studies(args):
             return schur_study(args, sc, dev, Nu, Np)
         if args.temp_study:
             return temp_study(args, sc, dev, Nu, Np)
+        if args.time_loop_study:
+            return time_loop_study(args, sc, dev, Nu, Np)
         X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
         X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
         field = inputs.SHField(2)
@@ -874,6 +880,76 @@ def temp_study(args, sc, dev, Nu, Np):
            "step_ms": last["ms_mmoc"] + last["ms_rhs"] + last["ms_solve"],
            "mmoc_share": last["ms_mmoc"] / (last["ms_mmoc"] + last["ms_rhs"] + last["ms_solve"])}
     print(json.dumps({"temp_study": out}), flush=True)
+
+
+def time_loop_study(args, sc, dev, Nu, Np):
+    """The coupled time loop of Sec. 3 and Sec. 6 at the given size: an initial
+    Stokes solve from zero, then --loop-steps coupled steps (temperature step
+    with the viscosity at the extrapolated temperature, then the Stokes solve
+    started from the previous solution to the absolute tolerance
+    tol_(u,p) = 1e-5 of table parametertable).  The viscosity model of eq.
+    ViscosityDef with the paper's E_A, V_A and the synthetic base profile; the
+    paper's Ra, Pe, Di; buoyancy scale Ra/Pe = 600; the initial temperature
+    linear in r between the Dirichlet values plus a seeded SH perturbation of
+    amplitude 0.1 that vanishes on both spheres; rho = exp(0.5 (1 - r)); a
+    step of a third of a micro-tet's radial height over max |u|.  Per-step
+    times of the MMOC, the temperature solve and the Stokes solve, and their
+    shares."""
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2506_04157_amd import default_params, temp_params
+    field = inputs.SHField(2)
+    X2 = torch.tensor(sc.coords(which=2)[0], device=dev)
+    T_in, T_out = 4200.0 / 3900.0, 300.0 / 3900.0
+    s_ = (torch.linalg.norm(X2, dim=1) - 0.55) / 0.45
+    T0 = (T_in + (T_out - T_in) * s_ + 0.1 * (field.temperature_torch(X2) - 0.5) * torch.sin(np.pi * s_))
+    T0 = T0.contiguous()
+    del X2, s_
+    X1 = torch.tensor(sc.coords(which=1)[0], device=dev)
+    lnrho = (0.5 * (1.0 - torch.linalg.norm(X1, dim=1))).contiguous()
+    del X1
+    base = inputs.base_viscosity_profile()
+    E_A, V_A, scale = 4.610, 2.996, 1.692e7 / 2.822e4
+    cold = default_params(precision=32, tol_rel=1e-30, tol_abs=1e-5, max_outer=200)
+    warm = default_params(precision=32, tol_rel=1e-30, tol_abs=1e-5, max_outer=200, initial_guess=1)
+    sc.set_temperature_viscosity(T0, base, E_A, V_A, lnrho=lnrho, params=cold)
+    u, p, rep0 = sc.solve(sc.rhs_buoyancy(T0, scale=scale), params=cold, allow_noconv=True)
+    torch.cuda.synchronize()
+    log(f"initial solve: {rep0['iterations']} its, abs {rep0['abs_residual']:.2e}, {rep0['seconds']:.1f} s")
+    umax = float(u.abs().max().item())
+    tau = (1.0 / 3.0) * (0.45 / args.n_rad / 2 ** args.level) / max(umax, 1e-30)
+    tp = temp_params(tau1=tau, tau0=tau, k=1.0, Pe=2.822e4, Cp=1.0, Di=0.4538, alpha=1.0, H=1.0, Ra=1.692e7,
+                     T_in=T_in, T_out=T_out, tol_abs=1e-10)
+    T_prev, T_cur, u_prev, u_cur, p_cur = T0, T0, u, u, p
+    steps = []
+    for it in range(args.loop_steps):
+        t0 = time.perf_counter()
+        T_new, u_new, p_new, trep, srep = sc.coupled_step(T_cur, T_prev, u_cur, u_prev, base, tp, params=warm,
+                                                          E_A=E_A, V_A=V_A, buoyancy_scale=scale, lnrho=lnrho,
+                                                          p_n=p_cur, allow_noconv=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = {"wall_s": wall, "temperature": {k: trep[k] for k in ("ms_mmoc", "ms_rhs", "ms_solve", "iterations",
+                                                                   "cg_its")},
+              "stokes": {k: srep[k] for k in ("iterations", "seconds", "initial_residual", "abs_residual",
+                                              "a_cg_its", "s_cg_its")}}
+        steps.append(st)
+        log(f"step {it}: {wall:.1f} s; temperature mmoc {trep['ms_mmoc']:.0f} ms, solve {trep['ms_solve']:.0f} ms "
+            f"({trep['iterations']} its); Stokes {srep['iterations']} its from {srep['initial_residual']:.2e} "
+            f"to {srep['abs_residual']:.2e}, {srep['seconds']:.1f} s")
+        T_prev, T_cur, u_prev, u_cur, p_cur = T_cur, T_new, u_cur, u_new, p_new
+    tot = sum(s_["wall_s"] for s_ in steps)
+    t_mmoc = sum(s_["temperature"]["ms_mmoc"] for s_ in steps) * 1e-3
+    t_temp = sum(s_["temperature"]["ms_rhs"] + s_["temperature"]["ms_solve"] for s_ in steps) * 1e-3
+    t_stokes = sum(s_["stokes"]["seconds"] for s_ in steps)
+    out = {"workload": f"shell {args.n_tan}x{args.n_rad} level {args.level}, N_u={Nu}, N_p={Np}, "
+                       f"temperature nodes {Nu // 3}",
+           "tau": tau, "initial_solve": {k: rep0[k] for k in ("iterations", "seconds", "abs_residual")},
+           "steps": steps, "total_step_s": tot,
+           "shares": {"stokes": t_stokes / tot, "mmoc": t_mmoc / tot, "temperature_solve": t_temp / tot}}
+    print(json.dumps({"time_loop_study": out}), flush=True)
 
 
 def schur_study(args, sc, dev, Nu, Np):

@@ -93,6 +93,9 @@ typedef struct {
   double a_l, a_r;     /* w-BFBT scalings of eta_l, eta_r near the Dirichlet boundary: 1, 1 */
   double tol_wbfbt;    /* CG on the Poisson operators K_{1/sqrt eta}: 1e-10 (relative or absolute) */
   double tol_vmass;    /* CG on the vector masses M_{sqrt eta}: 1e-4 */
+  int initial_guess;   /* 1: stk_solve / stk_solve_adjoint start FGMRES from the values u, p
+                          (lu, lp) hold on entry (projected first; in a time loop the previous
+                          step's solution, Sec. 6), 0: from zero.  The stop rule is unchanged */
 } stk_solver_params;
 
 enum { STK_UZAWA_SYMMETRIC = 0, STK_UZAWA_INEXACT = 1, STK_UZAWA_ADJOINT = 2 };
@@ -397,7 +400,11 @@ int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T
                          double* T_np1, double* That_n, double* That_nm1, stk_temp_report* rep);
 
 /* One step of the coupled scheme (Sec. 3: the temperature first, then the
- * Stokes problem of eq. StokesSub at the new temperature), on a shell:
+ * Stokes problem of eq. StokesSub at the new temperature), on a shell.  With
+ * sp->initial_guess = 1 the Stokes solve starts from u_n and p_n (p_n
+ * nullable: zero), the previous step's solution, as the paper's time loop
+ * does (an absolute tolerance that the updated problem may already meet,
+ * Sec. 6).  Steps:
  *  1. T* = T^n + (T^n - T^{n-1}) tau^{n+1}/tau^n (eq. Extrapolation) and the
  *     viscosity eta(x, T*) of the model of eq. ViscosityDef (arguments as in
  *     stk_set_temperature_viscosity), used in the shear heating;
@@ -406,14 +413,15 @@ int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T
  *     p^{n+1} from stk_solve (sp) with f = buoyancy_scale * int T^{n+1} r_hat
  *     . phi (stk_rhs_buoyancy), g = 0 and no Dirichlet data.
  * Device vectors: T_n, T_nm1, T_np1 (n_p2), u_n, u_nm1, u_np1 (3 n_p2),
- * p_np1 and lnrho (n_p1, lnrho nullable).  The context's fields are left at
+ * p_n, p_np1 and lnrho (n_p1; p_n and lnrho nullable).  The context's fields are left at
  * eta(x, T^{n+1}).  Returns the temperature solve's STK_ENOCONV without
  * solving the Stokes problem, else the Stokes solve's code; trep, srep
  * (nullable) receive both reports. */
 int stk_coupled_step(stk_ctx* ctx, const stk_solver_params* sp, const stk_temp_params* tp, const double* eta_base,
                      int n_base, double E_A, double V_A, int l_eta, double buoyancy_scale, const double* lnrho,
-                     const double* T_n, const double* T_nm1, const double* u_n, const double* u_nm1, double* T_np1,
-                     double* u_np1, double* p_np1, stk_temp_report* trep, stk_report* srep);
+                     const double* T_n, const double* T_nm1, const double* u_n, const double* u_nm1,
+                     const double* p_n, double* T_np1, double* u_np1, double* p_np1, stk_temp_report* trep,
+                     stk_report* srep);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ class SolverParams(ctypes.Structure):
                 ("max_inner", ctypes.c_int), ("use_Bbar", ctypes.c_int), ("power_its", ctypes.c_int),
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double), ("uzawa", ctypes.c_int),
                 ("schur", ctypes.c_int), ("a_l", ctypes.c_double), ("a_r", ctypes.c_double),
-                ("tol_wbfbt", ctypes.c_double), ("tol_vmass", ctypes.c_double)]
+                ("tol_wbfbt", ctypes.c_double), ("tol_vmass", ctypes.c_double), ("initial_guess", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -112,7 +112,7 @@ SIGNATURES = {
     "stk_temperature_step": [_CTX, ctypes.POINTER(TempParams), _P, _P, _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(TempReport)],
     "stk_coupled_step": [_CTX, ctypes.POINTER(SolverParams), ctypes.POINTER(TempParams), _P, _I, _D, _D, _I, _D,
-                         _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(TempReport), ctypes.POINTER(Report)],
+                         _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(TempReport), ctypes.POINTER(Report)],
 }
 
 _lib = None

@@ -298,11 +298,21 @@ class StokesContext:
         return x
 
     # -- solves ------------------------------------------------------------------------
-    def solve(self, f, g=None, u_dirichlet=None, params=None, allow_noconv=False):
+    def solve(self, f, g=None, u_dirichlet=None, params=None, allow_noconv=False, u0=None, p0=None):
+        """u0, p0 (optional): the initial guess of FGMRES (initial_guess = 1)."""
         params = params or self.params or default_params()
         pf, pg = self._u(f, name="f"), self._p(g, name="g")
         pd = self._u(u_dirichlet, name="u_dirichlet")
         u, p = self.zeros_u(), self.zeros_p()
+        if u0 is not None or p0 is not None:
+            if u0 is not None:
+                self._u(u0, name="u0")
+                u.copy_(u0)
+            if p0 is not None:
+                self._p(p0, name="p0")
+                p.copy_(p0)
+            params = SolverParams.from_buffer_copy(params)
+            params.initial_guess = 1
         rep = Report()
         rc = self.lib.stk_solve(self.h, ctypes.byref(params), pf, pg, pd, _ptr(u), _ptr(p), ctypes.byref(rep))
         if not (allow_noconv and rc == _lib.STK_ENOCONV):
@@ -401,7 +411,7 @@ class StokesContext:
         return (T, thn, thm, rep.as_dict()) if traced else (T, rep.as_dict())
 
     def coupled_step(self, T_n, T_nm1, u_n, u_nm1, eta_base, tparams, params=None, E_A=4.610, V_A=2.996,
-                     l_eta=-1, buoyancy_scale=1.0, lnrho=None, allow_noconv=False):
+                     l_eta=-1, buoyancy_scale=1.0, lnrho=None, p_n=None, allow_noconv=False):
         """One step of the coupled scheme (temperature, then Stokes at the new
         temperature): (T^{n+1}, u^{n+1}, p^{n+1}, temperature report, Stokes report)."""
         params = params or self.params or default_params()
@@ -413,7 +423,7 @@ class StokesContext:
             self.h, ctypes.byref(params), ctypes.byref(tparams), base.ctypes.data_as(ctypes.c_void_p), len(base),
             float(E_A), float(V_A), int(l_eta), float(buoyancy_scale), self._s1(lnrho, "lnrho"),
             self._s2(T_n, name="T_n"), self._s2(T_nm1, name="T_nm1"), self._u(u_n, name="u_n"),
-            self._u(u_nm1, name="u_nm1"), self._s2(T, name="T_np1"), self._u(u, name="u_np1"),
+            self._u(u_nm1, name="u_nm1"), self._p(p_n, name="p_n"), self._s2(T, name="T_np1"), self._u(u, name="u_np1"),
             self._p(p, name="p_np1"), ctypes.byref(trep), ctypes.byref(srep))
         if not (allow_noconv and rc == _lib.STK_ENOCONV):
             check(rc)

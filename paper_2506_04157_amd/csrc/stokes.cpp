@@ -960,7 +960,8 @@ struct FgmresOut {
   bool converged = false;
 };
 
-FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double* xp, bool transpose) {
+// warm: xu, xp enter as the initial guess (projected here); else they start at zero
+FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double* xp, bool transpose, bool warm) {
   const int l = c.L();
   LevelData& L = c.at(l);
   const long long N = 3 * L.h.n2, n1 = L.h.n1, Nt = N + n1;
@@ -979,22 +980,42 @@ FgmresOut fgmres(Ctx& c, const double* bu, const double* bp, double* xu, double*
   };
   auto precond = [&](const double* v, double* z) { precondition(c, v, z, transpose); };
   FgmresOut out;
-  vfill<double>(xu, 0.0, N, c.s);
-  vfill<double>(xp, 0.0, n1, c.s);
+  if (warm) {
+    project<double>(c, l, xu);
+    project_mean<double>(c, xp);
+  } else {
+    vfill<double>(xu, 0.0, N, c.s);
+    vfill<double>(xp, 0.0, n1, c.s);
+  }
   vcopy<double>(bu, b, N, c.s);
   vcopy<double>(bp, b + N, n1, c.s);
   project<double>(c, l, b);
   project_mean<double>(c, b + N);
   const double nb = nrm2<double>(c, b, Nt);
-  out.r0 = nb;
-  if (c.rep) c.rep->initial_residual = nb;
-  if (nb == 0.0) {
+  double beta = nb;
+  if (warm) {
+    // r0 = b - K x0 (the initial guess, both parts contiguous in Z(0))
+    double* tmp = Z(0);
+    vcopy<double>(xu, tmp, N, c.s);
+    vcopy<double>(xp, tmp + N, n1, c.s);
+    Kapply(tmp, V(0));
+    vaxpby<double>(1.0, b, -1.0, V(0), Nt, c.s);
+    beta = nrm2<double>(c, V(0), Nt);
+  } else {
+    vcopy<double>(b, V(0), Nt, c.s);
+  }
+  out.r0 = beta;
+  out.rfin = beta;
+  if (c.rep) c.rep->initial_residual = beta;
+  const double target = std::max(c.par.tol_rel * nb, c.par.tol_abs);
+  if (nb == 0.0 || beta <= target) {
     out.converged = true;
+    if (nb == 0.0) {
+      vfill<double>(xu, 0.0, N, c.s);
+      vfill<double>(xp, 0.0, n1, c.s);
+    }
     return out;
   }
-  const double target = std::max(c.par.tol_rel * nb, c.par.tol_abs);
-  double beta = nb;
-  vcopy<double>(b, V(0), Nt, c.s);
   int total = 0;
   while (total < c.par.max_outer) {
     vscale<double>(1.0 / beta, V(0), Nt, c.s);
@@ -1657,6 +1678,7 @@ void check_params(const stk_solver_params* p) {
   if (p->schur == STK_SCHUR_WBFBT)
     REQUIRE(p->a_l > 0 && p->a_r > 0 && p->tol_wbfbt > 0 && p->tol_vmass > 0,
             "w-BFBT needs a_l, a_r, tol_wbfbt, tol_vmass > 0");
+  REQUIRE(p->initial_guess == 0 || p->initial_guess == 1, "initial_guess must be 0 or 1");
 }
 
 // Gauss-Jacobi rule with k points for the weight (1 - x)^alpha on [-1, 1]
@@ -1975,6 +1997,7 @@ void stk_default_params(stk_solver_params* p) {
   p->a_r = 1.0;
   p->tol_wbfbt = 1e-10;
   p->tol_vmass = 1e-4;
+  p->initial_guess = 0;
 }
 
 int stk_create(const stk_mesh_desc* desc, void* hip_stream, stk_ctx** out) {
@@ -2407,7 +2430,7 @@ static int solve_common(stk_ctx* ctx, const stk_solver_params* params, const dou
       applyB<double>(c, l, ud, tp, c.has_rho && !transpose, 0);
       vaxpy<double>(-1.0, tp, bp, n1, c.s);
     }
-    FgmresOut fo = fgmres(c, bu, bp, u, p, transpose);
+    FgmresOut fo = fgmres(c, bu, bp, u, p, transpose, params->initial_guess == 1);
     if (have_ud) vaxpy<double>(1.0, ud, u, N, c.s);
     HIPCHK(hipStreamSynchronize(c.s));
     HIPCHK(hipGetLastError());
@@ -2605,8 +2628,9 @@ int stk_temperature_step(stk_ctx* ctx, const stk_temp_params* p, const double* T
 
 int stk_coupled_step(stk_ctx* ctx, const stk_solver_params* sp, const stk_temp_params* tp, const double* eta_base,
                      int n_base, double E_A, double V_A, int l_eta, double buoyancy_scale, const double* lnrho,
-                     const double* T_n, const double* T_nm1, const double* u_n, const double* u_nm1, double* T_np1,
-                     double* u_np1, double* p_np1, stk_temp_report* trep, stk_report* srep) {
+                     const double* T_n, const double* T_nm1, const double* u_n, const double* u_nm1,
+                     const double* p_n, double* T_np1, double* u_np1, double* p_np1, stk_temp_report* trep,
+                     stk_report* srep) {
   const int rc = guard([&] {
     REQUIRE(ctx && ctx->lv.size() > 0, "null context");
     REQUIRE(sp && eta_base && u_np1 && p_np1, "null argument");
@@ -2629,6 +2653,13 @@ int stk_coupled_step(stk_ctx* ctx, const stk_solver_params* sp, const stk_temp_p
     c.temp.fbuf.alloc((size_t)3 * n2);
     vfill<double>(c.temp.fbuf.p, 0.0, 3 * n2, c.s);
     launch_rhs(F.d, T_np1, buoyancy_scale, c.temp.fbuf.p, c.s);
+    if (sp->initial_guess == 1) {
+      // the Stokes solve starts from the step's previous solution
+      REQUIRE(u_np1 != u_n && (!p_n || p_np1 != p_n), "outputs must not alias u_n, p_n");
+      vcopy<double>(u_n, u_np1, 3 * n2, c.s);
+      if (p_n) vcopy<double>(p_n, p_np1, n1of(c, c.L()), c.s);
+      else vfill<double>(p_np1, 0.0, n1of(c, c.L()), c.s);
+    }
     HIPCHK(hipGetLastError());
   });
   if (rc != STK_OK) return rc;

@@ -521,3 +521,33 @@ def test_solve_shell_free_slip_on_both_spheres(precision):
     bnd = m.flag2 > 0
     nrm = m.X2[bnd] / np.linalg.norm(m.X2[bnd], axis=1)[:, None]
     assert np.abs(np.einsum("ij,ij->i", U[bnd], nrm)).max() <= 1e-12 * np.abs(U).max()
+
+
+def test_solve_from_an_initial_guess():
+    """initial_guess = 1: FGMRES starts from the given (u, p).  From the
+    converged solution the solve stops at once (0 iterations, same
+    solution); from the solution of a slightly different right-hand side it
+    converges in fewer iterations than from zero, to the same solution."""
+    print("\n[solve from an initial guess]", flush=True)
+    P = Pair("shell", 2, min_level=0, n_tan=1, n_rad=1)
+    m = P.meshes[2]
+    field = inputs.SHField(2)
+    eta = inputs.viscosity_contrast(field.temperature(m.X1), 1e4)
+    lnrho = inputs.ln_density(m.X1)
+    T = field.temperature(m.X2)
+    params = default_params(tol_rel=1e-10, precision=32)
+    P.ctx.set_fields(P.p_to_lib(eta), P.p_to_lib(lnrho), params=params)
+    f = P.ctx.rhs_buoyancy(P.s2_to_lib(T))
+    u, p, rep = P.ctx.solve(f, params=params)
+    u2, p2, rep2 = P.ctx.solve(f, params=params, u0=u, p0=p)
+    print("from the solution:", rep2["iterations"], rep2["initial_residual"], rep2["abs_residual"])
+    assert rep2["iterations"] == 0
+    assert relerr(P.u_to_or(u2), P.u_to_or(u)) < 1e-14 and relerr(P.p_to_or(p2), P.p_to_or(p)) < 1e-14
+    f2 = P.ctx.rhs_buoyancy(P.s2_to_lib(T + 0.01 * inputs.uniform(5, m.n2)))
+    uc, pc, rc = P.ctx.solve(f2, params=params)
+    uw, pw, rw = P.ctx.solve(f2, params=params, u0=u, p0=p)
+    print("cold", rc["iterations"], "warm", rw["iterations"], relerr(P.u_to_or(uw), P.u_to_or(uc)))
+    assert rw["iterations"] < rc["iterations"]
+    # both stop at 1e-10 |b|: they agree within condition x residual, the bar
+    # of the other solve tests' comparisons
+    assert relerr(P.u_to_or(uw), P.u_to_or(uc)) < 1e-6 and relerr(P.p_to_or(pw), P.p_to_or(pc)) < 1e-6
