@@ -71,6 +71,16 @@ template <typename R> __device__ __forceinline__ const R* tinv_of(const LevelDev
 template <> __device__ __forceinline__ const double* tinv_of<double>(const LevelDev& L) { return L.tinv; }
 template <> __device__ __forceinline__ const float* tinv_of<float>(const LevelDev& L) { return L.tinvf; }
 
+// Workgroups are dispatched to the chip's 8 XCDs round-robin by workgroup id,
+// and each XCD has its own L2.  Numbering the work items so that XCD x takes a
+// contiguous range of them (bijectively, for any grid size) puts neighbouring
+// macros, which read the same shared nodes, behind the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_item(int bid, int nwg) {
+  const int x = bid % NXCD, loc = bid / NXCD, q = nwg / NXCD, r = nwg % NXCD;
+  return x * q + (x < r ? x : r) + loc;
+}
+
 // 32-bit lattice arithmetic (side m <= 256: all products fit)
 __device__ __forceinline__ int tetc(int s) { return s < 0 ? 0 : (s + 1) * (s + 2) * (s + 3) / 6; }
 __device__ __forceinline__ int lloc(int I, int J, int K, int m) {
@@ -525,8 +535,9 @@ __global__ __launch_bounds__(256) void k_sweep(LevelDev L, const R* __restrict__
   int* sg1 = reinterpret_cast<int*>(smem_raw + lay.sg1);
   R* sti = reinterpret_cast<R*>(smem_raw + lay.sti);
 
-  const int strip = blockIdx.x % S.nstrips;
-  const int mac = blockIdx.x / S.nstrips;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int strip = wid % S.nstrips;
+  const int mac = wid / S.nstrips;
   const int j0 = S.strip[2 * strip];
   const int n = L.n, m2 = 2 * n;
   const int* poff2 = S.poff2 + strip * (m2 + 2);
@@ -969,7 +980,7 @@ __global__ __launch_bounds__(256) void k_mass_stencil(LevelDev L, const R* __res
                                                       R* __restrict__ y, R* __restrict__ sl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sp = reinterpret_cast<R*>(smem_raw);
-  const int nloc = L.nloc1, mac = blockIdx.x;
+  const int nloc = L.nloc1, mac = xcd_item(blockIdx.x, gridDim.x);
   const size_t ld = (size_t)nloc + 1;
   const uint32_t* l1 = L.l2g1 + (size_t)mac * nloc;
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) sp[t] = p[l1[t]];
@@ -1512,14 +1523,15 @@ __global__ __launch_bounds__(256) void k_temp(LevelDev L, VmassRule qr, TempCoef
 template <bool BLEND>
 __global__ __launch_bounds__(384) void k_temp_smat(LevelDev L, VmassRule qr, double s1, double tk,
                                                    const double* __restrict__ lnrho, double* __restrict__ S) {
-  const int tile = blockIdx.x % L.ntiles;
-  const int mac = blockIdx.x / L.ntiles;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int tile = wid % L.ntiles;
+  const int mac = wid / L.ntiles;
   const int type = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int px = L.tiles[3 * tile] + (lane & 3), py = L.tiles[3 * tile + 1] + ((lane >> 2) & 3),
             pz = L.tiles[3 * tile + 2] + (lane >> 4);
   if (px + py + pz > type_limit(type, L.n)) return;
   const size_t nslots = (size_t)L.nmacro * L.ntiles * 384;
-  const size_t slot = (size_t)blockIdx.x * 384 + threadIdx.x;
+  const size_t slot = (size_t)wid * 384 + threadIdx.x;
   TempElem e;
   temp_elem(L, mac, type | (px << 3) | (py << 13) | (pz << 23), e);
   double lr[4];
@@ -1553,8 +1565,9 @@ __global__ __launch_bounds__(384) void k_temp_smat(LevelDev L, VmassRule qr, dou
 __global__ __launch_bounds__(384) void k_temp_sapply(LevelDev L, const double* __restrict__ S,
                                                      const double* __restrict__ x, double* __restrict__ y) {
   __shared__ double sx[NB2], sy[NB2];
-  const int tile = blockIdx.x % L.ntiles;
-  const int mac = blockIdx.x / L.ntiles;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int tile = wid % L.ntiles;
+  const int mac = wid / L.ntiles;
   const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
   const int n = L.n, m2 = 2 * n;
   const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
@@ -1568,7 +1581,7 @@ __global__ __launch_bounds__(384) void k_temp_sapply(LevelDev L, const double* _
   const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
   if (ox + cx + oy + cy + oz + cz <= type_limit(type, n)) {
     const size_t nslots = (size_t)L.nmacro * L.ntiles * 384;
-    const size_t slot = (size_t)blockIdx.x * 384 + threadIdx.x;
+    const size_t slot = (size_t)wid * 384 + threadIdx.x;
     ElemIdx e;
     elem_indices(type, cx, cy, cz, e);
     double xs[10], acc[10];
@@ -1849,8 +1862,9 @@ template <typename R, bool BLEND>
 __global__ __launch_bounds__(384) void k_diag(LevelDev L, const R* __restrict__ eta, R* __restrict__ dout) {
   __shared__ R sy[3 * NB2];
   __shared__ R seta[NB1];
-  const int tile = blockIdx.x % L.ntiles;
-  const int mac = blockIdx.x / L.ntiles;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int tile = wid % L.ntiles;
+  const int mac = wid / L.ntiles;
   const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
   const int n = L.n, m2 = 2 * L.n;
   const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
@@ -1951,8 +1965,9 @@ template <typename R, bool BLEND, bool DIAG>
 __global__ __launch_bounds__(384) void k_mass(LevelDev L, const R* __restrict__ eta, const R* __restrict__ p,
                                               R* __restrict__ y) {
   __shared__ R seta[NB1], sp[NB1], sy[NB1];
-  const int tile = blockIdx.x % L.ntiles;
-  const int mac = blockIdx.x / L.ntiles;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int tile = wid % L.ntiles;
+  const int mac = wid / L.ntiles;
   const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
   const int n = L.n;
   const uint32_t* l1 = L.l2g1 + (size_t)mac * L.nloc1;
@@ -2041,8 +2056,9 @@ __global__ __launch_bounds__(384) void k_rhs_grad(LevelDev L, const double* __re
   __shared__ double sx[NIN * NB2];
   __shared__ double sy[NOUT * NB2];
   __shared__ double seta[MODE == 1 ? NB1 : 1], sg[MODE == 1 ? NB1 : 1];
-  const int tile = blockIdx.x % L.ntiles;
-  const int mac = blockIdx.x / L.ntiles;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int tile = wid % L.ntiles;
+  const int mac = wid / L.ntiles;
   const int ox = L.tiles[3 * tile], oy = L.tiles[3 * tile + 1], oz = L.tiles[3 * tile + 2];
   const int n = L.n, m2 = 2 * L.n;
   const uint32_t* l2 = L.l2g2 + (size_t)mac * L.nloc2;
@@ -2240,8 +2256,9 @@ __global__ __launch_bounds__(256) void k_transfer(LevelDev Lc, LevelDev Lf, cons
   constexpr bool PRO = MODE == 0 || MODE == 2;
   constexpr int NB = 4;   // fine points per thread and batch (all loads of a batch in flight together)
   __shared__ double sc[3 * NB2];   // FP64 staging / accumulation (fast LDS atomics)
-  const int tile = blockIdx.x % Lc.ntiles;
-  const int mac = blockIdx.x / Lc.ntiles;
+  const int wid = xcd_item(blockIdx.x, gridDim.x);
+  const int tile = wid % Lc.ntiles;
+  const int mac = wid / Lc.ntiles;
   const int ox = Lc.tiles[3 * tile], oy = Lc.tiles[3 * tile + 1], oz = Lc.tiles[3 * tile + 2];
   const int nc = Lc.n, mc2 = 2 * nc, mf2 = 4 * nc;
   const uint32_t* l2c = Lc.l2g2 + (size_t)mac * Lc.nloc2;
