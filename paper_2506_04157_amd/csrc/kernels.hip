@@ -1562,7 +1562,10 @@ __global__ __launch_bounds__(384) void k_temp_smat(LevelDev L, VmassRule qr, dou
 // product into an LDS box of the brick's nodes, and the box is written out
 // (plain stores for nodes inside both the brick and the macro, atomic adds
 // for the others).
-__global__ __launch_bounds__(384) void k_temp_sapply(LevelDev L, const double* __restrict__ S,
+// Four workgroups per CU asked of the compiler (at most 80 VGPRs, six waves
+// per SIMD): the kernel waits on memory latency, so resident waves pay more
+// than the extra loads in flight per wave that more registers would allow.
+__global__ __launch_bounds__(384, 4) void k_temp_sapply(LevelDev L, const double* __restrict__ S,
                                                      const double* __restrict__ x, double* __restrict__ y) {
   __shared__ double sx[NB2], sy[NB2];
   const int wid = xcd_item(blockIdx.x, gridDim.x);
