@@ -886,10 +886,24 @@ __global__ void k_gather(GatherDev gd, const R* __restrict__ sl, size_t sstride,
   R v[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) v[c] = 0;
-  for (int k = b; k < e; ++k) {
-    const size_t s = (size_t)gd.slot[k];
+  // batches of GB slots: their indices, then their values, are loaded together;
+  // the values are still added in slot order
+  constexpr int GB = 4;
+  for (int k0 = b; k0 < e; k0 += GB) {
+    size_t s[GB];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) v[c] += sl[s + c * sstride];
+    for (int j = 0; j < GB; ++j) s[j] = k0 + j < e ? (size_t)gd.slot[k0 + j] : 0;
+    R w[GB][NC];
+#pragma unroll
+    for (int j = 0; j < GB; ++j)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) w[j][c] = k0 + j < e ? sl[s[j] + c * sstride] : R(0);
+#pragma unroll
+    for (int j = 0; j < GB; ++j)
+      if (k0 + j < e) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] += w[j][c];
+      }
   }
   const size_t g = gd.node[i];
 #pragma unroll
